@@ -1,0 +1,112 @@
+// Structures shared between the host scheduler and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dh2 {
+
+// Source of matrix entries.
+enum EntrySource : int32_t { SRC_HELMHOLTZ = 0, SRC_DENSE = 1 };
+
+// Geometry and matrix access, all in the permuted (cluster-tree) order.
+struct GeomDev {
+  const double* pts;      // n x 4: x, y, z, w
+  const float* pts32;     // n x 4 (mixed precision), may be null
+  const double* G;        // dense complex128, ORIGINAL order, row-major (interleaved)
+  const int64_t* perm;    // position -> original index
+  int64_t ldg;            // leading dimension of G in complex elements
+  int64_t n;
+  double kappa;
+};
+
+// One (cluster, direction) block row of a basis.
+struct ItemDev {
+  int64_t row_off;   // first permuted position of the cluster
+  int64_t N;         // number of columns of F_tc
+  int64_t ent_begin; // leaf: first column-set entry
+  int64_t ent_end;
+  int64_t col_off;   // non-leaf: offset of F_tc inside the sons' sets
+  double2* R;        // R^T (N x k, complex), in the arena of its level
+  double2* M;        // Gram (r x r, column-major)
+  double2* Q;        // factor: r x k row-major (leaf: Q_tc, other: [E_t1c; E_t2c])
+  double* sig;       // singular values (r)
+  int32_t m;         // rows of the cluster
+  int32_t r;         // rows of the factor (m or k1+k2)
+  int32_t k;         // rank (filled by the factorisation)
+  int32_t leaf;
+  int32_t son[2];    // non-leaf: item ids of (t1,c'), (t2,c')
+  int32_t level;
+  int32_t pad;
+};
+
+// Column-set entry for generated block rows.
+struct EntDev {
+  int64_t col_start;  // first column of this entry inside F_tc
+  int64_t pos;        // first permuted position of the column cluster
+  int64_t len;        // number of columns
+  int32_t b;          // admissible block
+  int32_t d;          // level difference
+  double scale;       // 1 / (omega_b zeta^d)
+};
+
+// A contiguous column range of one block row, processed by one workgroup.
+struct UnitDev {
+  int32_t item;
+  int32_t pad;
+  int64_t col_begin;
+  int64_t ncols;
+  int64_t slot_off;   // partial-Gram slot offset in complex elements (Gram units)
+};
+
+// Projection task: S_b = omega_b * (R_tc restricted to the columns of s) * Wexp_sc.
+struct ProjDev {
+  const double2* R;   // R^T rows of the block (|s| x kt)
+  const double2* W;   // expanded column basis (|s| x ks row-major)
+  double2* S;         // output (kt x ks column-major)
+  int32_t kt, ks;
+  int32_t ns;         // |s|
+  int32_t b;
+};
+
+// Expansion task: rows of one son inside Wexp_sc = Wexp_{s_i c'} E_{s_i c}.
+struct ExpandDev {
+  const double2* src; // Wexp of the son (rows x ks) row-major
+  const double2* E;   // E rows inside the father's factor (ks x k row-major)
+  double2* dst;       // destination rows inside the father's Wexp
+  int32_t rows;       // |s_i|
+  int32_t ks;         // son rank
+  int32_t k;          // father rank
+  int32_t pad;
+};
+
+// Leaf cluster of the matrix-vector product: its rows, its items in the basis
+// being applied, and its references into the near field.
+struct LeafDev {
+  int64_t row_off;
+  int32_t len;
+  int32_t item_first;
+  int32_t item_count;
+  int32_t pad;
+  int64_t near_begin;
+  int64_t near_end;
+};
+
+// Inadmissible block: its dense entries (|t| x |s| column-major) at off.
+struct NearDev {
+  int64_t off;
+  int64_t t_off, t_len;
+  int64_t s_off, s_len;
+};
+
+// A leaf's reference to a near-field block that contains its rows.
+struct NearRefDev {
+  int64_t b;
+  int64_t row0;   // first row (op N) or column (op C) of the leaf inside the block
+};
+
+constexpr int kMaxR = 128;      // largest factor size handled by the kernels
+constexpr int kStageCols = 32;  // columns per LDS stage
+
+}  // namespace dh2

@@ -1,0 +1,1085 @@
+// Host engine of the directional H2 compression (see engine.hpp).
+//
+// Compression (Section 6 of the paper): for each basis, the (cluster,
+// direction) block rows are processed level by level from the leaves up.
+// Per level: Gram matrices of the weighted block rows (leaf clusters:
+// entries generated from the points; other clusters: zeta [R_t1c'; R_t2c']
+// read from the sons' coefficient matrices), factorisation into singular
+// values and left singular vectors, rank read-back, then R_tc = Q^* A.  The
+// column basis (rows of G^*) is built first and expanded level by level; the
+// row sweep then projects every admissible block right after its R_tc is
+// formed: S_b = omega_b R_tc|s W_sc = V^* G|_b W.  Subtrees rooted above the
+// first level with admissible blocks are independent and are swept in
+// batches to bound the memory of the R matrices (the paper parallelises
+// over independent subtrees in the same way).
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <random>
+#include <unordered_map>
+
+#include "kernels.hpp"
+
+namespace dh2 {
+
+void fail(dh2_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? DH2_ENOMEM : DH2_EDEVICE,
+         std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+static void launch_check(const char* what) { hip_check(hipGetLastError(), what); }
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+DevMem::~DevMem() {
+  for (auto& pr : live_) (void)hipFree(pr.first);
+}
+
+void* DevMem::alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (cap_ > 0 && used_ + (int64_t)bytes > cap_)
+    fail(DH2_ENOMEM, "device memory cap exceeded (" + std::to_string(used_ + bytes) + " > " +
+                         std::to_string(cap_) + " bytes)");
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(DH2_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  live_.push_back({p, bytes});
+  used_ += (int64_t)bytes;
+  peak_ = std::max(peak_, used_);
+  return p;
+}
+
+void DevMem::release(void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < live_.size(); ++i) {
+    if (live_[i].first == p) {
+      (void)hipFree(p);
+      used_ -= (int64_t)live_[i].second;
+      live_[i] = live_.back();
+      live_.pop_back();
+      return;
+    }
+  }
+}
+
+template <class T>
+static T* upload(DevMem& mem, const std::vector<T>& v, hipStream_t st) {
+  T* d = (T*)mem.alloc(v.size() * sizeof(T));
+  if (!v.empty()) {
+    hip_check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st),
+              "upload");
+    hip_check(hipStreamSynchronize(st), "upload sync");
+  }
+  return d;
+}
+
+template <class T>
+static void copy_to(T* d, const T* h, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  hip_check(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, st), "copy_to");
+  hip_check(hipStreamSynchronize(st), "copy_to sync");
+}
+
+template <class T>
+static void copy_from(T* h, const T* d, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  hip_check(hipMemcpyAsync(h, d, n * sizeof(T), hipMemcpyDeviceToHost, st), "copy_from");
+  hip_check(hipStreamSynchronize(st), "copy_from sync");
+}
+
+// ---------------------------------------------------------------------------
+// plan handles
+// ---------------------------------------------------------------------------
+std::shared_ptr<TreeData> make_tree(const double* pts, int64_t n, double kappa, const dh2_opts& o) {
+  auto t = std::make_shared<TreeData>();
+  t->pts.assign(pts, pts + 3 * n);
+  t->kappa = kappa;
+  t->opts = o;
+  t->tr = build_cluster_tree(pts, n, o.leaf_size);
+  t->dr = build_directions(t->tr, kappa, o.eta1, o.lowfreq_zero_dir != 0);
+  return t;
+}
+
+std::shared_ptr<BlocksData> make_blocks(std::shared_ptr<TreeData> t, const dh2_opts& o) {
+  auto b = std::make_shared<BlocksData>();
+  b->tree = t;
+  b->opts = o;
+  b->bt = build_block_tree(t->tr, t->dr, t->kappa, o.eta2, o.standard_only != 0);
+  b->cs[0] = build_column_sets(t->tr, t->dr, b->bt, 0);
+  b->cs[1] = build_column_sets(t->tr, t->dr, b->bt, 1);
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// matvec plan (built on first use)
+// ---------------------------------------------------------------------------
+struct SideMV {
+  int64_t* d_hoff = nullptr;       // coefficient offsets per item
+  int64_t total = 0;
+  // coupling: for op N on side 0 / op C on side 1 (this side receives)
+  int64_t* d_cbegin = nullptr;
+  int32_t* d_cblock = nullptr;
+  int32_t* d_cpartner = nullptr;
+  // backward: per level, items with fathers
+  std::vector<int32_t*> d_bl_items;
+  std::vector<int32_t> bl_count;
+  std::vector<int64_t*> d_bl_fbegin;
+  std::vector<int32_t*> d_bl_fitem;
+  std::vector<int32_t*> d_bl_fson;
+  // forward: leaf items, then non-leaf items per level (deepest first)
+  int32_t* d_fwd_leaf = nullptr;
+  int32_t n_fwd_leaf = 0;
+  std::vector<int32_t*> d_fwd_lvl;
+  std::vector<int32_t> fwd_count;
+  // leaves
+  LeafDev* d_leaves = nullptr;
+  NearRefDev* d_nref = nullptr;
+  int32_t nleaves = 0;
+};
+
+struct MatvecPlan {
+  SideMV s[2];
+  NearDev* d_nears = nullptr;
+  double2* const* d_Sptr = nullptr;
+  int32_t* d_Srows = nullptr;
+  int32_t* d_Scols = nullptr;
+  double2* xp = nullptr;
+  double2* yp = nullptr;
+  double2* xh = nullptr;  // sized for the larger side
+  double2* yh = nullptr;
+};
+
+MatrixData::~MatrixData() {
+  mv.reset();
+  mem.reset();
+}
+
+// ---------------------------------------------------------------------------
+// side construction
+// ---------------------------------------------------------------------------
+static int32_t first_adm_level(const BlocksData& B) {
+  int32_t l = 1 << 30;
+  for (int32_t t : B.bt.adm_t) l = std::min(l, B.tree->tr.level[t]);
+  return l;
+}
+
+static void build_side(MatrixData& M, int s, const std::vector<int32_t>& batch_of_cluster) {
+  const BlocksData& B = *M.blk;
+  const ClusterTree& tr = B.tree->tr;
+  const Directions& dr = B.tree->dr;
+  const ColumnSets& cs = B.cs[s];
+  Side& S = M.side[s];
+  int32_t ni = cs.nitems();
+  S.nitems = ni;
+  // internal order: (batch, level descending, external index)
+  std::vector<int32_t> order(ni);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    int32_t ta = cs.item_t[a], tb = cs.item_t[b];
+    int32_t ba = batch_of_cluster[ta], bb = batch_of_cluster[tb];
+    if (ba != bb) return ba < bb;
+    if (tr.level[ta] != tr.level[tb]) return tr.level[ta] > tr.level[tb];
+    return a < b;
+  });
+  S.int2ext = order;
+  S.ext2int.assign(ni, -1);
+  for (int32_t i = 0; i < ni; ++i) S.ext2int[order[i]] = i;
+  S.items.assign(ni, ItemDev{});
+  S.t.resize(ni);
+  S.c.resize(ni);
+  S.ent_col.assign(cs.ent.size(), 0);
+  // per external item: N and entry column starts
+  std::vector<int64_t> Next(ni, 0);
+  for (int32_t e = 0; e < ni; ++e) {
+    int64_t col = 0;
+    for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) {
+      S.ent_col[q] = col;
+      col += tr.size[cs.ent[q].s];
+    }
+    Next[e] = col;
+  }
+  // column offsets of F_tc inside the sons' sets
+  std::vector<int64_t> coloff(ni, 0);
+  for (int32_t t = 0; t < tr.nc(); ++t) {
+    if (tr.leaf(t) || cs.count[t] == 0) continue;
+    std::map<int32_t, int64_t> run;
+    const auto& sdl = dr.sd[tr.level[t]];
+    for (int32_t e = cs.first[t]; e < cs.first[t] + cs.count[t]; ++e) {
+      int32_t cp = sdl[cs.item_c[e]];
+      coloff[e] = run[cp];
+      run[cp] += Next[e];
+    }
+  }
+  S.ents.clear();
+  std::vector<int32_t> son_ext(2 * (size_t)ni, -1);
+  int32_t nb = M.nbatch;
+  S.range.assign(nb, std::vector<std::pair<int32_t, int32_t>>(tr.depth + 1, {0, 0}));
+  for (int32_t i = 0; i < ni; ++i) {
+    int32_t e = order[i];
+    int32_t t = cs.item_t[e], c = cs.item_c[e];
+    ItemDev& it = S.items[i];
+    S.t[i] = t;
+    S.c[i] = c;
+    it.row_off = tr.off[t];
+    it.N = Next[e];
+    it.m = (int32_t)tr.size[t];
+    it.leaf = tr.leaf(t) ? 1 : 0;
+    it.level = tr.level[t];
+    it.k = 0;
+    it.son[0] = it.son[1] = -1;
+    it.col_off = coloff[e];
+    if (it.leaf) {
+      it.r = it.m;
+      it.ent_begin = (int64_t)S.ents.size();
+      for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) {
+        const ColEntry& ce = cs.ent[q];
+        EntDev ed{};
+        ed.col_start = S.ent_col[q];
+        ed.pos = tr.off[ce.s];
+        ed.len = tr.size[ce.s];
+        ed.b = ce.b;
+        ed.d = ce.d;
+        ed.scale = 0.0;
+        S.ents.push_back(ed);
+      }
+      it.ent_end = (int64_t)S.ents.size();
+    } else {
+      int32_t cp = dr.sd[tr.level[t]][c];
+      for (int q = 0; q < 2; ++q) {
+        int32_t son = q == 0 ? tr.son1[t] : tr.son2[t];
+        int32_t se = cs.find(son, cp);
+        if (se < 0) fail(DH2_EDEVICE, "internal: son item missing");
+        son_ext[2 * (size_t)i + q] = se;
+      }
+      it.r = 0;
+    }
+    int32_t b = batch_of_cluster[t];
+    auto& rg = S.range[b][it.level];
+    if (rg.first == rg.second) rg = {i, i + 1};
+    else rg.second = i + 1;
+  }
+  for (int32_t i = 0; i < ni; ++i)
+    if (!S.items[i].leaf)
+      for (int q = 0; q < 2; ++q) {
+        int32_t so = S.ext2int[son_ext[2 * (size_t)i + q]];
+        S.items[i].son[q] = so;
+        // the kernels read columns col_off .. col_off+N of the son's R
+        if (S.items[i].col_off + S.items[i].N > S.items[so].N ||
+            S.items[so].level != S.items[i].level + 1)
+          fail(DH2_EDEVICE, "internal: inconsistent column sets");
+      }
+  S.wexp.assign(ni, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// compression
+// ---------------------------------------------------------------------------
+struct PhaseTimer {
+  hipEvent_t a, b;
+  hipStream_t st;
+  double acc = 0;
+  explicit PhaseTimer(hipStream_t s) : st(s) {
+    hip_check(hipEventCreate(&a), "event");
+    hip_check(hipEventCreate(&b), "event");
+  }
+  ~PhaseTimer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  void start() { hip_check(hipEventRecord(a, st), "event record"); }
+  void stop() {
+    hip_check(hipEventRecord(b, st), "event record");
+    hip_check(hipEventSynchronize(b), "event sync");
+    float ms = 0;
+    hip_check(hipEventElapsedTime(&ms, a, b), "event time");
+    acc += ms * 1e-3;
+  }
+};
+
+struct SweepStats {
+  double flops_gram = 0, flops_rprod = 0, flops_prj = 0;
+  double t_gram = 0, t_prj = 0;
+};
+
+static int64_t npairs_of(int r) {
+  int nt = (r + 15) / 16;
+  return (int64_t)nt * (nt + 1) / 2;
+}
+
+static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepStats& ss,
+                  int32_t* d_status) {
+  const BlocksData& B = *M.blk;
+  const ClusterTree& tr = B.tree->tr;
+  const ColumnSets& cs = B.cs[s];
+  Side& S = M.side[s];
+  DevMem& mem = *M.mem;
+  PhaseTimer tg(st), tp(st);
+  double2* partial = nullptr;
+  size_t partial_cap = 0;
+
+  for (int32_t b = 0; b < M.nbatch; ++b) {
+    void* R_prev = nullptr;
+    for (int32_t lv = tr.depth; lv >= 0; --lv) {
+      auto [lo, hi] = S.range[b][lv];
+      if (lo == hi) continue;
+      int32_t n = hi - lo;
+      // factor sizes of non-leaf items from the sons' ranks
+      int64_t sum_r2 = 0, sum_r = 0;
+      for (int32_t i = lo; i < hi; ++i) {
+        ItemDev& it = S.items[i];
+        if (!it.leaf) it.r = S.items[it.son[0]].k + S.items[it.son[1]].k;
+        if (it.r > kMaxR)
+          fail(DH2_EUNSUPPORTED, "block row with " + std::to_string(it.r) +
+                                     " factor rows exceeds the kernel limit " +
+                                     std::to_string(kMaxR));
+        sum_r2 += (int64_t)it.r * it.r;
+        sum_r += it.r;
+      }
+      double2* Marena = (double2*)mem.alloc(sum_r2 * sizeof(double2));
+      double2* Qarena = (double2*)mem.alloc(sum_r2 * sizeof(double2));
+      double* sarena = (double*)mem.alloc(sum_r * sizeof(double));
+      S.keep.push_back(Qarena);
+      S.keep.push_back(sarena);
+      {
+        int64_t o2 = 0, o1 = 0;
+        for (int32_t i = lo; i < hi; ++i) {
+          ItemDev& it = S.items[i];
+          it.M = Marena + o2;
+          it.Q = Qarena + o2;
+          it.sig = sarena + o1;
+          o2 += (int64_t)it.r * it.r;
+          o1 += it.r;
+        }
+      }
+      copy_to(S.d_items + lo, S.items.data() + lo, n, st);
+      // Gram units: leaf items first, then non-leaf items
+      int64_t totalN = 0;
+      for (int32_t i = lo; i < hi; ++i) totalN += S.items[i].N;
+      int64_t width = std::max<int64_t>(512, std::min<int64_t>(8192, totalN / 4096));
+      width = (width + 31) / 32 * 32;
+      std::vector<UnitDev> units;
+      std::vector<int32_t> litems, ubegin;
+      int64_t slot = 0, nleafu = 0;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int32_t i = lo; i < hi; ++i) {
+          const ItemDev& it = S.items[i];
+          if ((pass == 0) != (it.leaf != 0)) continue;
+          litems.push_back(i);
+          ubegin.push_back((int32_t)units.size());
+          if (it.r == 0) continue;
+          for (int64_t c0 = 0; c0 < it.N; c0 += width) {
+            UnitDev u{};
+            u.item = i;
+            u.col_begin = c0;
+            u.ncols = std::min(width, it.N - c0);
+            u.slot_off = slot;
+            slot += npairs_of(it.r) * 256;
+            units.push_back(u);
+            double rr = it.r;
+            ss.flops_gram += 4.0 * rr * rr * (double)u.ncols;
+          }
+        }
+        if (pass == 0) nleafu = (int64_t)units.size();
+      }
+      ubegin.push_back((int32_t)units.size());
+      if ((size_t)slot * sizeof(double2) > partial_cap) {
+        mem.release(partial);
+        partial_cap = std::max<size_t>((size_t)slot * sizeof(double2), partial_cap * 3 / 2);
+        partial = (double2*)mem.alloc(partial_cap);
+      }
+      UnitDev* d_units = upload(mem, units, st);
+      int32_t* d_litems = upload(mem, litems, st);
+      int32_t* d_ubegin = upload(mem, ubegin, st);
+      tg.start();
+      launch_gram(M.src, false, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s, partial, st);
+      launch_check("gram (leaf)");
+      launch_gram(M.src, true, g, S.d_items, S.d_ents, d_units + nleafu,
+                  (int64_t)units.size() - nleafu, M.zeta, s, partial, st);
+      launch_check("gram (non-leaf)");
+      tg.stop();
+      launch_gram_reduce(S.d_items, d_litems, n, d_ubegin, d_units, partial, st);
+      launch_check("gram reduce");
+      launch_factor(S.d_items, d_litems, n, M.eps, 60, d_status, st);
+      launch_check("factor");
+      copy_from(S.items.data() + lo, S.d_items + lo, n, st);
+      int32_t status = 0;
+      copy_from(&status, d_status, 1, st);
+      if (status & 1)
+        fail(DH2_EUNSUPPORTED, "numerical rank of a block row exceeds the factor capacity");
+      if (status & 2) fail(DH2_ENOTCONV, "one-sided Jacobi did not converge");
+      mem.release(Marena);
+      for (int32_t i = lo; i < hi; ++i) S.items[i].M = nullptr;
+      // coefficient matrices R of this level
+      int64_t sumNk = 0;
+      for (int32_t i = lo; i < hi; ++i) sumNk += S.items[i].N * S.items[i].k;
+      double2* Rarena = (double2*)mem.alloc(sumNk * sizeof(double2));
+      {
+        int64_t o = 0;
+        for (int32_t i = lo; i < hi; ++i) {
+          S.items[i].R = Rarena + o;
+          o += S.items[i].N * S.items[i].k;
+        }
+      }
+      copy_to(S.d_items + lo, S.items.data() + lo, n, st);
+      std::vector<UnitDev> ru;
+      int64_t rwidth = 1024, nleafr = 0;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int32_t i = lo; i < hi; ++i) {
+          const ItemDev& it = S.items[i];
+          if ((pass == 0) != (it.leaf != 0) || it.k == 0) continue;
+          for (int64_t c0 = 0; c0 < it.N; c0 += rwidth) {
+            UnitDev u{};
+            u.item = i;
+            u.col_begin = c0;
+            u.ncols = std::min(rwidth, it.N - c0);
+            ru.push_back(u);
+          }
+          ss.flops_rprod += 8.0 * it.k * (double)it.r * (double)it.N;
+        }
+        if (pass == 0) nleafr = (int64_t)ru.size();
+      }
+      UnitDev* d_ru = upload(mem, ru, st);
+      launch_rprod(M.src, false, g, S.d_items, S.d_ents, d_ru, nleafr, M.zeta, s, st);
+      launch_check("rprod (leaf)");
+      launch_rprod(M.src, true, g, S.d_items, S.d_ents, d_ru + nleafr, (int64_t)ru.size() - nleafr,
+                   M.zeta, s, st);
+      launch_check("rprod (non-leaf)");
+      // projection of the admissible blocks of this level (row sweep)
+      if (s == 0) {
+        std::vector<ProjDev> tasks;
+        int64_t sumS = 0;
+        for (int32_t i = lo; i < hi; ++i) {
+          int32_t e = S.int2ext[i];
+          for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) {
+            const ColEntry& ce = cs.ent[q];
+            if (ce.d != 0) continue;
+            int32_t we = B.cs[1].find(ce.s, S.c[i]);
+            int32_t wi = M.side[1].ext2int[we];
+            sumS += (int64_t)S.items[i].k * M.side[1].items[wi].k;
+          }
+        }
+        double2* Sarena = (double2*)mem.alloc(sumS * sizeof(double2));
+        S.keep.push_back(Sarena);
+        int64_t o = 0;
+        for (int32_t i = lo; i < hi; ++i) {
+          int32_t e = S.int2ext[i];
+          const ItemDev& it = S.items[i];
+          for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) {
+            const ColEntry& ce = cs.ent[q];
+            if (ce.d != 0) continue;
+            int32_t we = B.cs[1].find(ce.s, S.c[i]);
+            int32_t wi = M.side[1].ext2int[we];
+            int32_t ks = M.side[1].items[wi].k;
+            ProjDev pd{};
+            pd.R = it.R + S.ent_col[q] * it.k;
+            pd.W = M.side[1].wexp[wi];
+            pd.S = Sarena + o;
+            pd.kt = it.k;
+            pd.ks = ks;
+            pd.ns = (int32_t)tr.size[ce.s];
+            pd.b = ce.b;
+            M.S_ptr[ce.b] = Sarena + o;
+            M.S_rows[ce.b] = it.k;
+            M.S_cols[ce.b] = ks;
+            o += (int64_t)it.k * ks;
+            ss.flops_prj += 8.0 * it.k * (double)ks * (double)pd.ns;
+            if (it.k > 0 && ks > 0) tasks.push_back(pd);
+          }
+        }
+        ProjDev* d_tasks = upload(mem, tasks, st);
+        tp.start();
+        launch_project(d_tasks, (int64_t)tasks.size(), M.d_omega, st);
+        launch_check("project");
+        tp.stop();
+        mem.release(d_tasks);
+      }
+      hip_check(hipStreamSynchronize(st), "level sync");
+      mem.release(d_units);
+      mem.release(d_litems);
+      mem.release(d_ubegin);
+      mem.release(d_ru);
+      mem.release(R_prev);
+      R_prev = Rarena;
+    }
+    mem.release(R_prev);
+    for (int32_t i = 0; i < S.nitems; ++i) S.items[i].R = nullptr;
+  }
+  mem.release(partial);
+  ss.t_gram += tg.acc;
+  ss.t_prj += tp.acc;
+}
+
+// expanded column bases, level by level from the leaves
+static void expand_side(MatrixData& M, int s, hipStream_t st) {
+  const ClusterTree& tr = M.blk->tree->tr;
+  Side& S = M.side[s];
+  DevMem& mem = *M.mem;
+  for (int32_t lv = tr.depth; lv >= 0; --lv) {
+    std::vector<int32_t> idx;
+    int64_t total = 0;
+    for (int32_t b = 0; b < M.nbatch; ++b)
+      for (int32_t i = S.range[b][lv].first; i < S.range[b][lv].second; ++i) {
+        idx.push_back(i);
+        if (!S.items[i].leaf) total += (int64_t)S.items[i].m * S.items[i].k;
+      }
+    if (idx.empty()) continue;
+    double2* arena = total ? (double2*)mem.alloc(total * sizeof(double2)) : nullptr;
+    if (arena) S.keep.push_back(arena);
+    std::vector<ExpandDev> tasks;
+    int64_t o = 0;
+    for (int32_t i : idx) {
+      ItemDev& it = S.items[i];
+      if (it.leaf) {
+        S.wexp[i] = it.Q;
+        continue;
+      }
+      S.wexp[i] = arena + o;
+      int64_t rowo = 0;
+      int32_t koff = 0;
+      for (int q = 0; q < 2; ++q) {
+        const ItemDev& so = S.items[it.son[q]];
+        ExpandDev ed{};
+        ed.src = S.wexp[it.son[q]];
+        ed.E = it.Q + (int64_t)koff * it.k;
+        ed.dst = arena + o + rowo * it.k;
+        ed.rows = so.m;
+        ed.ks = so.k;
+        ed.k = it.k;
+        if (it.k > 0) tasks.push_back(ed);
+        rowo += so.m;
+        koff += so.k;
+      }
+      o += (int64_t)it.m * it.k;
+    }
+    ExpandDev* d_tasks = upload(mem, tasks, st);
+    launch_expand(d_tasks, (int64_t)tasks.size(), st);
+    launch_check("expand");
+    hip_check(hipStreamSynchronize(st), "expand sync");
+    mem.release(d_tasks);
+  }
+}
+
+std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, const void* G,
+                                     int64_t ld, const double* w, double eps, const dh2_opts& o,
+                                     hipStream_t st) {
+  auto Mp = std::make_unique<MatrixData>();
+  MatrixData& M = *Mp;
+  M.blk = blk;
+  M.src = src;
+  M.eps = eps;
+  M.zeta = o.zeta;
+  M.precision = o.precision;
+  M.mem = std::make_unique<DevMem>(o.max_device_bytes);
+  const ClusterTree& tr = blk->tree->tr;
+  const BlockTree& bt = blk->bt;
+  int64_t n = tr.n;
+  int64_t nadm = (int64_t)bt.adm_t.size();
+  DevMem& mem = *M.mem;
+
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+
+  // geometry in permuted order
+  M.w.assign(n, 4.0 * M_PI / (double)n);
+  if (w) M.w.assign(w, w + n);
+  std::vector<double> pp(4 * n);
+  for (int64_t p = 0; p < n; ++p) {
+    int64_t i = tr.perm[p];
+    for (int a = 0; a < 3; ++a) pp[4 * p + a] = blk->tree->pts[3 * i + a];
+    pp[4 * p + 3] = M.w[i];
+  }
+  M.d_pts = upload(mem, pp, st);
+  M.d_perm = upload(mem, tr.perm, st);
+  GeomDev g{};
+  g.pts = M.d_pts;
+  g.G = (const double*)G;
+  g.perm = M.d_perm;
+  g.ldg = ld;
+  g.n = n;
+  g.kappa = blk->tree->kappa;
+
+  // batches: subtrees rooted one level above the first admissible level
+  M.lmin = nadm ? first_adm_level(*blk) : 0;
+  int32_t lg = std::max(0, M.lmin - 1);
+  std::vector<int32_t> group(tr.nc(), -1);
+  int32_t ngroups = 0;
+  for (int32_t t = 0; t < tr.nc(); ++t) {
+    if (tr.level[t] == lg) group[t] = ngroups++;
+    else if (tr.level[t] > lg) group[t] = group[tr.father[t]];
+  }
+  // estimated R memory per level (16 bytes per coefficient, rank estimate)
+  std::vector<double> lvlN(tr.depth + 2, 0.0), grpN(std::max(1, ngroups), 0.0);
+  for (int s = 0; s < 2; ++s) {
+    const ColumnSets& cs = blk->cs[s];
+    for (int32_t e = 0; e < cs.nitems(); ++e) {
+      int32_t t = cs.item_t[e];
+      double N = 0;
+      for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) N += (double)tr.size[cs.ent[q].s];
+      lvlN[tr.level[t]] += N * 0.5;
+      if (group[t] >= 0) grpN[group[t]] += N;
+    }
+  }
+  double kest = std::min(48.0, (double)o.leaf_size);
+  double peak = 0;
+  for (int32_t l = 0; l <= tr.depth; ++l) peak = std::max(peak, (lvlN[l] + lvlN[l + 1]) * kest * 16.0);
+  size_t freeb = 0, totalb = 0;
+  hip_check(hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo");
+  double budget = 0.4 * (double)freeb;
+  if (o.max_device_bytes > 0) budget = std::min(budget, 0.4 * (double)o.max_device_bytes);
+  int32_t nb = o.groups > 0 ? o.groups : (int32_t)std::ceil(peak / std::max(1.0, budget));
+  nb = std::max(1, std::min(nb, std::max(1, ngroups)));
+  M.nbatch = nb;
+  std::vector<int32_t> batch_of(tr.nc(), 0);
+  {
+    double tot = std::accumulate(grpN.begin(), grpN.end(), 0.0), cum = 0;
+    std::vector<int32_t> gb(std::max(1, ngroups), 0);
+    for (int32_t q = 0; q < ngroups; ++q) {
+      gb[q] = tot > 0 ? std::min(nb - 1, (int32_t)(cum * nb / tot)) : 0;
+      cum += grpN[q];
+    }
+    for (int32_t t = 0; t < tr.nc(); ++t) batch_of[t] = group[t] >= 0 ? gb[group[t]] : 0;
+  }
+
+  build_side(M, 0, batch_of);
+  build_side(M, 1, batch_of);
+  M.S_ptr.assign(nadm, nullptr);
+  M.S_rows.assign(nadm, 0);
+  M.S_cols.assign(nadm, 0);
+
+  int32_t* d_status = (int32_t*)mem.alloc(sizeof(int32_t));
+  hip_check(hipMemsetAsync(d_status, 0, sizeof(int32_t), st), "memset");
+
+  // block weights and column scales
+  hip_check(hipEventRecord(e0, st), "event");
+  {
+    std::vector<int64_t> to(nadm), tl(nadm), so(nadm), sl(nadm);
+    for (int64_t b = 0; b < nadm; ++b) {
+      to[b] = tr.off[bt.adm_t[b]];
+      tl[b] = tr.size[bt.adm_t[b]];
+      so[b] = tr.off[bt.adm_s[b]];
+      sl[b] = tr.size[bt.adm_s[b]];
+    }
+    int64_t* d_to = upload(mem, to, st);
+    int64_t* d_tl = upload(mem, tl, st);
+    int64_t* d_so = upload(mem, so, st);
+    int64_t* d_sl = upload(mem, sl, st);
+    M.d_omega = (double*)mem.alloc(std::max<int64_t>(1, nadm) * sizeof(double));
+    launch_block_norm(src, g, d_to, d_tl, d_so, d_sl, nadm, M.d_omega, st);
+    launch_check("block norms");
+    for (int s = 0; s < 2; ++s) {
+      Side& S = M.side[s];
+      S.d_items = upload(mem, S.items, st);
+      S.d_ents = upload(mem, S.ents, st);
+      launch_entry_scale(S.d_ents, (int64_t)S.ents.size(), M.d_omega, M.zeta, st);
+      launch_check("entry scales");
+    }
+    hip_check(hipStreamSynchronize(st), "weights sync");
+    mem.release(d_to);
+    mem.release(d_tl);
+    mem.release(d_so);
+    mem.release(d_sl);
+  }
+  hip_check(hipEventRecord(e1, st), "event");
+  hip_check(hipEventSynchronize(e1), "event");
+  float ms_w = 0;
+  hip_check(hipEventElapsedTime(&ms_w, e0, e1), "event");
+
+  SweepStats ss_col, ss_row;
+  hip_check(hipEventRecord(e0, st), "event");
+  sweep(M, 1, g, st, ss_col, d_status);
+  expand_side(M, 1, st);
+  hip_check(hipEventRecord(e1, st), "event");
+  hip_check(hipEventSynchronize(e1), "event");
+  float ms_col = 0;
+  hip_check(hipEventElapsedTime(&ms_col, e0, e1), "event");
+
+  hip_check(hipEventRecord(e0, st), "event");
+  sweep(M, 0, g, st, ss_row, d_status);
+  hip_check(hipEventRecord(e1, st), "event");
+  hip_check(hipEventSynchronize(e1), "event");
+  float ms_row = 0;
+  hip_check(hipEventElapsedTime(&ms_row, e0, e1), "event");
+
+  // near field
+  hip_check(hipEventRecord(e0, st), "event");
+  int64_t nnear = (int64_t)bt.near_t.size();
+  {
+    std::vector<int64_t> to(nnear), tl(nnear), so(nnear), sl(nnear), oo(nnear);
+    int64_t tot = 0;
+    M.nears.resize(nnear);
+    for (int64_t b = 0; b < nnear; ++b) {
+      to[b] = tr.off[bt.near_t[b]];
+      tl[b] = tr.size[bt.near_t[b]];
+      so[b] = tr.off[bt.near_s[b]];
+      sl[b] = tr.size[bt.near_s[b]];
+      oo[b] = tot;
+      M.nears[b] = NearDev{tot, to[b], tl[b], so[b], sl[b]};
+      tot += tl[b] * sl[b];
+    }
+    M.d_near = (double2*)mem.alloc(std::max<int64_t>(1, tot) * sizeof(double2));
+    int64_t* d_to = upload(mem, to, st);
+    int64_t* d_tl = upload(mem, tl, st);
+    int64_t* d_so = upload(mem, so, st);
+    int64_t* d_sl = upload(mem, sl, st);
+    int64_t* d_oo = upload(mem, oo, st);
+    launch_near(src, g, d_to, d_tl, d_so, d_sl, d_oo, nnear, M.d_near, st);
+    launch_check("near field");
+    hip_check(hipStreamSynchronize(st), "near sync");
+    mem.release(d_to);
+    mem.release(d_tl);
+    mem.release(d_so);
+    mem.release(d_sl);
+    mem.release(d_oo);
+  }
+  hip_check(hipEventRecord(e1, st), "event");
+  hip_check(hipEventSynchronize(e1), "event");
+  float ms_near = 0;
+  hip_check(hipEventElapsedTime(&ms_near, e0, e1), "event");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  mem.release(d_status);
+  // the dense matrix is borrowed only for this call
+  M.omega.resize(nadm);
+  copy_from(M.omega.data(), M.d_omega, nadm, st);
+
+  // statistics
+  dh2_stats& S = M.stats;
+  S.n = n;
+  S.nadm = nadm;
+  S.nnear = nnear;
+  S.items[0] = M.side[0].nitems;
+  S.items[1] = M.side[1].nitems;
+  int32_t kmax = 0;
+  double words = 0;
+  for (int s = 0; s < 2; ++s)
+    for (const ItemDev& it : M.side[s].items) {
+      kmax = std::max(kmax, it.k);
+      words += (double)it.r * it.k;  // leaf Q or transfer [E1;E2]
+    }
+  for (int64_t b = 0; b < nadm; ++b) words += (double)M.S_rows[b] * M.S_cols[b];
+  for (const NearDev& nd : M.nears) words += (double)nd.t_len * nd.s_len;
+  S.k_max = kmax;
+  S.mem_bytes = words * 16.0;
+  S.mem_per_n_kib = S.mem_bytes / 1024.0 / (double)n;
+  S.t_col = ms_col * 1e-3;
+  S.t_prj = ss_row.t_prj;
+  S.t_row = ms_row * 1e-3 - ss_row.t_prj;
+  S.t_near = ms_near * 1e-3;
+  S.t_total = (ms_w + ms_col + ms_row + ms_near) * 1e-3;
+  S.flops_row = ss_row.flops_gram + ss_row.flops_rprod;
+  S.flops_col = ss_col.flops_gram + ss_col.flops_rprod;
+  S.flops_prj = ss_row.flops_prj;
+  S.flops_gram = ss_row.flops_gram + ss_col.flops_gram;
+  S.flops_rprod = ss_row.flops_rprod + ss_col.flops_rprod;
+  S.t_gram_kernel = ss_row.t_gram + ss_col.t_gram;
+  S.groups = M.nbatch;
+  S.precision = M.precision;
+  return Mp;
+}
+
+// ---------------------------------------------------------------------------
+// matrix-vector product
+// ---------------------------------------------------------------------------
+static void build_mv(MatrixData& M, hipStream_t st) {
+  auto P = std::make_unique<MatvecPlan>();
+  const BlocksData& B = *M.blk;
+  const ClusterTree& tr = B.tree->tr;
+  const Directions& dr = B.tree->dr;
+  const BlockTree& bt = B.bt;
+  DevMem& mem = *M.mem;
+  int64_t nadm = (int64_t)bt.adm_t.size();
+  int64_t maxh = 0;
+  for (int s = 0; s < 2; ++s) {
+    Side& S = M.side[s];
+    SideMV& V = P->s[s];
+    std::vector<int64_t> hoff(S.nitems + 1, 0);
+    for (int32_t i = 0; i < S.nitems; ++i) hoff[i + 1] = hoff[i] + S.items[i].k;
+    V.total = hoff[S.nitems];
+    maxh = std::max(maxh, V.total);
+    V.d_hoff = upload(mem, hoff, st);
+    // coupling lists: this side receives; blocks whose cluster on this side is the item
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> lst(S.nitems);
+    for (int64_t b = 0; b < nadm; ++b) {
+      int32_t t = s == 0 ? bt.adm_t[b] : bt.adm_s[b];
+      int32_t o = s == 0 ? bt.adm_s[b] : bt.adm_t[b];
+      int32_t c = bt.adm_c[b];
+      int32_t me = S.ext2int[B.cs[s].find(t, c)];
+      int32_t pe = M.side[1 - s].ext2int[B.cs[1 - s].find(o, c)];
+      lst[me].push_back({(int32_t)b, pe});
+    }
+    std::vector<int64_t> cb(S.nitems + 1, 0);
+    std::vector<int32_t> cblk, cpar;
+    for (int32_t i = 0; i < S.nitems; ++i) {
+      for (auto& pr : lst[i]) {
+        cblk.push_back(pr.first);
+        cpar.push_back(pr.second);
+      }
+      cb[i + 1] = (int64_t)cblk.size();
+    }
+    V.d_cbegin = upload(mem, cb, st);
+    V.d_cblock = upload(mem, cblk, st);
+    V.d_cpartner = upload(mem, cpar, st);
+    // forward lists
+    std::vector<int32_t> leafs;
+    std::vector<std::vector<int32_t>> byl(tr.depth + 1);
+    for (int32_t i = 0; i < S.nitems; ++i) {
+      if (S.items[i].leaf) leafs.push_back(i);
+      else byl[S.items[i].level].push_back(i);
+    }
+    V.d_fwd_leaf = upload(mem, leafs, st);
+    V.n_fwd_leaf = (int32_t)leafs.size();
+    for (int32_t l = tr.depth; l >= 0; --l) {
+      V.d_fwd_lvl.push_back(upload(mem, byl[l], st));
+      V.fwd_count.push_back((int32_t)byl[l].size());
+    }
+    // backward lists: per level, items with father items
+    for (int32_t l = 0; l <= tr.depth; ++l) {
+      std::vector<int32_t> items, fitem, fson;
+      std::vector<int64_t> fb{0};
+      for (int32_t i = 0; i < S.nitems; ++i) {
+        if (S.items[i].level != l) continue;
+        int32_t t = S.t[i], c = S.c[i];
+        int32_t fa = tr.father[t];
+        std::vector<std::pair<int32_t, int32_t>> fl;
+        if (fa >= 0) {
+          const auto& sdl = dr.sd[tr.level[fa]];
+          const ColumnSets& cs = B.cs[s];
+          for (int32_t e = cs.first[fa]; e < cs.first[fa] + cs.count[fa]; ++e)
+            if (sdl[cs.item_c[e]] == c) fl.push_back({S.ext2int[e], tr.son1[fa] == t ? 0 : 1});
+        }
+        if (fl.empty()) continue;
+        items.push_back(i);
+        for (auto& pr : fl) {
+          fitem.push_back(pr.first);
+          fson.push_back(pr.second);
+        }
+        fb.push_back((int64_t)fitem.size());
+      }
+      V.d_bl_items.push_back(upload(mem, items, st));
+      V.bl_count.push_back((int32_t)items.size());
+      V.d_bl_fbegin.push_back(upload(mem, fb, st));
+      V.d_bl_fitem.push_back(upload(mem, fitem, st));
+      V.d_bl_fson.push_back(upload(mem, fson, st));
+    }
+    // leaves with their items and near-field references
+    std::vector<LeafDev> leaves;
+    std::vector<NearRefDev> refs;
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> nl(tr.nc());
+    for (int64_t b = 0; b < (int64_t)bt.near_t.size(); ++b) {
+      int32_t t = s == 0 ? bt.near_t[b] : bt.near_s[b];
+      // every leaf below t
+      std::vector<int32_t> stk{t};
+      while (!stk.empty()) {
+        int32_t u = stk.back();
+        stk.pop_back();
+        if (tr.leaf(u)) nl[u].push_back({b, tr.off[u] - tr.off[t]});
+        else {
+          stk.push_back(tr.son1[u]);
+          stk.push_back(tr.son2[u]);
+        }
+      }
+    }
+    for (int32_t t = 0; t < tr.nc(); ++t) {
+      if (!tr.leaf(t)) continue;
+      LeafDev L{};
+      L.row_off = tr.off[t];
+      L.len = (int32_t)tr.size[t];
+      // items of t are contiguous in internal order
+      int32_t cnt = B.cs[s].count[t];
+      L.item_first = cnt ? S.ext2int[B.cs[s].first[t]] : 0;
+      L.item_count = cnt;
+      for (int32_t q = 1; q < cnt; ++q)
+        if (S.ext2int[B.cs[s].first[t] + q] != L.item_first + q) fail(DH2_EDEVICE, "internal: leaf items not contiguous");
+      L.near_begin = (int64_t)refs.size();
+      for (auto& pr : nl[t]) refs.push_back(NearRefDev{pr.first, pr.second});
+      L.near_end = (int64_t)refs.size();
+      leaves.push_back(L);
+    }
+    V.d_leaves = upload(mem, leaves, st);
+    V.d_nref = upload(mem, refs, st);
+    V.nleaves = (int32_t)leaves.size();
+  }
+  P->d_nears = upload(mem, M.nears, st);
+  std::vector<double2*> sp(M.S_ptr.begin(), M.S_ptr.end());
+  P->d_Sptr = upload(mem, sp, st);
+  P->d_Srows = upload(mem, M.S_rows, st);
+  P->d_Scols = upload(mem, M.S_cols, st);
+  int64_t n = tr.n;
+  P->xp = (double2*)mem.alloc(n * sizeof(double2));
+  P->yp = (double2*)mem.alloc(n * sizeof(double2));
+  P->xh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * sizeof(double2));
+  P->yh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * sizeof(double2));
+  M.mv = std::move(P);
+}
+
+void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st) {
+  if (!M.mv) build_mv(M, st);
+  MatvecPlan& P = *M.mv;
+  const ClusterTree& tr = M.blk->tree->tr;
+  int64_t n = tr.n;
+  int adj = (op == 'C' || op == 'c') ? 1 : 0;
+  int src_side = adj ? 0 : 1, dst_side = adj ? 1 : 0;
+  Side& A = M.side[src_side];
+  Side& Bs = M.side[dst_side];
+  SideMV& VA = P.s[src_side];
+  SideMV& VB = P.s[dst_side];
+  launch_gather_perm(x, M.d_perm, n, P.xp, st);
+  launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, P.xp, P.xh, st);
+  for (size_t q = 0; q < VA.d_fwd_lvl.size(); ++q)
+    launch_fwd_inner(A.d_items, VA.d_fwd_lvl[q], VA.fwd_count[q], VA.d_hoff, P.xh, st);
+  launch_coupling(Bs.d_items, Bs.nitems, VB.d_cbegin, VB.d_cblock, VB.d_cpartner, P.d_Sptr,
+                  P.d_Srows, P.d_Scols, VA.d_hoff, P.xh, VB.d_hoff, P.yh, adj, st);
+  for (size_t l = 0; l < VB.d_bl_items.size(); ++l)
+    launch_bwd_inner(Bs.d_items, VB.d_bl_items[l], VB.bl_count[l], VB.d_bl_fbegin[l],
+                     VB.d_bl_fitem[l], VB.d_bl_fson[l], VB.d_hoff, P.yh, st);
+  launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near, VB.d_hoff,
+                  P.yh, P.xp, P.yp, adj, st);
+  launch_scatter_perm(P.yp, M.d_perm, n, y, st);
+  launch_check("matvec");
+}
+
+// ---------------------------------------------------------------------------
+// error measures
+// ---------------------------------------------------------------------------
+static GeomDev geom(MatrixData& M, const void* G, int64_t ld) {
+  GeomDev g{};
+  g.pts = M.d_pts;
+  g.G = (const double*)G;
+  g.perm = M.d_perm;
+  g.ldg = ld;
+  g.n = M.blk->tree->tr.n;
+  g.kappa = M.blk->tree->kappa;
+  return g;
+}
+
+// y = G x or G^* x, all vectors in original order on the device
+static void direct_apply(MatrixData& M, int src, const GeomDev& g, const double2* x, double2* y,
+                         int adj, double2* tmp_p, double2* tmp_o, hipStream_t st) {
+  int64_t n = g.n;
+  launch_gather_perm(x, M.d_perm, n, tmp_p, st);
+  launch_direct(src, g, nullptr, n, tmp_p, adj, tmp_o, st);
+  launch_scatter_perm(tmp_o, M.d_perm, n, y, st);
+  launch_check("direct product");
+}
+
+double error_estimate(MatrixData& M, const void* G, int64_t ld, int iters, uint64_t seed,
+                      hipStream_t st) {
+  int64_t n = M.blk->tree->tr.n;
+  int src = G ? SRC_DENSE : SRC_HELMHOLTZ;
+  if (src == SRC_HELMHOLTZ && M.src == SRC_DENSE)
+    fail(DH2_EINVAL, "the matrix was compressed from a dense input: pass G");
+  GeomDev g = geom(M, G, ld);
+  DevMem& mem = *M.mem;
+  double2* bufs = (double2*)mem.alloc(6 * n * sizeof(double2));
+  double2 *x = bufs, *y1 = bufs + n, *y2 = bufs + 2 * n, *z = bufs + 3 * n, *tp = bufs + 4 * n,
+          *to = bufs + 5 * n;
+  std::vector<double2> hx(n), hy(n), hz(n);
+  auto run = [&](bool diff) {
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd;
+    double nrm = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      hx[i] = make_double2(nd(rng), nd(rng));
+      nrm += hx[i].x * hx[i].x + hx[i].y * hx[i].y;
+    }
+    nrm = std::sqrt(nrm);
+    for (auto& v : hx) v = make_double2(v.x / nrm, v.y / nrm);
+    double lam = 0, lam_old = 0;
+    for (int it = 0; it < iters; ++it) {
+      copy_to(x, hx.data(), n, st);
+      direct_apply(M, src, g, x, y1, 0, tp, to, st);
+      if (diff) {
+        matvec(M, 'N', x, y2, st);
+        copy_from(hy.data(), y1, n, st);
+        copy_from(hz.data(), y2, n, st);
+        for (int64_t i = 0; i < n; ++i) hy[i] = make_double2(hy[i].x - hz[i].x, hy[i].y - hz[i].y);
+        copy_to(y1, hy.data(), n, st);
+      }
+      direct_apply(M, src, g, y1, z, 1, tp, to, st);
+      if (diff) {
+        matvec(M, 'C', y1, y2, st);
+        copy_from(hz.data(), z, n, st);
+        copy_from(hy.data(), y2, n, st);
+        for (int64_t i = 0; i < n; ++i) hz[i] = make_double2(hz[i].x - hy[i].x, hz[i].y - hy[i].y);
+      } else {
+        copy_from(hz.data(), z, n, st);
+      }
+      double re = 0, zn = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        re += hx[i].x * hz[i].x + hx[i].y * hz[i].y;
+        zn += hz[i].x * hz[i].x + hz[i].y * hz[i].y;
+      }
+      lam = re;
+      zn = std::sqrt(zn);
+      if (zn == 0) return 0.0;
+      for (int64_t i = 0; i < n; ++i) hx[i] = make_double2(hz[i].x / zn, hz[i].y / zn);
+      if (lam_old > 0 && std::fabs(lam - lam_old) <= 1e-4 * lam) break;
+      lam_old = lam;
+    }
+    return std::sqrt(std::max(lam, 0.0));
+  };
+  double num = run(true);
+  double den = run(false);
+  mem.release(bufs);
+  return den > 0 ? num / den : 0.0;
+}
+
+void rows_check(MatrixData& M, const int64_t* rows, int32_t nrows, const double2* x,
+                double* direct, double* approx, double* max_rel, hipStream_t st) {
+  const ClusterTree& tr = M.blk->tree->tr;
+  int64_t n = tr.n;
+  if (M.src == SRC_DENSE) fail(DH2_EINVAL, "rows_check needs a matrix generated from points");
+  std::vector<int64_t> inv(n);
+  for (int64_t p = 0; p < n; ++p) inv[tr.perm[p]] = p;
+  std::vector<int64_t> pos(nrows);
+  for (int32_t q = 0; q < nrows; ++q) {
+    if (rows[q] < 0 || rows[q] >= n) fail(DH2_EINVAL, "row index out of range");
+    pos[q] = inv[rows[q]];
+  }
+  DevMem& mem = *M.mem;
+  GeomDev g = geom(M, nullptr, 0);
+  int64_t* d_pos = upload(mem, pos, st);
+  double2* bufs = (double2*)mem.alloc((2 * n + nrows) * sizeof(double2));
+  double2 *xp = bufs, *y = bufs + n, *out = bufs + 2 * n;
+  launch_gather_perm(x, M.d_perm, n, xp, st);
+  launch_direct(SRC_HELMHOLTZ, g, d_pos, nrows, xp, 0, out, st);
+  launch_check("rows direct");
+  matvec(M, 'N', x, y, st);
+  std::vector<double2> hd(nrows), hy(n);
+  copy_from(hd.data(), out, nrows, st);
+  copy_from(hy.data(), y, n, st);
+  double num = 0, den = 0;
+  for (int32_t q = 0; q < nrows; ++q) {
+    double2 a = hy[rows[q]];
+    if (direct) {
+      direct[2 * q] = hd[q].x;
+      direct[2 * q + 1] = hd[q].y;
+    }
+    if (approx) {
+      approx[2 * q] = a.x;
+      approx[2 * q + 1] = a.y;
+    }
+    num = std::max(num, std::hypot(a.x - hd[q].x, a.y - hd[q].y));
+    den = std::max(den, std::hypot(hd[q].x, hd[q].y));
+  }
+  if (max_rel) *max_rel = den > 0 ? num / den : 0.0;
+  mem.release(bufs);
+  mem.release(d_pos);
+}
+
+}  // namespace dh2

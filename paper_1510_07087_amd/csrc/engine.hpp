@@ -1,0 +1,113 @@
+// Host engine: plan handles, device memory, the compression sweep, the DH2
+// matrix-vector product and the error measures.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dh2.h"
+#include "common.hpp"
+#include "plan.hpp"
+
+namespace dh2 {
+
+struct Error {
+  dh2_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(dh2_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+// Device allocations with an optional cap (max_device_bytes).
+class DevMem {
+ public:
+  explicit DevMem(int64_t cap = 0) : cap_(cap) {}
+  ~DevMem();
+  void* alloc(size_t bytes);
+  void release(void* p);
+  int64_t used() const { return used_; }
+  int64_t peak() const { return peak_; }
+
+ private:
+  int64_t cap_;
+  int64_t used_ = 0;
+  int64_t peak_ = 0;
+  std::vector<std::pair<void*, size_t>> live_;
+};
+
+struct TreeData {
+  ClusterTree tr;
+  Directions dr;
+  std::vector<double> pts;  // original order, n x 3
+  double kappa = 0;
+  dh2_opts opts;
+};
+
+struct BlocksData {
+  std::shared_ptr<TreeData> tree;
+  BlockTree bt;
+  ColumnSets cs[2];
+  dh2_opts opts;
+};
+
+// One basis (side 0: rows of G, side 1: rows of G^*), items in internal
+// order: sorted by (batch, level descending, cluster, direction).
+struct Side {
+  int32_t nitems = 0;
+  std::vector<ItemDev> items;       // host mirror of the device array
+  ItemDev* d_items = nullptr;
+  std::vector<int32_t> ext2int;     // column-set order -> internal
+  std::vector<int32_t> int2ext;
+  std::vector<int32_t> t, c;        // per internal item
+  std::vector<EntDev> ents;         // leaf entries (device copy below)
+  EntDev* d_ents = nullptr;
+  std::vector<int64_t> ent_col;     // per column-set entry: column start inside its item
+  // (batch, level) ranges of internal items
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> range;  // [batch][level] -> [lo,hi)
+  std::vector<void*> keep;          // Q and sigma arenas
+  // expanded basis (column side): per internal item pointer, rows x k row-major
+  std::vector<double2*> wexp;
+};
+
+struct MatvecPlan;
+
+struct MatrixData {
+  std::shared_ptr<BlocksData> blk;
+  std::unique_ptr<DevMem> mem;
+  int src = SRC_HELMHOLTZ;
+  int precision = DH2_FP64;
+  double eps = 0, zeta = 0;
+  int32_t nbatch = 1;
+  int32_t lmin = 0;
+  // device geometry
+  double* d_pts = nullptr;     // permuted n x 4
+  int64_t* d_perm = nullptr;
+  std::vector<double> w;       // original-order weights
+  Side side[2];
+  double* d_omega = nullptr;
+  std::vector<double> omega;
+  std::vector<double2*> S_ptr; // per admissible block
+  std::vector<int32_t> S_rows, S_cols;
+  double2* d_near = nullptr;
+  std::vector<NearDev> nears;
+  dh2_stats stats{};
+  std::unique_ptr<MatvecPlan> mv;
+  ~MatrixData();
+};
+
+std::shared_ptr<TreeData> make_tree(const double* pts, int64_t n, double kappa, const dh2_opts& o);
+std::shared_ptr<BlocksData> make_blocks(std::shared_ptr<TreeData> t, const dh2_opts& o);
+std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> b, int src, const void* G,
+                                     int64_t ld, const double* w, double eps, const dh2_opts& o,
+                                     hipStream_t st);
+void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st);
+double error_estimate(MatrixData& M, const void* G, int64_t ld, int iters, uint64_t seed,
+                      hipStream_t st);
+void rows_check(MatrixData& M, const int64_t* rows, int32_t nrows, const double2* x,
+                double* direct, double* approx, double* max_rel, hipStream_t st);
+
+}  // namespace dh2

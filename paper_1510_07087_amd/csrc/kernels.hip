@@ -1,0 +1,1107 @@
+// gfx950 kernels of the directional H2 compression (FP64 path).
+//
+// Block rows are processed in LDS stages of kStageCols columns.  A stage
+// holds the tile A[rho][col] of the weighted block row G^w_tc (leaf
+// clusters: entries generated from the points; other clusters: the rows of
+// G_hat_tc = zeta [R_t1c' ; R_t2c'] gathered from the sons' coefficient
+// matrices).  Consumers:
+//   * Gram:      M += A A^*   (FP64 MFMA 16x16x4, lower-triangular tiles)
+//   * R-product: R^T += A^T conj(Q)   (FP64 MFMA), i.e. R_tc = Q^* A
+// The small factorisation (pivoted Cholesky of M, one-sided Jacobi on the
+// factor) produces the left singular vectors and singular values of the block
+// row (Section 6: the basis is formed by the first k left singular vectors).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace dh2 {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dvec4 mfma_f64(double a, double b, dvec4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
+
+// ---------------------------------------------------------------------------
+// Matrix entries.  Side 0 reads G, side 1 reads G^* (rows of G^* are columns
+// of G): entry(i,j) = conj(G_ji).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 helm_offdiag(double dx, double dy, double dz, double w,
+                                                double kappa, int side) {
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double s, c;
+  sincos(kappa * r, &s, &c);
+  double a = w * kInv4Pi / r;
+  return make_double2(a * c, side == 0 ? a * s : -a * s);
+}
+
+__device__ __forceinline__ double2 helm_entry(const GeomDev& g, int64_t pi, int64_t pj, int side) {
+  const double* xi = g.pts + 4 * pi;
+  const double* xj = g.pts + 4 * pj;
+  if (pi == pj) {
+    double w = xi[3];
+    double im = g.kappa * w * kInv4Pi;
+    return make_double2(0.5 * sqrt(w * 0.3183098861837907), side == 0 ? im : -im);
+  }
+  double w = side == 0 ? xj[3] : xi[3];
+  return helm_offdiag(xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2], w, g.kappa, side);
+}
+
+__device__ __forceinline__ double2 dense_entry(const GeomDev& g, int64_t pi, int64_t pj, int side) {
+  const double2* G = reinterpret_cast<const double2*>(g.G);
+  if (side == 0) return G[g.perm[pi] * g.ldg + g.perm[pj]];
+  double2 v = G[g.perm[pj] * g.ldg + g.perm[pi]];
+  return make_double2(v.x, -v.y);
+}
+
+template <int SRC>
+__device__ __forceinline__ double2 entry(const GeomDev& g, int64_t pi, int64_t pj, int side) {
+  if constexpr (SRC == SRC_HELMHOLTZ)
+    return helm_entry(g, pi, pj, side);
+  else
+    return dense_entry(g, pi, pj, side);
+}
+
+// ---------------------------------------------------------------------------
+// Block norms: omega_b^2 = sum |G_ij|^2 over the admissible block.
+// ---------------------------------------------------------------------------
+template <int SRC>
+__global__ __launch_bounds__(256) void k_block_norm(GeomDev g, const int64_t* t_off,
+                                                    const int64_t* t_len, const int64_t* s_off,
+                                                    const int64_t* s_len, int64_t nblocks,
+                                                    double* omega) {
+  __shared__ double red[256];
+  int64_t b = blockIdx.x;
+  if (b >= nblocks) return;
+  int64_t to = t_off[b], tl = t_len[b], so = s_off[b], sl = s_len[b];
+  double acc = 0.0;
+  int64_t tot = tl * sl;
+  for (int64_t e = threadIdx.x; e < tot; e += 256) {
+    int64_t i = to + e / sl, j = so + e % sl;
+    double v;
+    if constexpr (SRC == SRC_HELMHOLTZ) {
+      const double* xi = g.pts + 4 * i;
+      const double* xj = g.pts + 4 * j;
+      double dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
+      double a = xj[3] * kInv4Pi;
+      v = a * a / (dx * dx + dy * dy + dz * dz);
+    } else {
+      double2 z = dense_entry(g, i, j, 0);
+      v = z.x * z.x + z.y * z.y;
+    }
+    acc += v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) omega[b] = sqrt(red[0]);
+}
+
+// scale of each column-set entry: 1 / (omega_b zeta^d)
+__global__ void k_entry_scale(EntDev* ent, int64_t nent, const double* omega, double zeta) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nent) return;
+  double z = 1.0;
+  for (int q = 0; q < ent[e].d; ++q) z *= zeta;
+  ent[e].scale = 1.0 / (omega[ent[e].b] * z);
+}
+
+// ---------------------------------------------------------------------------
+// Stage producer: T[c * ld + rho] = A[rho][col0 + c] for c < kStageCols,
+// rho < rp (zero outside the item).  ld = rp + 1 (bank spread).
+// ---------------------------------------------------------------------------
+struct StageCtx {
+  const ItemDev* it;
+  int64_t item_r;     // rows of A
+  int rp;             // rows padded to 16
+  int ld;
+};
+
+template <int SRC>
+__device__ void produce_leaf(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
+                             int64_t col0, int64_t ncols, int rp, int ld, double2* T,
+                             int64_t* cpos, double* cscale) {
+  int tid = threadIdx.x;
+  if (tid < kStageCols) {
+    int64_t j = col0 + tid;
+    int64_t pos = -1;
+    double sc = 0.0;
+    if (tid < ncols) {
+      int64_t lo = it.ent_begin, hi = it.ent_end - 1;
+      while (lo < hi) {  // last entry with col_start <= j
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (ents[mid].col_start <= j)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const EntDev& e = ents[lo];
+      pos = e.pos + (j - e.col_start);
+      sc = e.scale;
+    }
+    cpos[tid] = pos;
+    cscale[tid] = sc;
+  }
+  __syncthreads();
+  int m = it.m;
+  for (int e = tid; e < kStageCols * rp; e += 256) {
+    int c = e / rp, rho = e - c * rp;
+    double2 v = make_double2(0.0, 0.0);
+    int64_t pj = cpos[c];
+    if (rho < m && pj >= 0) {
+      double2 z = entry<SRC>(g, it.row_off + rho, pj, side);
+      double s = cscale[c];
+      v = make_double2(z.x * s, z.y * s);
+    }
+    T[c * ld + rho] = v;
+  }
+}
+
+__device__ void produce_inner(const ItemDev* items, const ItemDev& it, double zeta, int64_t col0, int64_t ncols, int rp, int ld,
+                              double2* T) {
+  const ItemDev& s1 = items[it.son[0]];
+  const ItemDev& s2 = items[it.son[1]];
+  int k1 = s1.k, k2 = s2.k, r = it.r;
+  int tid = threadIdx.x;
+  for (int e = tid; e < kStageCols * rp; e += 256) {
+    int c = e / rp, rho = e - c * rp;
+    double2 v = make_double2(0.0, 0.0);
+    if (c < ncols && rho < r) {
+      int64_t j = it.col_off + col0 + c;
+      double2 z = rho < k1 ? s1.R[j * k1 + rho] : s2.R[j * k2 + (rho - k1)];
+      v = make_double2(z.x * zeta, z.y * zeta);
+    }
+    T[c * ld + rho] = v;
+  }
+}
+
+constexpr int kTileLds = kStageCols * (kMaxR + 1);  // double2 elements
+
+// ---------------------------------------------------------------------------
+// Gram of a block row: partial sums per unit into slot_off (lower tiles,
+// MFMA output layout [pair][v][lane]).  nt <= 4: every wave runs all tile
+// pairs on a quarter of the k-steps, then the waves are summed in a fixed
+// order; nt > 4: the waves split the tile pairs.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void gram_stage_all_pairs(const double2* T, int ld, int ncols, dvec4 (&acr)[10],
+                                     dvec4 (&aci)[10]) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int row = lane & 15, kq = lane >> 4;
+  for (int ks = w; ks * 4 < ncols; ks += 4) {
+    const double2* col = T + (ks * 4 + kq) * ld + row;
+    double ar[NT], ai[NT];
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+      double2 v = col[16 * I];
+      ar[I] = v.x;
+      ai[I] = v.y;
+    }
+    int p = 0;
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+#pragma unroll
+      for (int J = 0; J <= I; ++J) {
+        acr[p] = mfma_f64(ar[I], ar[J], acr[p]);
+        acr[p] = mfma_f64(ai[I], ai[J], acr[p]);
+        aci[p] = mfma_f64(ai[I], ar[J], aci[p]);
+        aci[p] = mfma_f64(-ar[I], ai[J], aci[p]);
+        ++p;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void pair_ij(int p, int& I, int& J) {
+  I = 0;
+  while ((I + 1) * (I + 2) / 2 <= p) ++I;
+  J = p - I * (I + 1) / 2;
+}
+
+template <int SRC, bool INNER>
+__global__ __launch_bounds__(256) void k_gram(GeomDev g, const ItemDev* items, const EntDev* ents,
+                                              const UnitDev* units, double zeta, int side,
+                                              double2* partial) {
+  __shared__ double2 T[kTileLds];
+  __shared__ int64_t cpos[kStageCols];
+  __shared__ double cscale[kStageCols];
+  const UnitDev u = units[blockIdx.x];
+  const ItemDev it = items[u.item];
+  int r = it.r;
+  int nt = (r + 15) / 16, rp = nt * 16, ld = rp + 1;
+  int npairs = nt * (nt + 1) / 2;
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double2* out = partial + u.slot_off;
+
+  if (nt <= 4) {
+    dvec4 acr[10], aci[10];
+#pragma unroll
+    for (int p = 0; p < 10; ++p) {
+      acr[p] = dvec4{0, 0, 0, 0};
+      aci[p] = dvec4{0, 0, 0, 0};
+    }
+    for (int64_t c0 = 0; c0 < u.ncols; c0 += kStageCols) {
+      int64_t nc = u.ncols - c0 < kStageCols ? u.ncols - c0 : kStageCols;
+      __syncthreads();
+      if constexpr (INNER)
+        produce_inner(items, it, zeta, u.col_begin + c0, nc, rp, ld, T);
+      else
+        produce_leaf<SRC>(g, it, ents, side, u.col_begin + c0, nc, rp, ld, T, cpos, cscale);
+      __syncthreads();
+      switch (nt) {
+        case 1: gram_stage_all_pairs<1>(T, ld, (int)nc, acr, aci); break;
+        case 2: gram_stage_all_pairs<2>(T, ld, (int)nc, acr, aci); break;
+        case 3: gram_stage_all_pairs<3>(T, ld, (int)nc, acr, aci); break;
+        default: gram_stage_all_pairs<4>(T, ld, (int)nc, acr, aci); break;
+      }
+    }
+    // fixed-order reduction over the four waves (wave 0 accumulates)
+    double* red = reinterpret_cast<double*>(T);
+    for (int src = 1; src < 4; ++src) {
+      __syncthreads();
+      if (w == src) {
+#pragma unroll
+        for (int p = 0; p < 10; ++p)
+          if (p < npairs)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              red[((p * 4 + v) * 64 + lane) * 2 + 0] = acr[p][v];
+              red[((p * 4 + v) * 64 + lane) * 2 + 1] = aci[p][v];
+            }
+      }
+      __syncthreads();
+      if (w == 0) {
+#pragma unroll
+        for (int p = 0; p < 10; ++p)
+          if (p < npairs)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              acr[p][v] += red[((p * 4 + v) * 64 + lane) * 2 + 0];
+              aci[p][v] += red[((p * 4 + v) * 64 + lane) * 2 + 1];
+            }
+      }
+    }
+    if (w == 0) {
+#pragma unroll
+      for (int p = 0; p < 10; ++p)
+        if (p < npairs)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[p][v], aci[p][v]);
+    }
+  } else {
+    // nt in 5..8: up to 36 tile pairs, wave w owns pairs w, w+4, ...
+    constexpr int kMaxOwn = 9;
+    dvec4 acr[kMaxOwn], aci[kMaxOwn];
+    int pi_[kMaxOwn], pj_[kMaxOwn];
+#pragma unroll
+    for (int q = 0; q < kMaxOwn; ++q) {
+      acr[q] = dvec4{0, 0, 0, 0};
+      aci[q] = dvec4{0, 0, 0, 0};
+      int p = w + 4 * q;
+      int I = 0, J = 0;
+      if (p < npairs) pair_ij(p, I, J);
+      pi_[q] = I;
+      pj_[q] = J;
+    }
+    int row = lane & 15, kq = lane >> 4;
+    for (int64_t c0 = 0; c0 < u.ncols; c0 += kStageCols) {
+      int64_t nc = u.ncols - c0 < kStageCols ? u.ncols - c0 : kStageCols;
+      __syncthreads();
+      if constexpr (INNER)
+        produce_inner(items, it, zeta, u.col_begin + c0, nc, rp, ld, T);
+      else
+        produce_leaf<SRC>(g, it, ents, side, u.col_begin + c0, nc, rp, ld, T, cpos, cscale);
+      __syncthreads();
+      for (int ks = 0; ks * 4 < nc; ++ks) {
+        const double2* col = T + (ks * 4 + kq) * ld + row;
+#pragma unroll
+        for (int q = 0; q < kMaxOwn; ++q) {
+          if (w + 4 * q < npairs) {
+            double2 a = col[16 * pi_[q]];
+            double2 b = col[16 * pj_[q]];
+            acr[q] = mfma_f64(a.x, b.x, acr[q]);
+            acr[q] = mfma_f64(a.y, b.y, acr[q]);
+            aci[q] = mfma_f64(a.y, b.x, aci[q]);
+            aci[q] = mfma_f64(-a.x, b.y, aci[q]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxOwn; ++q) {
+      int p = w + 4 * q;
+      if (p < npairs)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[q][v], aci[q][v]);
+    }
+  }
+}
+
+// Sum the partial Grams of each item (in unit order) into M (r x r,
+// column-major, Hermitian: both triangles written).
+__global__ __launch_bounds__(256) void k_gram_reduce(const ItemDev* items, const int32_t* litems,
+                                                     const int32_t* ubegin, const UnitDev* units,
+                                                     const double2* partial) {
+  int32_t i = litems[blockIdx.x];
+  const ItemDev& it = items[i];
+  int r = it.r, nt = (r + 15) / 16, npairs = nt * (nt + 1) / 2;
+  int32_t ub = ubegin[blockIdx.x], ue = ubegin[blockIdx.x + 1];
+  double2* Mi = it.M;
+  for (int e = threadIdx.x; e < npairs * 256; e += 256) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int32_t q = ub; q < ue; ++q) {
+      double2 v = partial[units[q].slot_off + e];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    int p = e >> 8, v = (e >> 6) & 3, lane = e & 63;
+    int I, J;
+    pair_ij(p, I, J);
+    int row = 16 * I + 4 * (lane >> 4) + v, col = 16 * J + (lane & 15);
+    if (row < r && col < r) {
+      if (I != J || row >= col) {
+        Mi[row + (int64_t)col * r] = s;
+        if (row != col) Mi[col + (int64_t)row * r] = make_double2(s.x, -s.y);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Factorisation of one Gram matrix: pivoted Cholesky M ~ X X^* (stopped when
+// the remaining diagonal falls below tau), then one-sided Jacobi on X.
+// The columns of the rotated X are U Sigma: U = left singular vectors of the
+// block row, Sigma its singular values.  Output: sigma (descending, r values,
+// zeros past the factor), Q = first k columns of U (row-major r x k),
+// k = #{sigma > eps}.
+// ---------------------------------------------------------------------------
+constexpr int kEigLds = 9216;  // double2 elements of X (144 KiB)
+
+__device__ __forceinline__ double wave_sum(double v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* litems, double eps,
+                                                int max_sweeps, int32_t* status) {
+  extern __shared__ double2 X[];  // column-major r x pmax
+  __shared__ double d[kMaxR];
+  __shared__ int done[kMaxR];
+  __shared__ double bval[4];
+  __shared__ int bidx[4];
+  __shared__ int s_piv;
+  __shared__ double s_dmax;
+  __shared__ int s_p;
+  __shared__ int s_rot;
+  __shared__ double s_norm[kMaxR];
+  __shared__ int s_rank[kMaxR];
+
+  int32_t ii = litems[blockIdx.x];
+  ItemDev& it = items[ii];
+  int r = it.r;
+  int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double2* Mi = it.M;
+  if (r == 0) {
+    if (tid == 0) it.k = 0;
+    return;
+  }
+  int pmax = kEigLds / r;
+  if (pmax > r) pmax = r;
+  if (pmax & 1) --pmax;  // even number of columns for the pairing
+  if (pmax < 2) pmax = 2;
+
+  double dmax0 = 0.0;
+  for (int i = tid; i < r; i += 256) {
+    d[i] = Mi[i + (int64_t)i * r].x;
+    done[i] = 0;
+  }
+  __syncthreads();
+  for (int i = 0; i < r; ++i) dmax0 = fmax(dmax0, d[i]);
+  double tau = fmax(1e-4 * eps * eps / r, 64.0 * 2.220446049250313e-16 * dmax0);
+
+  // ---- pivoted Cholesky, left-looking ----
+  int p = 0;
+  for (int j = 0; j < pmax; ++j) {
+    // argmax of d over rows not yet pivoted
+    double bv = -1.0;
+    int bi = -1;
+    for (int i = tid; i < r; i += 256)
+      if (!done[i] && d[i] > bv) {
+        bv = d[i];
+        bi = i;
+      }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_xor(bv, o, 64);
+      int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi >= 0 && (bi < 0 || oi < bi))) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      bval[w] = bv;
+      bidx[w] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = bval[0];
+      int ix = bidx[0];
+      for (int q = 1; q < 4; ++q)
+        if (bval[q] > v || (bval[q] == v && bidx[q] >= 0 && (ix < 0 || bidx[q] < ix))) {
+          v = bval[q];
+          ix = bidx[q];
+        }
+      s_piv = ix;
+      s_dmax = v;
+    }
+    __syncthreads();
+    int piv = s_piv;
+    double dm = s_dmax;
+    if (piv < 0 || !(dm > tau)) break;
+    double sq = sqrt(dm), inv = 1.0 / sq;
+    for (int i = tid; i < r; i += 256) {
+      double2 v;
+      if (i == piv) {
+        v = make_double2(sq, 0.0);
+      } else if (done[i]) {
+        v = make_double2(0.0, 0.0);
+      } else {
+        double2 a = Mi[i + (int64_t)piv * r];
+        for (int q = 0; q < j; ++q) {
+          double2 x = X[q * r + i], y = X[q * r + piv];
+          // a -= x * conj(y)
+          a.x -= x.x * y.x + x.y * y.y;
+          a.y -= x.y * y.x - x.x * y.y;
+        }
+        v = make_double2(a.x * inv, a.y * inv);
+      }
+      X[j * r + i] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < r; i += 256) {
+      if (i == piv) {
+        done[i] = 1;
+        d[i] = 0.0;
+      } else if (!done[i]) {
+        double2 v = X[j * r + i];
+        d[i] = fmax(0.0, d[i] - (v.x * v.x + v.y * v.y));
+      }
+    }
+    __syncthreads();
+    p = j + 1;
+  }
+  if (tid == 0) {
+    s_p = p;
+    // remaining diagonal not captured by the factor
+    double rest = 0.0;
+    for (int i = 0; i < r; ++i)
+      if (!done[i]) rest += d[i];
+    if (p == pmax && rest > 0.1 * eps * eps) atomicMax(status, 1);
+  }
+  __syncthreads();
+  p = s_p;
+  int pe = p + (p & 1);
+  for (int i = tid; i < r; i += 256)
+    if (pe > p) X[p * r + i] = make_double2(0.0, 0.0);
+  __syncthreads();
+
+  // ---- one-sided Jacobi on the columns of X (r x pe) ----
+  int npair = pe / 2;
+  int g = 1;
+  while (g * 2 * npair <= 256 && g < 64) g *= 2;
+  int pair = tid / g, gl = tid % g;
+  int sweep = 0;
+  if (pe >= 2) {
+    for (sweep = 0; sweep < max_sweeps; ++sweep) {
+      if (tid == 0) s_rot = 0;
+      __syncthreads();
+      for (int step = 0; step < pe - 1; ++step) {
+        if (pair < npair) {
+          int pa = pair, pb = pe - 1 - pair;
+          int a = pa == 0 ? 0 : 1 + (pa - 1 + step) % (pe - 1);
+          int b = pb == 0 ? 0 : 1 + (pb - 1 + step) % (pe - 1);
+          double al = 0, be = 0, gr = 0, gi = 0;
+          for (int i = gl; i < r; i += g) {
+            double2 x = X[a * r + i], y = X[b * r + i];
+            al += x.x * x.x + x.y * x.y;
+            be += y.x * y.x + y.y * y.y;
+            gr += x.x * y.x + x.y * y.y;  // conj(x) * y
+            gi += x.x * y.y - x.y * y.x;
+          }
+          al = wave_sum(al, g);
+          be = wave_sum(be, g);
+          gr = wave_sum(gr, g);
+          gi = wave_sum(gi, g);
+          double ag = sqrt(gr * gr + gi * gi);
+          if (ag > 1e-15 * sqrt(al * be) && ag > 1e-300) {
+            double tz = (be - al) / (2.0 * ag);
+            double t = (tz >= 0 ? 1.0 : -1.0) / (fabs(tz) + sqrt(1.0 + tz * tz));
+            double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+            double er = gr / ag, ei = -gi / ag;  // e^{-i phi}
+            for (int i = gl; i < r; i += g) {
+              double2 x = X[a * r + i], y = X[b * r + i];
+              double2 ey = make_double2(er * y.x - ei * y.y, er * y.y + ei * y.x);
+              X[a * r + i] = make_double2(c * x.x - s * ey.x, c * x.y - s * ey.y);
+              X[b * r + i] = make_double2(s * x.x + c * ey.x, s * x.y + c * ey.y);
+            }
+            if (gl == 0) s_rot = 1;
+          }
+        }
+        __syncthreads();
+      }
+      int rot = s_rot;
+      __syncthreads();
+      if (!rot) break;
+    }
+    if (sweep == max_sweeps && tid == 0) atomicMax(status, 2);
+  }
+
+  // ---- singular values, ordering, rank ----
+  for (int q = tid; q < pe; q += 256) {
+    double s2 = 0;
+    for (int i = 0; i < r; ++i) {
+      double2 x = X[q * r + i];
+      s2 += x.x * x.x + x.y * x.y;
+    }
+    s_norm[q] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int q = tid; q < pe; q += 256) {
+    int rk = 0;
+    double v = s_norm[q];
+    for (int q2 = 0; q2 < pe; ++q2) {
+      double o = s_norm[q2];
+      if (o > v || (o == v && q2 < q)) ++rk;
+    }
+    s_rank[q] = rk;
+  }
+  __syncthreads();
+  int k = 0;
+  for (int q = 0; q < pe; ++q)
+    if (s_norm[q] > eps) ++k;
+  double* sg = it.sig;
+  for (int q = tid; q < r; q += 256) sg[q] = 0.0;
+  __syncthreads();
+  for (int q = tid; q < pe; q += 256) sg[s_rank[q]] = s_norm[q];
+  double2* Q = it.Q;  // row-major r x k
+  for (int e = tid; e < pe * r; e += 256) {
+    int q = e / r, i = e - q * r;
+    int rk = s_rank[q];
+    if (rk < k) {
+      double inv = 1.0 / s_norm[q];
+      double2 x = X[q * r + i];
+      Q[(int64_t)i * k + rk] = make_double2(x.x * inv, x.y * inv);
+    }
+  }
+  if (tid == 0) it.k = k;
+}
+
+// ---------------------------------------------------------------------------
+// R^T (N x k) of a block row: R_tc = Q^* A, i.e. R^T[j][kk] = sum_rho
+// A[rho][j] conj(Q[rho][kk]).  Output tiles (16 columns x 16 ranks) are split
+// over the waves.
+// ---------------------------------------------------------------------------
+template <int SRC, bool INNER>
+__global__ __launch_bounds__(256) void k_rprod(GeomDev g, const ItemDev* items, const EntDev* ents,
+                                               const UnitDev* units, double zeta, int side) {
+  __shared__ double2 T[kTileLds];
+  __shared__ int64_t cpos[kStageCols];
+  __shared__ double cscale[kStageCols];
+  const UnitDev u = units[blockIdx.x];
+  const ItemDev it = items[u.item];
+  int r = it.r, k = it.k;
+  if (k == 0) return;
+  int nt = (r + 15) / 16, rp = nt * 16, ld = rp + 1;
+  int kt = (k + 15) / 16;
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int row = lane & 15, kq = lane >> 4;
+  const double2* Q = it.Q;
+  double2* Ro = it.R;
+  int ntask = (kStageCols / 16) * kt;
+  for (int64_t c0 = 0; c0 < u.ncols; c0 += kStageCols) {
+    int64_t nc = u.ncols - c0 < kStageCols ? u.ncols - c0 : kStageCols;
+    __syncthreads();
+    if constexpr (INNER)
+      produce_inner(items, it, zeta, u.col_begin + c0, nc, rp, ld, T);
+    else
+      produce_leaf<SRC>(g, it, ents, side, u.col_begin + c0, nc, rp, ld, T, cpos, cscale);
+    __syncthreads();
+    for (int task = w; task < ntask; task += 4) {
+      int cg = task / kt, tk = task - cg * kt;
+      if (cg * 16 >= nc) continue;
+      dvec4 acr = {0, 0, 0, 0}, aci = {0, 0, 0, 0};
+      int kk = tk * 16 + row;
+      for (int i0 = 0; i0 < r; i0 += 4) {
+        int rho = i0 + kq;
+        double2 a = T[(cg * 16 + row) * ld + rho];
+        double2 q = (rho < r && kk < k) ? Q[(int64_t)rho * k + kk] : make_double2(0.0, 0.0);
+        // A^T conj(Q): re = ar qr + ai qi, im = ai qr - ar qi
+        acr = mfma_f64(a.x, q.x, acr);
+        acr = mfma_f64(a.y, q.y, acr);
+        aci = mfma_f64(a.y, q.x, aci);
+        aci = mfma_f64(-a.x, q.y, aci);
+      }
+      for (int v = 0; v < 4; ++v) {
+        int64_t jj = u.col_begin + c0 + cg * 16 + 4 * kq + v;
+        int64_t jl = c0 + cg * 16 + 4 * kq + v;
+        if (jl < u.ncols && kk < k) Ro[jj * k + kk] = make_double2(acr[v], aci[v]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Expansion of the column basis: dst rows = src (rows x ks) * E (ks x k).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_expand(const ExpandDev* tasks) {
+  const ExpandDev t = tasks[blockIdx.x];
+  int64_t tot = (int64_t)t.rows * t.k;
+  for (int64_t e = threadIdx.x; e < tot; e += 256) {
+    int64_t i = e / t.k;
+    int kk = (int)(e - i * t.k);
+    double2 s = make_double2(0.0, 0.0);
+    for (int q = 0; q < t.ks; ++q) {
+      double2 a = t.src[i * t.ks + q];
+      double2 b = t.E[(int64_t)q * t.k + kk];
+      s.x += a.x * b.x - a.y * b.y;
+      s.y += a.x * b.y + a.y * b.x;
+    }
+    t.dst[i * t.k + kk] = s;
+  }
+}
+
+// copy a leaf basis (row-major rows x k) into the expanded-basis arena
+__global__ void k_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
+                         int64_t count) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) dst[dst_off + e] = src[src_off + e];
+}
+
+// ---------------------------------------------------------------------------
+// Projection: S_b = omega_b * R_tc[o.. o+|s|)^T^T * Wexp_sc, one wave per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t ntasks,
+                                                 const double* omega) {
+  int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (ti >= ntasks) return;
+  const ProjDev t = tasks[ti];
+  int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  int kt = t.kt, ks = t.ks;
+  if (kt == 0 || ks == 0) return;
+  double om = omega[t.b];
+  int nti = (kt + 15) / 16, ntj = (ks + 15) / 16;
+  const double2* Rb = t.R;
+  const double2* Wb = t.W;
+  double2* Sb = t.S;
+  for (int ti16 = 0; ti16 < nti; ++ti16) {
+    dvec4 acr[8], aci[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      acr[q] = dvec4{0, 0, 0, 0};
+      aci[q] = dvec4{0, 0, 0, 0};
+    }
+    int ii = ti16 * 16 + row;
+    for (int j0 = 0; j0 < t.ns; j0 += 4) {
+      int j = j0 + kq;
+      double2 a = (j < t.ns && ii < kt) ? Rb[(int64_t)j * kt + ii] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q < ntj) {
+          int jj = q * 16 + row;
+          double2 b = (j < t.ns && jj < ks) ? Wb[(int64_t)j * ks + jj] : make_double2(0.0, 0.0);
+          // R W: re = ar br - ai bi, im = ar bi + ai br
+          acr[q] = mfma_f64(a.x, b.x, acr[q]);
+          acr[q] = mfma_f64(-a.y, b.y, acr[q]);
+          aci[q] = mfma_f64(a.x, b.y, aci[q]);
+          aci[q] = mfma_f64(a.y, b.x, aci[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < ntj) {
+        int jj = q * 16 + row;
+        for (int v = 0; v < 4; ++v) {
+          int i = ti16 * 16 + 4 * kq + v;
+          if (i < kt && jj < ks) Sb[i + (int64_t)jj * kt] = make_double2(om * acr[q][v], om * aci[q][v]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Near field: G|_b column-major per inadmissible block.
+// ---------------------------------------------------------------------------
+template <int SRC>
+__global__ __launch_bounds__(256) void k_near(GeomDev g, const int64_t* t_off, const int64_t* t_len,
+                                              const int64_t* s_off, const int64_t* s_len,
+                                              const int64_t* out_off, double2* out) {
+  int64_t b = blockIdx.x;
+  int64_t to = t_off[b], tl = t_len[b], so = s_off[b], sl = s_len[b];
+  double2* o = out + out_off[b];
+  for (int64_t e = threadIdx.x; e < tl * sl; e += 256) {
+    int64_t j = e / tl, i = e - j * tl;
+    o[e] = entry<SRC>(g, to + i, so + j, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-vector product kernels (verification path, VALU).
+// ---------------------------------------------------------------------------
+__global__ void k_gather_perm(const double2* x, const int64_t* perm, int64_t n, double2* xp) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) xp[p] = x[perm[p]];
+}
+__global__ void k_scatter_perm(const double2* yp, const int64_t* perm, int64_t n, double2* y) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) y[perm[p]] = yp[p];
+}
+
+// forward, leaf items: xh = Q^* x|t
+__global__ __launch_bounds__(128) void k_fwd_leaf(const ItemDev* items, const int32_t* litems,
+                                                  const int64_t* xh_off, const double2* xp,
+                                                  double2* xh) {
+  int32_t i = litems[blockIdx.x];
+  const ItemDev& it = items[i];
+  int k = it.k;
+  for (int kk = threadIdx.x; kk < k; kk += blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int j = 0; j < it.m; ++j) {
+      double2 v = cmulc(it.Q[(int64_t)j * k + kk], xp[it.row_off + j]);
+      s.x += v.x;
+      s.y += v.y;
+    }
+    xh[xh_off[i] + kk] = s;
+  }
+}
+
+// forward, non-leaf items: xh_tc = Q_hat^* [xh_t1c'; xh_t2c']
+__global__ __launch_bounds__(128) void k_fwd_inner(const ItemDev* items, const int32_t* litems,
+                                                   const int64_t* xh_off, double2* xh) {
+  int32_t i = litems[blockIdx.x];
+  const ItemDev& it = items[i];
+  int k = it.k;
+  const ItemDev& s1 = items[it.son[0]];
+  for (int kk = threadIdx.x; kk < k; kk += blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int rho = 0; rho < it.r; ++rho) {
+      double2 z = rho < s1.k ? xh[xh_off[it.son[0]] + rho] : xh[xh_off[it.son[1]] + rho - s1.k];
+      double2 v = cmulc(it.Q[(int64_t)rho * k + kk], z);
+      s.x += v.x;
+      s.y += v.y;
+    }
+    xh[xh_off[i] + kk] = s;
+  }
+}
+
+// coupling: yh_i = sum over the item's blocks of S_b xh_partner (or S_b^* for
+// the adjoint, where S_b is kr x kc with the item on the column side)
+__global__ __launch_bounds__(128) void k_coupling(const ItemDev* items, int32_t nitems,
+                                                  const int64_t* cbegin, const int32_t* cblock,
+                                                  const int32_t* cpartner,
+                                                  const double2* const* S_ptr,
+                                                  const int32_t* S_rows, const int32_t* S_cols,
+                                                  const int64_t* xh_off, const double2* xh,
+                                                  const int64_t* yh_off, double2* yh,
+                                                  int adjoint) {
+  int32_t i = blockIdx.x;
+  if (i >= nitems) return;
+  int k = items[i].k;
+  for (int kk = threadIdx.x; kk < k; kk += blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int64_t q = cbegin[i]; q < cbegin[i + 1]; ++q) {
+      int32_t b = cblock[q];
+      const double2* Sb = S_ptr[b];
+      int kr = S_rows[b], kc = S_cols[b];
+      const double2* x = xh + xh_off[cpartner[q]];
+      if (!adjoint) {
+        for (int jj = 0; jj < kc; ++jj) {
+          double2 v = cmul(Sb[kk + (int64_t)jj * kr], x[jj]);
+          s.x += v.x;
+          s.y += v.y;
+        }
+      } else {
+        for (int jj = 0; jj < kr; ++jj) {
+          double2 v = cmulc(Sb[jj + (int64_t)kk * kr], x[jj]);
+          s.x += v.x;
+          s.y += v.y;
+        }
+      }
+    }
+    yh[yh_off[i] + kk] = s;
+  }
+}
+
+// backward to the sons: yh_{t'c'} += sum over father items (fa,c+) with
+// sd(c+) = c' of E_{t'c+} yh_{fa c+}; E_{t'c+} = rows of the father's factor.
+__global__ __launch_bounds__(128) void k_bwd_inner(const ItemDev* items, const int32_t* litems,
+                                                   const int64_t* fbegin, const int32_t* fitem,
+                                                   const int32_t* fsonidx, const int64_t* yh_off,
+                                                   double2* yh) {
+  int32_t i = litems[blockIdx.x];
+  const ItemDev& it = items[i];
+  int k = it.k;
+  for (int kk = threadIdx.x; kk < k; kk += blockDim.x) {
+    double2 s = yh[yh_off[i] + kk];
+    for (int64_t q = fbegin[blockIdx.x]; q < fbegin[blockIdx.x + 1]; ++q) {
+      const ItemDev& fa = items[fitem[q]];
+      int rowoff = fsonidx[q] == 0 ? 0 : items[fa.son[0]].k;
+      const double2* y = yh + yh_off[fitem[q]];
+      for (int jj = 0; jj < fa.k; ++jj) {
+        double2 v = cmul(fa.Q[(int64_t)(rowoff + kk) * fa.k + jj], y[jj]);
+        s.x += v.x;
+        s.y += v.y;
+      }
+    }
+    yh[yh_off[i] + kk] = s;
+  }
+}
+
+// leaf rows: y|L = sum_c Q_Lc yh_Lc + near-field rows of L
+__global__ __launch_bounds__(128) void k_bwd_leaf(const ItemDev* items, const LeafDev* leaves,
+                                                  const NearRefDev* nref, const NearDev* nears,
+                                                  const double2* nearv, const int64_t* yh_off,
+                                                  const double2* yh, const double2* xp,
+                                                  double2* yp, int adjoint) {
+  const LeafDev L = leaves[blockIdx.x];
+  for (int j = threadIdx.x; j < L.len; j += blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int q = L.item_first; q < L.item_first + L.item_count; ++q) {
+      const ItemDev& it = items[q];
+      for (int kk = 0; kk < it.k; ++kk) {
+        double2 v = cmul(it.Q[(int64_t)j * it.k + kk], yh[yh_off[q] + kk]);
+        s.x += v.x;
+        s.y += v.y;
+      }
+    }
+    for (int64_t q = L.near_begin; q < L.near_end; ++q) {
+      const NearRefDev ref = nref[q];
+      const NearDev nb = nears[ref.b];
+      int64_t row = ref.row0 + j;  // row of the block (column for the adjoint)
+      const double2* B = nearv + nb.off;
+      if (!adjoint) {
+        for (int64_t c = 0; c < nb.s_len; ++c) {
+          double2 v = cmul(B[row + c * nb.t_len], xp[nb.s_off + c]);
+          s.x += v.x;
+          s.y += v.y;
+        }
+      } else {
+        for (int64_t c = 0; c < nb.t_len; ++c) {
+          double2 v = cmulc(B[c + row * nb.t_len], xp[nb.t_off + c]);
+          s.x += v.x;
+          s.y += v.y;
+        }
+      }
+    }
+    yp[L.row_off + j] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Direct products with the matrix (FP64): y_i = sum_j G_ij x_j (op 'N') or
+// y_i = sum_j conj(G_ji) x_j (op 'C'); rows are permuted positions.
+// ---------------------------------------------------------------------------
+template <int SRC>
+__global__ __launch_bounds__(256) void k_direct(GeomDev g, const int64_t* rows, int64_t nrows,
+                                                const double2* xp, int adjoint, double2* out) {
+  __shared__ double2 red[256];
+  int64_t q = blockIdx.x;
+  if (q >= nrows) return;
+  int64_t i = rows ? rows[q] : q;
+  double2 s = make_double2(0.0, 0.0);
+  for (int64_t j = threadIdx.x; j < g.n; j += 256) {
+    double2 e = adjoint ? entry<SRC>(g, i, j, 1) : entry<SRC>(g, i, j, 0);
+    double2 v = cmul(e, xp[j]);
+    s.x += v.x;
+    s.y += v.y;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[threadIdx.x].x += red[threadIdx.x + o].x;
+      red[threadIdx.x].y += red[threadIdx.x + o].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_block_norm(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
+                       const int64_t* s_off, const int64_t* s_len, int64_t nblocks, double* omega,
+                       hipStream_t st) {
+  if (nblocks == 0) return;
+  if (src == SRC_HELMHOLTZ)
+    hipLaunchKernelGGL(k_block_norm<SRC_HELMHOLTZ>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
+                       t_off, t_len, s_off, s_len, nblocks, omega);
+  else
+    hipLaunchKernelGGL(k_block_norm<SRC_DENSE>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
+                       t_off, t_len, s_off, s_len, nblocks, omega);
+}
+
+void launch_entry_scale(EntDev* ent, int64_t nent, const double* omega, double zeta,
+                        hipStream_t st) {
+  if (nent == 0) return;
+  hipLaunchKernelGGL(k_entry_scale, dim3(blocks_for(nent, 256)), dim3(256), 0, st, ent, nent,
+                     omega, zeta);
+}
+
+void launch_gram(int src, bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
+                 const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
+                 hipStream_t st) {
+  if (nunits == 0) return;
+  dim3 grid((unsigned)nunits), blk(256);
+  if (inner)
+    hipLaunchKernelGGL((k_gram<SRC_HELMHOLTZ, true>), grid, blk, 0, st, g, items, ents, units,
+                       zeta, side, partial);
+  else if (src == SRC_HELMHOLTZ)
+    hipLaunchKernelGGL((k_gram<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents, units,
+                       zeta, side, partial);
+  else
+    hipLaunchKernelGGL((k_gram<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents, units, zeta,
+                       side, partial);
+}
+
+void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
+                        const int32_t* ubegin, const UnitDev* units, const double2* partial,
+                        hipStream_t st) {
+  if (nl == 0) return;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(nl), dim3(256), 0, st, items, litems, ubegin, units,
+                     partial);
+}
+
+void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, double eps, int max_sweeps,
+                   int32_t* status, hipStream_t st) {
+  if (nl == 0) return;
+  static bool attr_set = false;
+  size_t lds = (size_t)kEigLds * sizeof(double2);
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_factor, dim3(nl), dim3(256), lds, st, items, litems, eps, max_sweeps,
+                     status);
+}
+
+void launch_rprod(int src, bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
+                  const UnitDev* units, int64_t nunits, double zeta, int side, hipStream_t st) {
+  if (nunits == 0) return;
+  dim3 grid((unsigned)nunits), blk(256);
+  if (inner)
+    hipLaunchKernelGGL((k_rprod<SRC_HELMHOLTZ, true>), grid, blk, 0, st, g, items, ents, units,
+                       zeta, side);
+  else if (src == SRC_HELMHOLTZ)
+    hipLaunchKernelGGL((k_rprod<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents, units,
+                       zeta, side);
+  else
+    hipLaunchKernelGGL((k_rprod<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents, units, zeta,
+                       side);
+}
+
+void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st) {
+  if (ntasks == 0) return;
+  hipLaunchKernelGGL(k_expand, dim3((unsigned)ntasks), dim3(256), 0, st, tasks);
+}
+
+void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
+                   int64_t count, hipStream_t st) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_copy_c, dim3(blocks_for(count, 256)), dim3(256), 0, st, src, src_off, dst,
+                     dst_off, count);
+}
+
+void launch_project(const ProjDev* tasks, int64_t ntasks, const double* omega, hipStream_t st) {
+  if (ntasks == 0) return;
+  hipLaunchKernelGGL(k_project, dim3(blocks_for(ntasks, 4)), dim3(256), 0, st, tasks, ntasks,
+                     omega);
+}
+
+void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
+                 const int64_t* s_off, const int64_t* s_len, const int64_t* out_off,
+                 int64_t nblocks, double2* out, hipStream_t st) {
+  if (nblocks == 0) return;
+  if (src == SRC_HELMHOLTZ)
+    hipLaunchKernelGGL(k_near<SRC_HELMHOLTZ>, dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
+                       t_len, s_off, s_len, out_off, out);
+  else
+    hipLaunchKernelGGL(k_near<SRC_DENSE>, dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
+                       t_len, s_off, s_len, out_off, out);
+}
+
+void launch_gather_perm(const double2* x, const int64_t* perm, int64_t n, double2* xp,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, perm, n, xp);
+}
+void launch_scatter_perm(const double2* yp, const int64_t* perm, int64_t n, double2* y,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_perm, dim3(blocks_for(n, 256)), dim3(256), 0, st, yp, perm, n, y);
+}
+void launch_fwd_leaf(const ItemDev* items, const int32_t* litems, int32_t nl,
+                     const int64_t* xh_off, const double2* xp, double2* xh, hipStream_t st) {
+  if (nl == 0) return;
+  hipLaunchKernelGGL(k_fwd_leaf, dim3(nl), dim3(128), 0, st, items, litems, xh_off, xp, xh);
+}
+void launch_fwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
+                      const int64_t* xh_off, double2* xh, hipStream_t st) {
+  if (nl == 0) return;
+  hipLaunchKernelGGL(k_fwd_inner, dim3(nl), dim3(128), 0, st, items, litems, xh_off, xh);
+}
+void launch_coupling(const ItemDev* items, int32_t nitems, const int64_t* cbegin,
+                     const int32_t* cblock, const int32_t* cpartner, const double2* const* S_ptr,
+                     const int32_t* S_rows, const int32_t* S_cols, const int64_t* xh_off,
+                     const double2* xh, const int64_t* yh_off, double2* yh, int adjoint,
+                     hipStream_t st) {
+  if (nitems == 0) return;
+  hipLaunchKernelGGL(k_coupling, dim3(nitems), dim3(128), 0, st, items, nitems, cbegin, cblock,
+                     cpartner, S_ptr, S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint);
+}
+void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
+                      const int64_t* fbegin, const int32_t* fitem, const int32_t* fsonidx,
+                      const int64_t* yh_off, double2* yh, hipStream_t st) {
+  if (nl == 0) return;
+  hipLaunchKernelGGL(k_bwd_inner, dim3(nl), dim3(128), 0, st, items, litems, fbegin, fitem,
+                     fsonidx, yh_off, yh);
+}
+void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleaves,
+                     const NearRefDev* nref, const NearDev* nears, const double2* nearv,
+                     const int64_t* yh_off, const double2* yh, const double2* xp, double2* yp,
+                     int adjoint, hipStream_t st) {
+  if (nleaves == 0) return;
+  hipLaunchKernelGGL(k_bwd_leaf, dim3(nleaves), dim3(128), 0, st, items, leaves, nref, nears,
+                     nearv, yh_off, yh, xp, yp, adjoint);
+}
+void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
+                   const double2* xp, int adjoint, double2* out, hipStream_t st) {
+  if (nrows == 0) return;
+  if (src == SRC_HELMHOLTZ)
+    hipLaunchKernelGGL(k_direct<SRC_HELMHOLTZ>, dim3((unsigned)nrows), dim3(256), 0, st, g, rows,
+                       nrows, xp, adjoint, out);
+  else
+    hipLaunchKernelGGL(k_direct<SRC_DENSE>, dim3((unsigned)nrows), dim3(256), 0, st, g, rows,
+                       nrows, xp, adjoint, out);
+}
+
+}  // namespace dh2

@@ -1,0 +1,55 @@
+// Launchers of the gfx950 kernels (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace dh2 {
+
+void launch_block_norm(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
+                       const int64_t* s_off, const int64_t* s_len, int64_t nblocks, double* omega,
+                       hipStream_t st);
+void launch_entry_scale(EntDev* ent, int64_t nent, const double* omega, double zeta,
+                        hipStream_t st);
+void launch_gram(int src, bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
+                 const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
+                 hipStream_t st);
+void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
+                        const int32_t* ubegin, const UnitDev* units, const double2* partial,
+                        hipStream_t st);
+void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, double eps, int max_sweeps,
+                   int32_t* status, hipStream_t st);
+void launch_rprod(int src, bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
+                  const UnitDev* units, int64_t nunits, double zeta, int side, hipStream_t st);
+void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st);
+void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
+                   int64_t count, hipStream_t st);
+void launch_project(const ProjDev* tasks, int64_t ntasks, const double* omega, hipStream_t st);
+void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
+                 const int64_t* s_off, const int64_t* s_len, const int64_t* out_off,
+                 int64_t nblocks, double2* out, hipStream_t st);
+void launch_gather_perm(const double2* x, const int64_t* perm, int64_t n, double2* xp,
+                        hipStream_t st);
+void launch_scatter_perm(const double2* yp, const int64_t* perm, int64_t n, double2* y,
+                         hipStream_t st);
+void launch_fwd_leaf(const ItemDev* items, const int32_t* litems, int32_t nl,
+                     const int64_t* xh_off, const double2* xp, double2* xh, hipStream_t st);
+void launch_fwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
+                      const int64_t* xh_off, double2* xh, hipStream_t st);
+void launch_coupling(const ItemDev* items, int32_t nitems, const int64_t* cbegin,
+                     const int32_t* cblock, const int32_t* cpartner, const double2* const* S_ptr,
+                     const int32_t* S_rows, const int32_t* S_cols, const int64_t* xh_off,
+                     const double2* xh, const int64_t* yh_off, double2* yh, int adjoint,
+                     hipStream_t st);
+void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
+                      const int64_t* fbegin, const int32_t* fitem, const int32_t* fsonidx,
+                      const int64_t* yh_off, double2* yh, hipStream_t st);
+void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleaves,
+                     const NearRefDev* nref, const NearDev* nears, const double2* nearv,
+                     const int64_t* yh_off, const double2* yh, const double2* xp, double2* yp,
+                     int adjoint, hipStream_t st);
+void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
+                   const double2* xp, int adjoint, double2* out, hipStream_t st);
+
+}  // namespace dh2
