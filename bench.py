@@ -1,0 +1,190 @@
+"""Benchmark: directional H2 compression on one MI355X.
+
+A step is one full compression (both bases, transfer matrices, projection of
+every admissible block, near field) of a synthetic workload whose points are
+already on the device side of the call.  The default workload is the
+131072-point golden-spiral sphere, kappa = 64, leaf size 64, eps = 1e-4,
+eta1 = 20, eta2 = 5, entries generated on the fly.
+
+Prints ONE JSON line (the contract in the repository's README of the driver):
+metric/value/unit, roofline of the dominant kernel (the Gram kernel), and the
+CPU baseline (the FP64 oracle on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "compression s & GFLOP/s, mixed vs FP64 form at equal eps, n=131072 kappa=64"
+PEAK_FP64_MFMA = 78.6e12  # MI355X dense FP64 matrix peak (FLOP/s)
+PEAK_FP32_MFMA = 157.3e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(dh2, torch, blocks, w, eps, leaf, form, steps, warmup, groups):
+    prec = dh2.FP64 if form == "fp64" else dh2.MIXED
+    o = dh2.opts(leaf_size=leaf, precision=prec, groups=groups)
+    times, st, m = [], None, None
+    for it in range(warmup + steps):
+        m = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m = dh2.compress_helmholtz(blocks, w, eps, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = dh2.stats(m)
+        log(f"[bench] {form} step {it} {'warmup' if it < warmup else 'timed'}: {dt:.3f} s "
+            f"(device {st['t_total']:.3f} s, gram {st['t_gram_kernel']:.3f} s, "
+            f"k_max {st['k_max']}, groups {st['groups']})")
+        if it >= warmup:
+            times.append(dt)
+    return m, st, times
+
+
+def cpu_baseline(points, w, kappa, leaf, eps, budget_s):
+    """The oracle on a bounded sample: leaf block rows of the row basis, in a
+    seeded random order, each with its block weights, weighted block row,
+    SVD and R product, until the time budget is used."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import compress as OC
+    from oracle import matrix as OM
+    from oracle import plan as OP
+
+    t_plan = time.perf_counter()
+    plan = OP.build_plan(points, kappa, leaf)
+    t_plan = time.perf_counter() - t_plan
+    M = OM.HelmholtzMatrix(points, w, kappa, plan.tree.perm)
+    tr, bt = plan.tree, plan.blocks
+    items = [(t, c) for t in range(tr.nc) if tr.son1[t] < 0 for c in plan.rowsets.used(t)]
+    order = np.random.default_rng(0).permutation(len(items))
+    omega = {}
+    flops, done = 0.0, 0
+    t0 = time.perf_counter()
+    for idx in order:
+        t, c = items[idx]
+        for (b, s, d) in plan.rowsets.F[t][c]:
+            if b not in omega:
+                omega[b] = np.linalg.norm(M.block(tr.rows(bt.adm_t[b]), tr.rows(bt.adm_s[b])))
+        A = OC.weighted_block_row(M, plan, plan.rowsets, t, c, omega, 2.0 / 3.0)
+        Q, sig, k = OC.truncated_left_singular(A, eps)
+        _ = Q.conj().T @ A
+        r, N = A.shape
+        flops += 4.0 * r * r * N + 8.0 * k * r * N
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} of {len(items)} leaf block rows of the row basis "
+                      f"(weights, weighted block row, SVD, R product) in {el:.1f} s; "
+                      f"oracle plan {t_plan:.1f} s not timed",
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sphere131072")
+    ap.add_argument("--forms", default="fp64")
+    ap.add_argument("--groups", type=int, default=0)
+    ap.add_argument("--err-iters", type=int, default=8)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1510_07087_amd import dh2
+
+    dh2.lib()
+    torch.cuda.set_device(0)
+    p, w, kappa, leaf, eps = synth.workload(args.workload)
+    n = len(p)
+    log(f"[bench] workload {args.workload}: n={n} kappa={kappa} leaf={leaf} eps={eps}")
+    o = dh2.opts(leaf_size=leaf)
+    t0 = time.perf_counter()
+    tree = dh2.tree_build(p, kappa, o)
+    blocks = dh2.blocks_build(tree, o)
+    t_plan = time.perf_counter() - t0
+    binfo = dh2.blocks_info(blocks)
+    log(f"[bench] host plan {t_plan:.2f} s: {binfo}")
+
+    forms = [f for f in args.forms.split(",") if f]
+    res = {}
+    for form in forms:
+        m, st, times = run_form(dh2, torch, blocks, w, eps, leaf, form, args.steps, args.warmup,
+                                args.groups)
+        rows = np.random.default_rng(5).choice(n, 16, replace=False)
+        x = torch.from_numpy(synth.complex_gaussian(n, 6)).to("cuda")
+        _, _, rows_rel = dh2.rows_check(m, rows, x)
+        err = dh2.error_estimate(m, None, iters=args.err_iters, seed=1) if args.err_iters > 0 \
+            else None
+        s = float(np.median(times))
+        flops = st["flops_row"] + st["flops_col"] + st["flops_prj"]
+        res[form] = dict(s=s, gflops=flops / s / 1e9, stats=st, rows_rel=rows_rel, rel_err=err)
+        log(f"[bench] {form}: {s:.3f} s, {flops / s / 1e9:.1f} GFLOP/s, rows {rows_rel:.2e}, "
+            f"err {err}")
+        del m
+    head = "mixed" if "mixed" in res else forms[0]
+    r = res[head]
+    st = r["stats"]
+    peak = PEAK_FP64_MFMA
+    achieved = st["flops_gram"] / st["t_gram_kernel"] if st["t_gram_kernel"] > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": r["gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "kappa": kappa, "leaf_size": leaf,
+                   "eps": eps, "eta1": 20.0, "eta2": 5.0, "zeta": 2.0 / 3.0, "form": head,
+                   "entries": "generated on the fly"},
+        "roofline": {"bound": "mfma", "kernel": "k_gram (FP64 MFMA Gram of block rows)",
+                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None},
+        "compression_s": {f: res[f]["s"] for f in res},
+        "gflops": {f: res[f]["gflops"] for f in res},
+        "rel_err_2": {f: res[f]["rel_err"] for f in res},
+        "rows_check_max_rel": {f: res[f]["rows_rel"] for f in res},
+        "phases_s": {f: {k: res[f]["stats"][k] for k in ("t_row", "t_col", "t_prj", "t_near")}
+                     for f in res},
+        "k_max": st["k_max"],
+        "mem_per_n_kib": st["mem_per_n_kib"],
+        "host_plan_s": t_plan,
+    }
+    if "mixed" in res and "fp64" in res:
+        out["speedup_mixed_vs_fp64"] = res["fp64"]["s"] / res["mixed"]["s"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, w, kappa, leaf, eps, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -26,6 +26,11 @@ __device__ __forceinline__ dvec4 mfma_f64(double a, double b, dvec4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Output layout of the FP64 16x16x4 MFMA (measured on gfx950): accumulator
+// register v of lane l holds row (l / 16) + 4 v, column l % 16.  Operand A
+// (16 x 4): lane l holds A[l % 16][l / 16]; operand B (4 x 16): B[l / 16][l % 16].
+__device__ __forceinline__ int f64_row(int lane, int v) { return (lane >> 4) + 4 * v; }
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const ItemDev* items, const
     int p = e >> 8, v = (e >> 6) & 3, lane = e & 63;
     int I, J;
     pair_ij(p, I, J);
-    int row = 16 * I + 4 * (lane >> 4) + v, col = 16 * J + (lane & 15);
+    int row = 16 * I + f64_row(lane, v), col = 16 * J + (lane & 15);
     if (row < r && col < r) {
       if (I != J || row >= col) {
         Mi[row + (int64_t)col * r] = s;
@@ -421,10 +426,10 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
     if (tid == 0) it.k = 0;
     return;
   }
-  int pmax = kEigLds / r;
-  if (pmax > r) pmax = r;
-  if (pmax & 1) --pmax;  // even number of columns for the pairing
-  if (pmax < 2) pmax = 2;
+  // X holds ncap columns; the pairing needs an even column count pe <= ncap
+  int ncap = kEigLds / r;
+  int pmax = r < ncap ? r : ncap;
+  if ((pmax & 1) && pmax + 1 > ncap) --pmax;
 
   double dmax0 = 0.0;
   for (int i = tid; i < r; i += 256) {
@@ -598,7 +603,8 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
   double* sg = it.sig;
   for (int q = tid; q < r; q += 256) sg[q] = 0.0;
   __syncthreads();
-  for (int q = tid; q < pe; q += 256) sg[s_rank[q]] = s_norm[q];
+  for (int q = tid; q < pe; q += 256)
+    if (s_rank[q] < r) sg[s_rank[q]] = s_norm[q];  // the zero pad column may rank r
   double2* Q = it.Q;  // row-major r x k
   for (int e = tid; e < pe * r; e += 256) {
     int q = e / r, i = e - q * r;
@@ -658,8 +664,8 @@ __global__ __launch_bounds__(256) void k_rprod(GeomDev g, const ItemDev* items, 
         aci = mfma_f64(-a.x, q.y, aci);
       }
       for (int v = 0; v < 4; ++v) {
-        int64_t jj = u.col_begin + c0 + cg * 16 + 4 * kq + v;
-        int64_t jl = c0 + cg * 16 + 4 * kq + v;
+        int64_t jj = u.col_begin + c0 + cg * 16 + f64_row(lane, v);
+        int64_t jl = c0 + cg * 16 + f64_row(lane, v);
         if (jl < u.ncols && kk < k) Ro[jj * k + kk] = make_double2(acr[v], aci[v]);
       }
     }
@@ -738,7 +744,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
       if (q < ntj) {
         int jj = q * 16 + row;
         for (int v = 0; v < 4; ++v) {
-          int i = ti16 * 16 + 4 * kq + v;
+          int i = ti16 * 16 + f64_row(lane, v);
           if (i < kt && jj < ks) Sb[i + (int64_t)jj * kt] = make_double2(om * acr[q][v], om * aci[q][v]);
         }
       }
