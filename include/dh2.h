@@ -190,6 +190,13 @@ dh2_status dh2_compress_helmholtz(dh2_blocks blocks, const double* w, double eps
                                   dh2_matrix* out);
 void dh2_matrix_free(dh2_matrix m);
 
+/* Device memory freed by the library (matrices freed, per-level work arrays)
+ * is kept in a process-wide cache, up to half of the device memory, and reused
+ * by later calls: handing touched memory back to the driver costs about
+ * 10-20 ms per gigabyte.  This call returns the whole cache to the driver.
+ * Do not call it while another thread is inside a dh2 call.                */
+void dh2_release_cached_memory(void);
+
 /* ---------------------------------------------------------------------------
  * Matrix-vector product with the compressed matrix (Section 4: forward
  * transformation, coupling, backward transformation, near field).

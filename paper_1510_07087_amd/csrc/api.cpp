@@ -250,6 +250,8 @@ dh2_status dh2_compress_helmholtz(dh2_blocks b, const double* w, double eps, con
 
 void dh2_matrix_free(dh2_matrix m) { delete m; }
 
+void dh2_release_cached_memory(void) { release_cached_memory(); }
+
 dh2_status dh2_matvec(dh2_matrix m, char op, int64_t nrhs, const void* x, void* y, void* stream) {
   DH2_TRY({
     if (!m || !x || !y) fail(DH2_EINVAL, "NULL argument");

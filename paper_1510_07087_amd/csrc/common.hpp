@@ -54,7 +54,8 @@ struct EntDev {
 // A contiguous column range of one block row, processed by one workgroup.
 struct UnitDev {
   int32_t item;
-  int32_t pad;
+  int16_t pair_begin; // Gram units of non-leaf items: tile pairs [pair_begin, +pair_count)
+  int16_t pair_count;
   int64_t col_begin;
   int64_t ncols;
   int64_t slot_off;   // partial-Gram slot offset in complex elements (Gram units)

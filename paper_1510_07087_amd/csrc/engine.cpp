@@ -15,9 +15,13 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <random>
 #include <unordered_map>
@@ -38,24 +42,131 @@ void hip_check(hipError_t e, const char* what) {
 
 static void launch_check(const char* what) { hip_check(hipGetLastError(), what); }
 
+// Optional host-side phase tracing (environment DH2_TRACE=1), to stderr.
+static bool trace_on() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = std::getenv("DH2_TRACE");
+    on = (e && e[0] == '1') ? 1 : 0;
+  }
+  return on == 1;
+}
+struct Trace {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  std::chrono::steady_clock::time_point last = t0;
+  void mark(const char* what, int side, int b, int lv) {
+    if (!trace_on()) return;
+    auto now = std::chrono::steady_clock::now();
+    double d = std::chrono::duration<double, std::milli>(now - last).count();
+    double tot = std::chrono::duration<double, std::milli>(now - t0).count();
+    std::fprintf(stderr, "[dh2 trace] side %d batch %d level %d %-14s %9.2f ms (t=%9.1f)\n", side, b,
+                 lv, what, d, tot);
+    last = now;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // device memory
 // ---------------------------------------------------------------------------
+// Freed device blocks are kept in a process-wide cache and handed out again
+// for requests of a similar size: returning touched memory to the driver is
+// expensive (hundreds of milliseconds for tens of gigabytes), and the sweep
+// allocates and frees one arena of coefficient matrices per level.
+namespace {
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+size_t g_cached = 0;
+
+size_t size_class(size_t b) {
+  if (b < 4096) return (b + 255) & ~size_t(255);
+  size_t top = size_t(1) << (63 - __builtin_clzll((unsigned long long)b));
+  size_t gran = top / 16;  // at most 6.25 % rounding
+  return (b + gran - 1) / gran * gran;
+}
+
+size_t cache_limit() {
+  static size_t lim = 0;
+  if (lim == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      tot = size_t(64) << 30;
+    }
+    lim = tot / 2;
+  }
+  return lim;
+}
+
+void trim_cache_locked(size_t keep) {
+  while (g_cached > keep && !g_cache.empty()) {
+    size_t big = 0;
+    for (size_t i = 1; i < g_cache.size(); ++i)
+      if (g_cache[i].bytes > g_cache[big].bytes) big = i;
+    (void)hipFree(g_cache[big].p);
+    g_cached -= g_cache[big].bytes;
+    g_cache[big] = g_cache.back();
+    g_cache.pop_back();
+  }
+}
+}  // namespace
+
+void release_cached_memory() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  trim_cache_locked(0);
+}
+
 DevMem::~DevMem() {
-  for (auto& pr : live_) (void)hipFree(pr.first);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& pr : live_) {
+    g_cache.push_back({pr.first, pr.second});
+    g_cached += pr.second;
+  }
+  live_.clear();
+  trim_cache_locked(cache_limit());
 }
 
 void* DevMem::alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
-  bytes = (bytes + 255) & ~size_t(255);
+  bytes = size_class(bytes);
   if (cap_ > 0 && used_ + (int64_t)bytes > cap_)
     fail(DH2_ENOMEM, "device memory cap exceeded (" + std::to_string(used_ + bytes) + " > " +
                          std::to_string(cap_) + " bytes)");
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    fail(DH2_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    size_t best = g_cache.size();
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+      size_t cb = g_cache[i].bytes;
+      if (cb >= bytes && cb <= bytes + bytes / 4 &&
+          (best == g_cache.size() || cb < g_cache[best].bytes))
+        best = i;
+    }
+    if (best < g_cache.size()) {
+      p = g_cache[best].p;
+      bytes = g_cache[best].bytes;
+      g_cached -= bytes;
+      g_cache[best] = g_cache.back();
+      g_cache.pop_back();
+    }
+  }
+  if (!p) {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        trim_cache_locked(0);
+      }
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(DH2_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      }
+    }
   }
   live_.push_back({p, bytes});
   used_ += (int64_t)bytes;
@@ -65,12 +176,15 @@ void* DevMem::alloc(size_t bytes) {
 
 void DevMem::release(void* p) {
   if (!p) return;
-  for (size_t i = 0; i < live_.size(); ++i) {
+  for (size_t i = live_.size(); i-- > 0;) {
     if (live_[i].first == p) {
-      (void)hipFree(p);
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      g_cache.push_back({p, live_[i].second});
+      g_cached += live_[i].second;
       used_ -= (int64_t)live_[i].second;
       live_[i] = live_.back();
       live_.pop_back();
+      trim_cache_locked(cache_limit());
       return;
     }
   }
@@ -331,12 +445,14 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
   double2* partial = nullptr;
   size_t partial_cap = 0;
 
+  Trace tr_;
   for (int32_t b = 0; b < M.nbatch; ++b) {
     void* R_prev = nullptr;
     for (int32_t lv = tr.depth; lv >= 0; --lv) {
       auto [lo, hi] = S.range[b][lv];
       if (lo == hi) continue;
       int32_t n = hi - lo;
+      tr_.mark("level start", s, b, lv);
       // factor sizes of non-leaf items from the sons' ranks
       int64_t sum_r2 = 0, sum_r = 0;
       for (int32_t i = lo; i < hi; ++i) {
@@ -366,11 +482,13 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         }
       }
       copy_to(S.d_items + lo, S.items.data() + lo, n, st);
+      tr_.mark("arenas", s, b, lv);
       // Gram units: leaf items first, then non-leaf items
       int64_t totalN = 0;
       for (int32_t i = lo; i < hi; ++i) totalN += S.items[i].N;
-      int64_t width = std::max<int64_t>(512, std::min<int64_t>(8192, totalN / 4096));
-      width = (width + 31) / 32 * 32;
+      // one Gram unit per wave: aim for about 8 waves of work per SIMD
+      int64_t width = std::max<int64_t>(256, std::min<int64_t>(2048, totalN / 8192));
+      width = (width + 63) / 64 * 64;
       std::vector<UnitDev> units;
       std::vector<int32_t> litems, ubegin;
       int64_t slot = 0, nleafu = 0;
@@ -381,16 +499,24 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           litems.push_back(i);
           ubegin.push_back((int32_t)units.size());
           if (it.r == 0) continue;
+          if (it.leaf && it.m > 64)
+            fail(DH2_EUNSUPPORTED, "leaf clusters with more than 64 points are not supported");
+          int64_t np = npairs_of(it.r);
           for (int64_t c0 = 0; c0 < it.N; c0 += width) {
-            UnitDev u{};
-            u.item = i;
-            u.col_begin = c0;
-            u.ncols = std::min(width, it.N - c0);
-            u.slot_off = slot;
-            slot += npairs_of(it.r) * 256;
-            units.push_back(u);
+            // non-leaf rows: at most 10 tile pairs per wave (register budget)
+            for (int64_t pb = 0; pb < np; pb += (it.leaf ? np : 10)) {
+              UnitDev u{};
+              u.item = i;
+              u.col_begin = c0;
+              u.ncols = std::min(width, it.N - c0);
+              u.pair_begin = (int16_t)pb;
+              u.pair_count = (int16_t)(it.leaf ? np : std::min<int64_t>(10, np - pb));
+              u.slot_off = slot;
+              slot += (int64_t)u.pair_count * 256;
+              units.push_back(u);
+            }
             double rr = it.r;
-            ss.flops_gram += 4.0 * rr * rr * (double)u.ncols;
+            ss.flops_gram += 4.0 * rr * rr * (double)std::min(width, it.N - c0);
           }
         }
         if (pass == 0) nleafu = (int64_t)units.size();
@@ -404,6 +530,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       UnitDev* d_units = upload(mem, units, st);
       int32_t* d_litems = upload(mem, litems, st);
       int32_t* d_ubegin = upload(mem, ubegin, st);
+      tr_.mark("gram units", s, b, lv);
       tg.start();
       launch_gram(M.src, false, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s, partial, st);
       launch_check("gram (leaf)");
@@ -411,6 +538,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
                   (int64_t)units.size() - nleafu, M.zeta, s, partial, st);
       launch_check("gram (non-leaf)");
       tg.stop();
+      tr_.mark("gram", s, b, lv);
       launch_gram_reduce(S.d_items, d_litems, n, d_ubegin, d_units, partial, st);
       launch_check("gram reduce");
       launch_factor(S.d_items, d_litems, n, M.eps, 60, d_status, st);
@@ -421,6 +549,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       if (status & 1)
         fail(DH2_EUNSUPPORTED, "numerical rank of a block row exceeds the factor capacity");
       if (status & 2) fail(DH2_ENOTCONV, "one-sided Jacobi did not converge");
+      tr_.mark("factor", s, b, lv);
       mem.release(Marena);
       for (int32_t i = lo; i < hi; ++i) S.items[i].M = nullptr;
       // coefficient matrices R of this level
@@ -453,11 +582,14 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         if (pass == 0) nleafr = (int64_t)ru.size();
       }
       UnitDev* d_ru = upload(mem, ru, st);
+      tr_.mark("rprod units", s, b, lv);
       launch_rprod(M.src, false, g, S.d_items, S.d_ents, d_ru, nleafr, M.zeta, s, st);
       launch_check("rprod (leaf)");
       launch_rprod(M.src, true, g, S.d_items, S.d_ents, d_ru + nleafr, (int64_t)ru.size() - nleafr,
                    M.zeta, s, st);
       launch_check("rprod (non-leaf)");
+      if (trace_on()) hip_check(hipStreamSynchronize(st), "trace sync");
+      tr_.mark("rprod", s, b, lv);
       // projection of the admissible blocks of this level (row sweep)
       if (s == 0) {
         std::vector<ProjDev> tasks;
@@ -501,10 +633,12 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           }
         }
         ProjDev* d_tasks = upload(mem, tasks, st);
+        tr_.mark("proj tasks", s, b, lv);
         tp.start();
         launch_project(d_tasks, (int64_t)tasks.size(), M.d_omega, st);
         launch_check("project");
         tp.stop();
+        tr_.mark("project", s, b, lv);
         mem.release(d_tasks);
       }
       hip_check(hipStreamSynchronize(st), "level sync");
@@ -514,6 +648,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       mem.release(d_ru);
       mem.release(R_prev);
       R_prev = Rarena;
+      tr_.mark("level end", s, b, lv);
     }
     mem.release(R_prev);
     for (int32_t i = 0; i < S.nitems; ++i) S.items[i].R = nullptr;
@@ -639,6 +774,10 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   for (int32_t l = 0; l <= tr.depth; ++l) peak = std::max(peak, (lvlN[l] + lvlN[l + 1]) * kest * 16.0);
   size_t freeb = 0, totalb = 0;
   hip_check(hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo");
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    freeb += g_cached;  // blocks held in the cache are available to this call
+  }
   double budget = 0.4 * (double)freeb;
   if (o.max_device_bytes > 0) budget = std::min(budget, 0.4 * (double)o.max_device_bytes);
   int32_t nb = o.groups > 0 ? o.groups : (int32_t)std::ceil(peak / std::max(1.0, budget));

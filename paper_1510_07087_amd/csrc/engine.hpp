@@ -21,6 +21,8 @@ struct Error {
 
 [[noreturn]] void fail(dh2_status code, const std::string& msg);
 void hip_check(hipError_t e, const char* what);
+// Return the cached (freed but kept) device blocks to the driver.
+void release_cached_memory();
 
 // Device allocations with an optional cap (max_device_bytes).
 class DevMem {

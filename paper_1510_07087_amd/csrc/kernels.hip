@@ -131,52 +131,6 @@ __global__ void k_entry_scale(EntDev* ent, int64_t nent, const double* omega, do
 // Stage producer: T[c * ld + rho] = A[rho][col0 + c] for c < kStageCols,
 // rho < rp (zero outside the item).  ld = rp + 1 (bank spread).
 // ---------------------------------------------------------------------------
-struct StageCtx {
-  const ItemDev* it;
-  int64_t item_r;     // rows of A
-  int rp;             // rows padded to 16
-  int ld;
-};
-
-template <int SRC>
-__device__ void produce_leaf(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
-                             int64_t col0, int64_t ncols, int rp, int ld, double2* T,
-                             int64_t* cpos, double* cscale) {
-  int tid = threadIdx.x;
-  if (tid < kStageCols) {
-    int64_t j = col0 + tid;
-    int64_t pos = -1;
-    double sc = 0.0;
-    if (tid < ncols) {
-      int64_t lo = it.ent_begin, hi = it.ent_end - 1;
-      while (lo < hi) {  // last entry with col_start <= j
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (ents[mid].col_start <= j)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      const EntDev& e = ents[lo];
-      pos = e.pos + (j - e.col_start);
-      sc = e.scale;
-    }
-    cpos[tid] = pos;
-    cscale[tid] = sc;
-  }
-  __syncthreads();
-  int m = it.m;
-  for (int e = tid; e < kStageCols * rp; e += 256) {
-    int c = e / rp, rho = e - c * rp;
-    double2 v = make_double2(0.0, 0.0);
-    int64_t pj = cpos[c];
-    if (rho < m && pj >= 0) {
-      double2 z = entry<SRC>(g, it.row_off + rho, pj, side);
-      double s = cscale[c];
-      v = make_double2(z.x * s, z.y * s);
-    }
-    T[c * ld + rho] = v;
-  }
-}
 
 __device__ void produce_inner(const ItemDev* items, const ItemDev& it, double zeta, int64_t col0, int64_t ncols, int rp, int ld,
                               double2* T) {
@@ -198,164 +152,10 @@ __device__ void produce_inner(const ItemDev* items, const ItemDev& it, double ze
 
 constexpr int kTileLds = kStageCols * (kMaxR + 1);  // double2 elements
 
-// ---------------------------------------------------------------------------
-// Gram of a block row: partial sums per unit into slot_off (lower tiles,
-// MFMA output layout [pair][v][lane]).  nt <= 4: every wave runs all tile
-// pairs on a quarter of the k-steps, then the waves are summed in a fixed
-// order; nt > 4: the waves split the tile pairs.
-// ---------------------------------------------------------------------------
-template <int NT>
-__device__ void gram_stage_all_pairs(const double2* T, int ld, int ncols, dvec4 (&acr)[10],
-                                     dvec4 (&aci)[10]) {
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int row = lane & 15, kq = lane >> 4;
-  for (int ks = w; ks * 4 < ncols; ks += 4) {
-    const double2* col = T + (ks * 4 + kq) * ld + row;
-    double ar[NT], ai[NT];
-#pragma unroll
-    for (int I = 0; I < NT; ++I) {
-      double2 v = col[16 * I];
-      ar[I] = v.x;
-      ai[I] = v.y;
-    }
-    int p = 0;
-#pragma unroll
-    for (int I = 0; I < NT; ++I) {
-#pragma unroll
-      for (int J = 0; J <= I; ++J) {
-        acr[p] = mfma_f64(ar[I], ar[J], acr[p]);
-        acr[p] = mfma_f64(ai[I], ai[J], acr[p]);
-        aci[p] = mfma_f64(ai[I], ar[J], aci[p]);
-        aci[p] = mfma_f64(-ar[I], ai[J], aci[p]);
-        ++p;
-      }
-    }
-  }
-}
-
 __device__ __forceinline__ void pair_ij(int p, int& I, int& J) {
   I = 0;
   while ((I + 1) * (I + 2) / 2 <= p) ++I;
   J = p - I * (I + 1) / 2;
-}
-
-template <int SRC, bool INNER>
-__global__ __launch_bounds__(256) void k_gram(GeomDev g, const ItemDev* items, const EntDev* ents,
-                                              const UnitDev* units, double zeta, int side,
-                                              double2* partial) {
-  __shared__ double2 T[kTileLds];
-  __shared__ int64_t cpos[kStageCols];
-  __shared__ double cscale[kStageCols];
-  const UnitDev u = units[blockIdx.x];
-  const ItemDev it = items[u.item];
-  int r = it.r;
-  int nt = (r + 15) / 16, rp = nt * 16, ld = rp + 1;
-  int npairs = nt * (nt + 1) / 2;
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double2* out = partial + u.slot_off;
-
-  if (nt <= 4) {
-    dvec4 acr[10], aci[10];
-#pragma unroll
-    for (int p = 0; p < 10; ++p) {
-      acr[p] = dvec4{0, 0, 0, 0};
-      aci[p] = dvec4{0, 0, 0, 0};
-    }
-    for (int64_t c0 = 0; c0 < u.ncols; c0 += kStageCols) {
-      int64_t nc = u.ncols - c0 < kStageCols ? u.ncols - c0 : kStageCols;
-      __syncthreads();
-      if constexpr (INNER)
-        produce_inner(items, it, zeta, u.col_begin + c0, nc, rp, ld, T);
-      else
-        produce_leaf<SRC>(g, it, ents, side, u.col_begin + c0, nc, rp, ld, T, cpos, cscale);
-      __syncthreads();
-      switch (nt) {
-        case 1: gram_stage_all_pairs<1>(T, ld, (int)nc, acr, aci); break;
-        case 2: gram_stage_all_pairs<2>(T, ld, (int)nc, acr, aci); break;
-        case 3: gram_stage_all_pairs<3>(T, ld, (int)nc, acr, aci); break;
-        default: gram_stage_all_pairs<4>(T, ld, (int)nc, acr, aci); break;
-      }
-    }
-    // fixed-order reduction over the four waves (wave 0 accumulates)
-    double* red = reinterpret_cast<double*>(T);
-    for (int src = 1; src < 4; ++src) {
-      __syncthreads();
-      if (w == src) {
-#pragma unroll
-        for (int p = 0; p < 10; ++p)
-          if (p < npairs)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              red[((p * 4 + v) * 64 + lane) * 2 + 0] = acr[p][v];
-              red[((p * 4 + v) * 64 + lane) * 2 + 1] = aci[p][v];
-            }
-      }
-      __syncthreads();
-      if (w == 0) {
-#pragma unroll
-        for (int p = 0; p < 10; ++p)
-          if (p < npairs)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              acr[p][v] += red[((p * 4 + v) * 64 + lane) * 2 + 0];
-              aci[p][v] += red[((p * 4 + v) * 64 + lane) * 2 + 1];
-            }
-      }
-    }
-    if (w == 0) {
-#pragma unroll
-      for (int p = 0; p < 10; ++p)
-        if (p < npairs)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[p][v], aci[p][v]);
-    }
-  } else {
-    // nt in 5..8: up to 36 tile pairs, wave w owns pairs w, w+4, ...
-    constexpr int kMaxOwn = 9;
-    dvec4 acr[kMaxOwn], aci[kMaxOwn];
-    int pi_[kMaxOwn], pj_[kMaxOwn];
-#pragma unroll
-    for (int q = 0; q < kMaxOwn; ++q) {
-      acr[q] = dvec4{0, 0, 0, 0};
-      aci[q] = dvec4{0, 0, 0, 0};
-      int p = w + 4 * q;
-      int I = 0, J = 0;
-      if (p < npairs) pair_ij(p, I, J);
-      pi_[q] = I;
-      pj_[q] = J;
-    }
-    int row = lane & 15, kq = lane >> 4;
-    for (int64_t c0 = 0; c0 < u.ncols; c0 += kStageCols) {
-      int64_t nc = u.ncols - c0 < kStageCols ? u.ncols - c0 : kStageCols;
-      __syncthreads();
-      if constexpr (INNER)
-        produce_inner(items, it, zeta, u.col_begin + c0, nc, rp, ld, T);
-      else
-        produce_leaf<SRC>(g, it, ents, side, u.col_begin + c0, nc, rp, ld, T, cpos, cscale);
-      __syncthreads();
-      for (int ks = 0; ks * 4 < nc; ++ks) {
-        const double2* col = T + (ks * 4 + kq) * ld + row;
-#pragma unroll
-        for (int q = 0; q < kMaxOwn; ++q) {
-          if (w + 4 * q < npairs) {
-            double2 a = col[16 * pi_[q]];
-            double2 b = col[16 * pj_[q]];
-            acr[q] = mfma_f64(a.x, b.x, acr[q]);
-            acr[q] = mfma_f64(a.y, b.y, acr[q]);
-            aci[q] = mfma_f64(a.y, b.x, aci[q]);
-            aci[q] = mfma_f64(-a.x, b.y, aci[q]);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kMaxOwn; ++q) {
-      int p = w + 4 * q;
-      if (p < npairs)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[q][v], aci[q][v]);
-    }
-  }
 }
 
 // Sum the partial Grams of each item (in unit order) into M (r x r,
@@ -370,12 +170,14 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const ItemDev* items, const
   double2* Mi = it.M;
   for (int e = threadIdx.x; e < npairs * 256; e += 256) {
     double2 s = make_double2(0.0, 0.0);
-    for (int32_t q = ub; q < ue; ++q) {
-      double2 v = partial[units[q].slot_off + e];
-      s.x += v.x;
-      s.y += v.y;
-    }
     int p = e >> 8, v = (e >> 6) & 3, lane = e & 63;
+    for (int32_t q = ub; q < ue; ++q) {
+      const UnitDev& uq = units[q];
+      if (p < uq.pair_begin || p >= uq.pair_begin + uq.pair_count) continue;
+      double2 val = partial[uq.slot_off + (int64_t)(p - uq.pair_begin) * 256 + (e & 255)];
+      s.x += val.x;
+      s.y += val.y;
+    }
     int I, J;
     pair_ij(p, I, J);
     int row = 16 * I + f64_row(lane, v), col = 16 * J + (lane & 15);
@@ -623,12 +425,10 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
 // A[rho][j] conj(Q[rho][kk]).  Output tiles (16 columns x 16 ranks) are split
 // over the waves.
 // ---------------------------------------------------------------------------
-template <int SRC, bool INNER>
-__global__ __launch_bounds__(256) void k_rprod(GeomDev g, const ItemDev* items, const EntDev* ents,
-                                               const UnitDev* units, double zeta, int side) {
+// R^T of a non-leaf block row from LDS-staged tiles of G_hat (coalesced loads).
+__global__ __launch_bounds__(256) void k_rprod_inner(const ItemDev* items, const UnitDev* units,
+                                                     double zeta) {
   __shared__ double2 T[kTileLds];
-  __shared__ int64_t cpos[kStageCols];
-  __shared__ double cscale[kStageCols];
   const UnitDev u = units[blockIdx.x];
   const ItemDev it = items[u.item];
   int r = it.r, k = it.k;
@@ -643,10 +443,7 @@ __global__ __launch_bounds__(256) void k_rprod(GeomDev g, const ItemDev* items, 
   for (int64_t c0 = 0; c0 < u.ncols; c0 += kStageCols) {
     int64_t nc = u.ncols - c0 < kStageCols ? u.ncols - c0 : kStageCols;
     __syncthreads();
-    if constexpr (INNER)
-      produce_inner(items, it, zeta, u.col_begin + c0, nc, rp, ld, T);
-    else
-      produce_leaf<SRC>(g, it, ents, side, u.col_begin + c0, nc, rp, ld, T, cpos, cscale);
+    produce_inner(items, it, zeta, u.col_begin + c0, nc, rp, ld, T);
     __syncthreads();
     for (int task = w; task < ntask; task += 4) {
       int cg = task / kt, tk = task - cg * kt;
@@ -951,6 +748,289 @@ __global__ __launch_bounds__(256) void k_direct(GeomDev g, const int64_t* rows, 
 }
 
 // ---------------------------------------------------------------------------
+// Wave-level pipelines.  Each wave owns a work unit and builds exactly the
+// MFMA operands it consumes: no block barriers, so entry generation (VALU)
+// of one k-step overlaps the MFMAs of the previous one.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Column j of a leaf block row: permuted position and scale 1/(omega_b zeta^d).
+__device__ __forceinline__ void leaf_column(const ItemDev& it, const EntDev* ents, int64_t j,
+                                            int64_t& pos, double& scale) {
+  int64_t lo = it.ent_begin, hi = it.ent_end - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (ents[mid].col_start <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  pos = ents[lo].pos + (j - ents[lo].col_start);
+  scale = ents[lo].scale;
+}
+
+// Staged column data: x, y, z and the column factor.  Helmholtz: factor =
+// scale * (side 0 ? w_j : 1) / (4 pi); dense: factor = scale, index in .x.
+template <int SRC>
+__device__ __forceinline__ double4 column_data(const GeomDev& g, const ItemDev& it,
+                                               const EntDev* ents, int side, int64_t j,
+                                               bool valid) {
+  if (!valid) return make_double4(0.0, 0.0, 0.0, 0.0);
+  int64_t pos;
+  double sc;
+  leaf_column(it, ents, j, pos, sc);
+  if constexpr (SRC == SRC_HELMHOLTZ) {
+    const double* p = g.pts + 4 * pos;
+    return make_double4(p[0], p[1], p[2], sc * (side == 0 ? p[3] : 1.0) * kInv4Pi);
+  } else {
+    return make_double4(__longlong_as_double((long long)g.perm[pos]), 0.0, 0.0, sc);
+  }
+}
+
+struct RowData {
+  double x, y, z, f;   // Helmholtz: coordinates and row factor; dense: original index in x
+};
+
+template <int SRC>
+__device__ __forceinline__ RowData row_data(const GeomDev& g, const ItemDev& it, int rho, int side) {
+  RowData r{0.0, 0.0, 0.0, 0.0};
+  if (rho < it.m) {
+    int64_t pos = it.row_off + rho;
+    if constexpr (SRC == SRC_HELMHOLTZ) {
+      const double* p = g.pts + 4 * pos;
+      r.x = p[0];
+      r.y = p[1];
+      r.z = p[2];
+      r.f = side == 1 ? p[3] : 1.0;
+    } else {
+      r.x = __longlong_as_double((long long)g.perm[pos]);
+      r.f = 1.0;
+    }
+  }
+  return r;
+}
+
+// entry of the weighted block row from staged row and column data
+template <int SRC>
+__device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw, double4 cc,
+                                             int side) {
+  double f = rw.f * cc.w;
+  if (f == 0.0) return make_double2(0.0, 0.0);
+  if constexpr (SRC == SRC_HELMHOLTZ) {
+    double dx = rw.x - cc.x, dy = rw.y - cc.y, dz = rw.z - cc.z;
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double sn, cs;
+    sincos(g.kappa * r, &sn, &cs);
+    double a = f / r;
+    return make_double2(a * cs, side == 0 ? a * sn : -a * sn);
+  } else {
+    const double2* G = reinterpret_cast<const double2*>(g.G);
+    int64_t i = (int64_t)__double_as_longlong(rw.x), j = (int64_t)__double_as_longlong(cc.x);
+    double2 v = side == 0 ? G[i * g.ldg + j] : G[j * g.ldg + i];
+    return make_double2(v.x * f, (side == 0 ? v.y : -v.y) * f);
+  }
+}
+
+// Gram of a leaf block row, one unit per wave, all lower tile pairs.
+template <int SRC, int NT>
+__device__ void gram_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
+                               const UnitDev& u, double2* out, double4* cl) {
+  constexpr int NP = NT * (NT + 1) / 2;
+  int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  RowData rw[NT];
+#pragma unroll
+  for (int I = 0; I < NT; ++I) rw[I] = row_data<SRC>(g, it, 16 * I + row, side);
+  dvec4 acr[NP], aci[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    acr[p] = dvec4{0, 0, 0, 0};
+    aci[p] = dvec4{0, 0, 0, 0};
+  }
+  for (int64_t c0 = 0; c0 < u.ncols; c0 += 64) {
+    int64_t left = u.ncols - c0;
+    wave_sync();
+    cl[lane] = column_data<SRC>(g, it, ents, side, u.col_begin + c0 + lane, lane < left);
+    wave_sync();
+    int nks = left >= 64 ? 16 : (int)((left + 3) / 4);
+    for (int ks = 0; ks < nks; ++ks) {
+      double4 cc = cl[4 * ks + kq];
+      double ar[NT], ai[NT];
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        double2 e = gen_entry<SRC>(g, rw[I], cc, side);
+        ar[I] = e.x;
+        ai[I] = e.y;
+      }
+      int p = 0;
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+#pragma unroll
+        for (int J = 0; J <= I; ++J) {
+          acr[p] = mfma_f64(ar[I], ar[J], acr[p]);
+          acr[p] = mfma_f64(ai[I], ai[J], acr[p]);
+          aci[p] = mfma_f64(ai[I], ar[J], aci[p]);
+          aci[p] = mfma_f64(-ar[I], ai[J], aci[p]);
+          ++p;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[p][v], aci[p][v]);
+}
+
+template <int SRC>
+__global__ __launch_bounds__(256) void k_gram_leaf_w(GeomDev g, const ItemDev* items,
+                                                     const EntDev* ents, const UnitDev* units,
+                                                     int64_t nunits, int side, double2* partial) {
+  __shared__ double4 cls[4][64];
+  int w = threadIdx.x >> 6;
+  int64_t ui = (int64_t)blockIdx.x * 4 + w;
+  if (ui >= nunits) return;
+  const UnitDev u = units[ui];
+  const ItemDev& it = items[u.item];
+  int nt = (it.r + 15) / 16;
+  double2* out = partial + u.slot_off;
+  switch (nt) {
+    case 1: gram_leaf_wave<SRC, 1>(g, it, ents, side, u, out, cls[w]); break;
+    case 2: gram_leaf_wave<SRC, 2>(g, it, ents, side, u, out, cls[w]); break;
+    case 3: gram_leaf_wave<SRC, 3>(g, it, ents, side, u, out, cls[w]); break;
+    default: gram_leaf_wave<SRC, 4>(g, it, ents, side, u, out, cls[w]); break;
+  }
+}
+
+// Row rho of G_hat_tc = zeta [R_t1c' ; R_t2c'] at column j (0 outside).
+__device__ __forceinline__ double2 ghat(const ItemDev& s1, const ItemDev& s2, int64_t j, int rho,
+                                        int r, double zeta) {
+  if (rho >= r) return make_double2(0.0, 0.0);
+  double2 z = rho < s1.k ? s1.R[j * s1.k + rho] : s2.R[j * s2.k + (rho - s1.k)];
+  return make_double2(z.x * zeta, z.y * zeta);
+}
+
+// Gram of a non-leaf block row, one unit (column range x tile-pair subset) per wave.
+__global__ __launch_bounds__(256) void k_gram_inner_w(const ItemDev* items, const UnitDev* units,
+                                                      int64_t nunits, double zeta,
+                                                      double2* partial) {
+  constexpr int kMaxPairs = 10;
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  int64_t ui = (int64_t)blockIdx.x * 4 + w;
+  if (ui >= nunits) return;
+  const UnitDev u = units[ui];
+  const ItemDev& it = items[u.item];
+  const ItemDev& s1 = items[it.son[0]];
+  const ItemDev& s2 = items[it.son[1]];
+  int r = it.r;
+  int pi_[kMaxPairs], pj_[kMaxPairs];
+  dvec4 acr[kMaxPairs], aci[kMaxPairs];
+#pragma unroll
+  for (int q = 0; q < kMaxPairs; ++q) {
+    int I = 0, J = 0;
+    if (q < u.pair_count) pair_ij(u.pair_begin + q, I, J);
+    pi_[q] = 16 * I + row;
+    pj_[q] = 16 * J + row;
+    acr[q] = dvec4{0, 0, 0, 0};
+    aci[q] = dvec4{0, 0, 0, 0};
+  }
+  int64_t jb = it.col_off + u.col_begin;
+  for (int64_t c = kq; c < ((u.ncols + 3) & ~int64_t(3)); c += 4) {
+    bool cv = c < u.ncols;
+    int64_t j = jb + c;
+#pragma unroll
+    for (int q = 0; q < kMaxPairs; ++q) {
+      if (q < u.pair_count) {
+        double2 a = cv ? ghat(s1, s2, j, pi_[q], r, zeta) : make_double2(0.0, 0.0);
+        double2 b = cv ? ghat(s1, s2, j, pj_[q], r, zeta) : make_double2(0.0, 0.0);
+        acr[q] = mfma_f64(a.x, b.x, acr[q]);
+        acr[q] = mfma_f64(a.y, b.y, acr[q]);
+        aci[q] = mfma_f64(a.y, b.x, aci[q]);
+        aci[q] = mfma_f64(-a.x, b.y, aci[q]);
+      }
+    }
+  }
+  double2* out = partial + u.slot_off;
+#pragma unroll
+  for (int q = 0; q < kMaxPairs; ++q)
+    if (q < u.pair_count)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(q * 4 + v) * 64 + lane] = make_double2(acr[q][v], aci[q][v]);
+}
+
+// R^T of a leaf block row: the workgroup's four waves share the item's factor
+// Q (in LDS) and take 16-column groups in turn.
+template <int SRC, int KT>
+__device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
+                                const UnitDev& u, const double2* Qs, const RowData* rows) {
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  int r = it.r, k = it.k;
+  int nks = (r + 3) / 4;
+  for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
+    int64_t j = u.col_begin + j0 + row;
+    double4 cc = column_data<SRC>(g, it, ents, side, j, j0 + row < u.ncols);
+    dvec4 acr[KT], aci[KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      acr[t] = dvec4{0, 0, 0, 0};
+      aci[t] = dvec4{0, 0, 0, 0};
+    }
+    for (int ks = 0; ks < nks; ++ks) {
+      int rho = 4 * ks + kq;
+      double2 a = gen_entry<SRC>(g, rows[rho], cc, side);
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        double2 q = Qs[rho * (16 * KT) + 16 * t + row];
+        // A^T conj(Q): re = ar qr + ai qi, im = ai qr - ar qi
+        acr[t] = mfma_f64(a.x, q.x, acr[t]);
+        acr[t] = mfma_f64(a.y, q.y, acr[t]);
+        aci[t] = mfma_f64(a.y, q.x, aci[t]);
+        aci[t] = mfma_f64(-a.x, q.y, aci[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      int kk = 16 * t + row;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int64_t jl = j0 + f64_row(lane, v);
+        if (jl < u.ncols && kk < k)
+          it.R[(u.col_begin + jl) * k + kk] = make_double2(acr[t][v], aci[t][v]);
+      }
+    }
+  }
+}
+
+template <int SRC>
+__global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* items,
+                                                      const EntDev* ents, const UnitDev* units,
+                                                      int side) {
+  __shared__ double2 Qs[68 * 64];   // (r + 4) x (16 KT), zero padded rows past r
+  __shared__ RowData rows[64 + 4];
+  const UnitDev u = units[blockIdx.x];
+  const ItemDev& it = items[u.item];
+  int r = it.r, k = it.k;
+  if (k == 0) return;
+  int kt = (k + 15) / 16;
+  int ldq = 16 * kt;
+  for (int e = threadIdx.x; e < (r + 4) * ldq; e += 256) {
+    int i = e / ldq, kk = e - i * ldq;
+    Qs[e] = (i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0);
+  }
+  for (int i = threadIdx.x; i < 68; i += 256) rows[i] = row_data<SRC>(g, it, i, side);
+  __syncthreads();
+  switch (kt) {
+    case 1: rprod_leaf_wave<SRC, 1>(g, it, ents, side, u, Qs, rows); break;
+    case 2: rprod_leaf_wave<SRC, 2>(g, it, ents, side, u, Qs, rows); break;
+    case 3: rprod_leaf_wave<SRC, 3>(g, it, ents, side, u, Qs, rows); break;
+    default: rprod_leaf_wave<SRC, 4>(g, it, ents, side, u, Qs, rows); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -978,15 +1058,14 @@ void launch_gram(int src, bool inner, const GeomDev& g, const ItemDev* items, co
                  const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
                  hipStream_t st) {
   if (nunits == 0) return;
-  dim3 grid((unsigned)nunits), blk(256);
+  dim3 grid(blocks_for(nunits, 4)), blk(256);
   if (inner)
-    hipLaunchKernelGGL((k_gram<SRC_HELMHOLTZ, true>), grid, blk, 0, st, g, items, ents, units,
-                       zeta, side, partial);
+    hipLaunchKernelGGL(k_gram_inner_w, grid, blk, 0, st, items, units, nunits, zeta, partial);
   else if (src == SRC_HELMHOLTZ)
-    hipLaunchKernelGGL((k_gram<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents, units,
-                       zeta, side, partial);
+    hipLaunchKernelGGL(k_gram_leaf_w<SRC_HELMHOLTZ>, grid, blk, 0, st, g, items, ents, units,
+                       nunits, side, partial);
   else
-    hipLaunchKernelGGL((k_gram<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents, units, zeta,
+    hipLaunchKernelGGL(k_gram_leaf_w<SRC_DENSE>, grid, blk, 0, st, g, items, ents, units, nunits,
                        side, partial);
 }
 
@@ -1017,14 +1096,12 @@ void launch_rprod(int src, bool inner, const GeomDev& g, const ItemDev* items, c
   if (nunits == 0) return;
   dim3 grid((unsigned)nunits), blk(256);
   if (inner)
-    hipLaunchKernelGGL((k_rprod<SRC_HELMHOLTZ, true>), grid, blk, 0, st, g, items, ents, units,
-                       zeta, side);
+    hipLaunchKernelGGL(k_rprod_inner, grid, blk, 0, st, items, units, zeta);
   else if (src == SRC_HELMHOLTZ)
-    hipLaunchKernelGGL((k_rprod<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents, units,
-                       zeta, side);
-  else
-    hipLaunchKernelGGL((k_rprod<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents, units, zeta,
+    hipLaunchKernelGGL(k_rprod_leaf_w<SRC_HELMHOLTZ>, grid, blk, 0, st, g, items, ents, units,
                        side);
+  else
+    hipLaunchKernelGGL(k_rprod_leaf_w<SRC_DENSE>, grid, blk, 0, st, g, items, ents, units, side);
 }
 
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st) {

@@ -62,7 +62,7 @@ EXPORTED = [
     "dh2_blocks_free", "dh2_blocks_get_info", "dh2_blocks_export", "dh2_blocks_colsets",
     "dh2_compress_dense", "dh2_compress_helmholtz", "dh2_matrix_free", "dh2_matvec",
     "dh2_error_estimate", "dh2_rows_check", "dh2_get_stats", "dh2_basis_export",
-    "dh2_coupling_export", "dh2_near_export",
+    "dh2_coupling_export", "dh2_near_export", "dh2_release_cached_memory",
 ]
 
 _lib = None
@@ -103,6 +103,7 @@ def lib():
                                    P(I32), P(I64), P(D), P(I64), P(D)]),
         "dh2_coupling_export": (I32, [VP, P(I64), P(D)]),
         "dh2_near_export": (I32, [VP, P(I64), P(D)]),
+        "dh2_release_cached_memory": (None, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -338,3 +339,8 @@ def near_export(m: Matrix, nnear: int):
     N = np.empty(max(1, 2 * int(off[-1])))
     _check(lib().dh2_near_export(m.h, _p(off, C.c_int64), _p(N, C.c_double)))
     return off, N[:2 * int(off[-1])].view(np.complex128)
+
+
+def release_cached_memory():
+    """Return the library's cached device memory to the driver."""
+    lib().dh2_release_cached_memory()
