@@ -96,7 +96,22 @@ dh2_status dh2_tree_build(const double* pts, int64_t n, double kappa, const dh2_
     if (!(kappa >= 0) || !std::isfinite(kappa)) fail(DH2_EINVAL, "kappa must be finite and >= 0");
     for (int64_t i = 0; i < 3 * n; ++i)
       if (!std::isfinite(pts[i])) fail(DH2_EINVAL, "non-finite point coordinate");
-    auto h = new dh2_tree_s{make_tree(pts, n, kappa, *opts)};
+    auto td = make_tree(pts, n, kappa, *opts);
+    // coincident points always end in the same leaf (the split is by
+    // coordinate), where they would make the kernel singular
+    const auto& tr = td->tr;
+    for (int32_t t = 0; t < tr.nc(); ++t) {
+      if (!tr.leaf(t)) continue;
+      for (int64_t a = tr.off[t]; a < tr.off[t] + tr.size[t]; ++a)
+        for (int64_t b = a + 1; b < tr.off[t] + tr.size[t]; ++b) {
+          const double* x = pts + 3 * tr.perm[a];
+          const double* y = pts + 3 * tr.perm[b];
+          if (x[0] == y[0] && x[1] == y[1] && x[2] == y[2])
+            fail(DH2_EINVAL, "coincident points " + std::to_string(tr.perm[a]) + " and " +
+                                 std::to_string(tr.perm[b]));
+        }
+    }
+    auto h = new dh2_tree_s{td};
     *out = h;
   })
 }

@@ -54,8 +54,9 @@ struct EntDev {
 // A contiguous column range of one block row, processed by one workgroup.
 struct UnitDev {
   int32_t item;
-  int16_t pair_begin; // Gram units of non-leaf items: tile pairs [pair_begin, +pair_count)
-  int16_t pair_count;
+  // Gram units: row tiles [a0, a0+na) against row tiles [b0, b0+nb) of the
+  // 16-row tiles of the factor; a0 == b0 marks a diagonal block (pairs J <= I)
+  int8_t a0, na, b0, nb;
   int64_t col_begin;
   int64_t ncols;
   int64_t slot_off;   // partial-Gram slot offset in complex elements (Gram units)
@@ -108,6 +109,5 @@ struct NearRefDev {
 };
 
 constexpr int kMaxR = 128;      // largest factor size handled by the kernels
-constexpr int kStageCols = 32;  // columns per LDS stage
 
 }  // namespace dh2

@@ -15,6 +15,7 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -501,18 +502,31 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           if (it.r == 0) continue;
           if (it.leaf && it.m > 64)
             fail(DH2_EUNSUPPORTED, "leaf clusters with more than 64 points are not supported");
-          int64_t np = npairs_of(it.r);
+          // tile blocks per unit (register budget: at most 10 tile pairs per wave):
+          // nt <= 4: one diagonal block; otherwise the diagonal blocks of tiles
+          // 0..3 and 4..nt-1 and the off-diagonal part in bands of two tiles
+          int nt = (it.r + 15) / 16;
+          std::vector<std::array<int, 4>> blocksets;
+          if (nt <= 4) {
+            blocksets.push_back({0, nt, 0, nt});
+          } else {
+            blocksets.push_back({0, 4, 0, 4});
+            blocksets.push_back({4, nt - 4, 4, nt - 4});
+            for (int a0 = 4; a0 < nt; a0 += 2) blocksets.push_back({a0, std::min(2, nt - a0), 0, 4});
+          }
           for (int64_t c0 = 0; c0 < it.N; c0 += width) {
-            // non-leaf rows: at most 10 tile pairs per wave (register budget)
-            for (int64_t pb = 0; pb < np; pb += (it.leaf ? np : 10)) {
+            for (const auto& bs : blocksets) {
               UnitDev u{};
               u.item = i;
               u.col_begin = c0;
               u.ncols = std::min(width, it.N - c0);
-              u.pair_begin = (int16_t)pb;
-              u.pair_count = (int16_t)(it.leaf ? np : std::min<int64_t>(10, np - pb));
+              u.a0 = (int8_t)bs[0];
+              u.na = (int8_t)bs[1];
+              u.b0 = (int8_t)bs[2];
+              u.nb = (int8_t)bs[3];
+              int npair = bs[0] == bs[2] ? bs[1] * (bs[1] + 1) / 2 : bs[1] * bs[3];
               u.slot_off = slot;
-              slot += (int64_t)u.pair_count * 256;
+              slot += (int64_t)npair * 256;
               units.push_back(u);
             }
             double rr = it.r;
@@ -565,8 +579,10 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       }
       copy_to(S.d_items + lo, S.items.data() + lo, n, st);
       std::vector<UnitDev> ru;
-      int64_t rwidth = 1024, nleafr = 0;
+      int64_t nleafr = 0;
       for (int pass = 0; pass < 2; ++pass) {
+        // leaf units are shared by a workgroup, non-leaf units by one wave
+        int64_t rwidth = pass == 0 ? 1024 : 512;
         for (int32_t i = lo; i < hi; ++i) {
           const ItemDev& it = S.items[i];
           if ((pass == 0) != (it.leaf != 0) || it.k == 0) continue;

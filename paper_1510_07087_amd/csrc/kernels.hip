@@ -1,10 +1,9 @@
 // gfx950 kernels of the directional H2 compression (FP64 path).
 //
-// Block rows are processed in LDS stages of kStageCols columns.  A stage
-// holds the tile A[rho][col] of the weighted block row G^w_tc (leaf
-// clusters: entries generated from the points; other clusters: the rows of
-// G_hat_tc = zeta [R_t1c' ; R_t2c'] gathered from the sons' coefficient
-// matrices).  Consumers:
+// Block rows are processed by wave-level pipelines.  The operand of a wave
+// is the weighted block row G^w_tc (leaf clusters: entries generated from
+// the points; other clusters: the rows of G_hat_tc = zeta [R_t1c' ; R_t2c']
+// read from the sons' coefficient matrices).  Consumers:
 //   * Gram:      M += A A^*   (FP64 MFMA 16x16x4, lower-triangular tiles)
 //   * R-product: R^T += A^T conj(Q)   (FP64 MFMA), i.e. R_tc = Q^* A
 // The small factorisation (pivoted Cholesky of M, one-sided Jacobi on the
@@ -44,12 +43,65 @@ constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
 // Matrix entries.  Side 0 reads G, side 1 reads G^* (rows of G^* are columns
 // of G): entry(i,j) = conj(G_ji).
 // ---------------------------------------------------------------------------
+// sin and cos of x in [0, 2^20 pi/2): Cody-Waite reduction y = x - n pi/2
+// with pi/2 split in three parts (the first two with 33 significant bits, so
+// n * part is exact), then Taylor polynomials of sin and cos on |y| <= pi/4
+// up to degree 17 and 16 (truncation error below 1e-18).
+__device__ __forceinline__ void sincos_cw(double x, double& s, double& c) {
+  double n = rint(x * 0.6366197723675814);
+  double y = fma(-n, 0x1.921fb544p+0, x);
+  y = fma(-n, 0x1.0b4611a6p-34, y);
+  y = fma(-n, 0x1.3198a2e037073p-69, y);
+  double y2 = y * y;
+  double ps = 2.8114572543455206e-15;            // 1/17!
+  ps = fma(ps, y2, -7.647163731819816e-13);       // -1/15!
+  ps = fma(ps, y2, 1.6059043836821613e-10);       // 1/13!
+  ps = fma(ps, y2, -2.505210838544172e-08);       // -1/11!
+  ps = fma(ps, y2, 2.7557319223985893e-06);       // 1/9!
+  ps = fma(ps, y2, -0.0001984126984126984);       // -1/7!
+  ps = fma(ps, y2, 0.008333333333333333);         // 1/5!
+  ps = fma(ps, y2, -0.16666666666666666);         // -1/3!
+  double sy = fma(ps * y2, y, y);
+  double pc = 4.779477332387385e-14;             // 1/16!
+  pc = fma(pc, y2, -1.1470745597729725e-11);      // -1/14!
+  pc = fma(pc, y2, 2.08767569878681e-09);         // 1/12!
+  pc = fma(pc, y2, -2.755731922398589e-07);       // -1/10!
+  pc = fma(pc, y2, 2.48015873015873e-05);         // 1/8!
+  pc = fma(pc, y2, -0.001388888888888889);        // -1/6!
+  pc = fma(pc, y2, 0.041666666666666664);         // 1/4!
+  pc = fma(pc, y2, -0.5);                         // -1/2!
+  double cy = fma(pc, y2, 1.0);
+  int q = (int)((long long)n & 3);
+  double ss = (q & 1) ? cy : sy, cc = (q & 1) ? sy : cy;
+  s = (q & 2) ? -ss : ss;
+  c = ((q + 1) & 2) ? -cc : cc;
+}
+
+__device__ __forceinline__ void sincos_phase(double x, double& s, double& c) {
+  if (x < 1.6e6)
+    sincos_cw(x, s, c);
+  else
+    sincos(x, &s, &c);
+}
+
+// 1/sqrt(r2) to about half an ulp: hardware estimate refined by one Newton
+// step whose residual is formed with an FMA.
+__device__ __forceinline__ double rsqrt_nr(double r2) {
+  double ri = rsqrt(r2);
+  double h = r2 * ri;                 // ~ sqrt(r2)
+  double e = fma(-h, ri, 1.0);        // 1 - r2 ri^2
+  return fma(0.5 * ri, e, ri);
+}
+
+// w exp(+-i kappa r) / (4 pi r) from the difference vector (r > 0)
 __device__ __forceinline__ double2 helm_offdiag(double dx, double dy, double dz, double w,
                                                 double kappa, int side) {
-  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double r2 = dx * dx + dy * dy + dz * dz;
+  double ri = rsqrt_nr(r2);
+  double r = r2 * ri;
   double s, c;
-  sincos(kappa * r, &s, &c);
-  double a = w * kInv4Pi / r;
+  sincos_phase(kappa * r, s, c);
+  double a = w * kInv4Pi * ri;
   return make_double2(a * c, side == 0 ? a * s : -a * s);
 }
 
@@ -127,31 +179,6 @@ __global__ void k_entry_scale(EntDev* ent, int64_t nent, const double* omega, do
   ent[e].scale = 1.0 / (omega[ent[e].b] * z);
 }
 
-// ---------------------------------------------------------------------------
-// Stage producer: T[c * ld + rho] = A[rho][col0 + c] for c < kStageCols,
-// rho < rp (zero outside the item).  ld = rp + 1 (bank spread).
-// ---------------------------------------------------------------------------
-
-__device__ void produce_inner(const ItemDev* items, const ItemDev& it, double zeta, int64_t col0, int64_t ncols, int rp, int ld,
-                              double2* T) {
-  const ItemDev& s1 = items[it.son[0]];
-  const ItemDev& s2 = items[it.son[1]];
-  int k1 = s1.k, k2 = s2.k, r = it.r;
-  int tid = threadIdx.x;
-  for (int e = tid; e < kStageCols * rp; e += 256) {
-    int c = e / rp, rho = e - c * rp;
-    double2 v = make_double2(0.0, 0.0);
-    if (c < ncols && rho < r) {
-      int64_t j = it.col_off + col0 + c;
-      double2 z = rho < k1 ? s1.R[j * k1 + rho] : s2.R[j * k2 + (rho - k1)];
-      v = make_double2(z.x * zeta, z.y * zeta);
-    }
-    T[c * ld + rho] = v;
-  }
-}
-
-constexpr int kTileLds = kStageCols * (kMaxR + 1);  // double2 elements
-
 __device__ __forceinline__ void pair_ij(int p, int& I, int& J) {
   I = 0;
   while ((I + 1) * (I + 2) / 2 <= p) ++I;
@@ -171,15 +198,23 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const ItemDev* items, const
   for (int e = threadIdx.x; e < npairs * 256; e += 256) {
     double2 s = make_double2(0.0, 0.0);
     int p = e >> 8, v = (e >> 6) & 3, lane = e & 63;
+    int I, J;
+    pair_ij(p, I, J);
     for (int32_t q = ub; q < ue; ++q) {
       const UnitDev& uq = units[q];
-      if (p < uq.pair_begin || p >= uq.pair_begin + uq.pair_count) continue;
-      double2 val = partial[uq.slot_off + (int64_t)(p - uq.pair_begin) * 256 + (e & 255)];
+      int loc;
+      if (uq.a0 == uq.b0) {  // diagonal block of tiles
+        if (I < uq.a0 || I >= uq.a0 + uq.na || J < uq.b0) continue;
+        int Il = I - uq.a0, Jl = J - uq.b0;
+        loc = Il * (Il + 1) / 2 + Jl;
+      } else {
+        if (I < uq.a0 || I >= uq.a0 + uq.na || J < uq.b0 || J >= uq.b0 + uq.nb) continue;
+        loc = (I - uq.a0) * uq.nb + (J - uq.b0);
+      }
+      double2 val = partial[uq.slot_off + (int64_t)loc * 256 + (e & 255)];
       s.x += val.x;
       s.y += val.y;
     }
-    int I, J;
-    pair_ij(p, I, J);
     int row = 16 * I + f64_row(lane, v), col = 16 * J + (lane & 15);
     if (row < r && col < r) {
       if (I != J || row >= col) {
@@ -425,50 +460,6 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
 // A[rho][j] conj(Q[rho][kk]).  Output tiles (16 columns x 16 ranks) are split
 // over the waves.
 // ---------------------------------------------------------------------------
-// R^T of a non-leaf block row from LDS-staged tiles of G_hat (coalesced loads).
-__global__ __launch_bounds__(256) void k_rprod_inner(const ItemDev* items, const UnitDev* units,
-                                                     double zeta) {
-  __shared__ double2 T[kTileLds];
-  const UnitDev u = units[blockIdx.x];
-  const ItemDev it = items[u.item];
-  int r = it.r, k = it.k;
-  if (k == 0) return;
-  int nt = (r + 15) / 16, rp = nt * 16, ld = rp + 1;
-  int kt = (k + 15) / 16;
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int row = lane & 15, kq = lane >> 4;
-  const double2* Q = it.Q;
-  double2* Ro = it.R;
-  int ntask = (kStageCols / 16) * kt;
-  for (int64_t c0 = 0; c0 < u.ncols; c0 += kStageCols) {
-    int64_t nc = u.ncols - c0 < kStageCols ? u.ncols - c0 : kStageCols;
-    __syncthreads();
-    produce_inner(items, it, zeta, u.col_begin + c0, nc, rp, ld, T);
-    __syncthreads();
-    for (int task = w; task < ntask; task += 4) {
-      int cg = task / kt, tk = task - cg * kt;
-      if (cg * 16 >= nc) continue;
-      dvec4 acr = {0, 0, 0, 0}, aci = {0, 0, 0, 0};
-      int kk = tk * 16 + row;
-      for (int i0 = 0; i0 < r; i0 += 4) {
-        int rho = i0 + kq;
-        double2 a = T[(cg * 16 + row) * ld + rho];
-        double2 q = (rho < r && kk < k) ? Q[(int64_t)rho * k + kk] : make_double2(0.0, 0.0);
-        // A^T conj(Q): re = ar qr + ai qi, im = ai qr - ar qi
-        acr = mfma_f64(a.x, q.x, acr);
-        acr = mfma_f64(a.y, q.y, acr);
-        aci = mfma_f64(a.y, q.x, aci);
-        aci = mfma_f64(-a.x, q.y, aci);
-      }
-      for (int v = 0; v < 4; ++v) {
-        int64_t jj = u.col_begin + c0 + cg * 16 + f64_row(lane, v);
-        int64_t jl = c0 + cg * 16 + f64_row(lane, v);
-        if (jl < u.ncols && kk < k) Ro[jj * k + kk] = make_double2(acr[v], aci[v]);
-      }
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Expansion of the column basis: dst rows = src (rows x ks) * E (ks x k).
 // ---------------------------------------------------------------------------
@@ -822,10 +813,11 @@ __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw
   if (f == 0.0) return make_double2(0.0, 0.0);
   if constexpr (SRC == SRC_HELMHOLTZ) {
     double dx = rw.x - cc.x, dy = rw.y - cc.y, dz = rw.z - cc.z;
-    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double ri = rsqrt_nr(r2);
     double sn, cs;
-    sincos(g.kappa * r, &sn, &cs);
-    double a = f / r;
+    sincos_phase(g.kappa * (r2 * ri), sn, cs);
+    double a = f * ri;
     return make_double2(a * cs, side == 0 ? a * sn : -a * sn);
   } else {
     const double2* G = reinterpret_cast<const double2*>(g.G);
@@ -835,7 +827,9 @@ __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw
   }
 }
 
-// Gram of a leaf block row, one unit per wave, all lower tile pairs.
+// Gram of a leaf block row, one unit per wave, all lower tile pairs.  The
+// entries of k-step s+1 are generated while the MFMAs of k-step s issue; the
+// scheduling hints interleave one MFMA with a group of VALU instructions.
 template <int SRC, int NT>
 __device__ void gram_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
                                const UnitDev& u, double2* out, double4* cl) {
@@ -856,27 +850,38 @@ __device__ void gram_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev
     cl[lane] = column_data<SRC>(g, it, ents, side, u.col_begin + c0 + lane, lane < left);
     wave_sync();
     int nks = left >= 64 ? 16 : (int)((left + 3) / 4);
-    for (int ks = 0; ks < nks; ++ks) {
-      double4 cc = cl[4 * ks + kq];
-      double ar[NT], ai[NT];
+    double2 cur[NT];
+    {
+      double4 cc = cl[kq];
 #pragma unroll
-      for (int I = 0; I < NT; ++I) {
-        double2 e = gen_entry<SRC>(g, rw[I], cc, side);
-        ar[I] = e.x;
-        ai[I] = e.y;
-      }
+      for (int I = 0; I < NT; ++I) cur[I] = gen_entry<SRC>(g, rw[I], cc, side);
+    }
+    for (int ks = 0; ks < nks; ++ks) {
+      double2 nxt[NT];
+      double4 cn = cl[(4 * (ks + 1) + kq) & 63];
+      bool more = ks + 1 < nks;
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+        nxt[I] = more ? gen_entry<SRC>(g, rw[I], cn, side) : make_double2(0.0, 0.0);
       int p = 0;
 #pragma unroll
       for (int I = 0; I < NT; ++I) {
 #pragma unroll
         for (int J = 0; J <= I; ++J) {
-          acr[p] = mfma_f64(ar[I], ar[J], acr[p]);
-          acr[p] = mfma_f64(ai[I], ai[J], acr[p]);
-          aci[p] = mfma_f64(ai[I], ar[J], aci[p]);
-          aci[p] = mfma_f64(-ar[I], ai[J], aci[p]);
+          acr[p] = mfma_f64(cur[I].x, cur[J].x, acr[p]);
+          acr[p] = mfma_f64(cur[I].y, cur[J].y, acr[p]);
+          aci[p] = mfma_f64(cur[I].y, cur[J].x, aci[p]);
+          aci[p] = mfma_f64(-cur[I].x, cur[J].y, aci[p]);
           ++p;
         }
       }
+#pragma unroll
+      for (int q = 0; q < 4 * NP; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+      }
+#pragma unroll
+      for (int I = 0; I < NT; ++I) cur[I] = nxt[I];
     }
   }
 #pragma unroll
@@ -913,52 +918,168 @@ __device__ __forceinline__ double2 ghat(const ItemDev& s1, const ItemDev& s2, in
   return make_double2(z.x * zeta, z.y * zeta);
 }
 
-// Gram of a non-leaf block row, one unit (column range x tile-pair subset) per wave.
+// Gram of a non-leaf block row, one unit (column range x tile block) per wave.
+// The wave loads the rows of its tiles for 4 columns per k-step (software
+// pipelined one k-step ahead) and accumulates the tile pairs of its block.
+template <int NA, int NB, bool DIAG>
+__device__ void gram_inner_wave(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
+                                const UnitDev& u, double zeta, double2* out) {
+  constexpr int NP = DIAG ? NA * (NA + 1) / 2 : NA * NB;
+  constexpr int NL = DIAG ? 0 : NB;
+  int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  int r = it.r;
+  dvec4 acr[NP], aci[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    acr[p] = dvec4{0, 0, 0, 0};
+    aci[p] = dvec4{0, 0, 0, 0};
+  }
+  int64_t jb = it.col_off + u.col_begin;
+  int64_t nc4 = (u.ncols + 3) & ~int64_t(3);
+  double2 ca[NA], cb[NL > 0 ? NL : 1];
+  auto load = [&](int64_t c, double2* a, double2* b) {
+    bool cv = c < u.ncols;
+    int64_t j = jb + c;
+#pragma unroll
+    for (int I = 0; I < NA; ++I)
+      a[I] = cv ? ghat(s1, s2, j, 16 * (u.a0 + I) + row, r, zeta) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int J = 0; J < NL; ++J)
+      b[J] = cv ? ghat(s1, s2, j, 16 * (u.b0 + J) + row, r, zeta) : make_double2(0.0, 0.0);
+  };
+  load(kq, ca, cb);
+  for (int64_t c = kq; c < nc4; c += 4) {
+    double2 na_[NA], nb_[NL > 0 ? NL : 1];
+    load(c + 4, na_, nb_);
+    int p = 0;
+#pragma unroll
+    for (int I = 0; I < NA; ++I) {
+#pragma unroll
+      for (int J = 0; J < (DIAG ? I + 1 : NB); ++J) {
+        double2 x = ca[I];
+        double2 y = DIAG ? ca[J] : cb[J];
+        acr[p] = mfma_f64(x.x, y.x, acr[p]);
+        acr[p] = mfma_f64(x.y, y.y, acr[p]);
+        aci[p] = mfma_f64(x.y, y.x, aci[p]);
+        aci[p] = mfma_f64(-x.x, y.y, aci[p]);
+        ++p;
+      }
+    }
+#pragma unroll
+    for (int I = 0; I < NA; ++I) ca[I] = na_[I];
+#pragma unroll
+    for (int J = 0; J < NL; ++J) cb[J] = nb_[J];
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[p][v], aci[p][v]);
+}
+
 __global__ __launch_bounds__(256) void k_gram_inner_w(const ItemDev* items, const UnitDev* units,
                                                       int64_t nunits, double zeta,
                                                       double2* partial) {
-  constexpr int kMaxPairs = 10;
-  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  int w = threadIdx.x >> 6;
   int64_t ui = (int64_t)blockIdx.x * 4 + w;
   if (ui >= nunits) return;
   const UnitDev u = units[ui];
   const ItemDev& it = items[u.item];
   const ItemDev& s1 = items[it.son[0]];
   const ItemDev& s2 = items[it.son[1]];
-  int r = it.r;
-  int pi_[kMaxPairs], pj_[kMaxPairs];
-  dvec4 acr[kMaxPairs], aci[kMaxPairs];
-#pragma unroll
-  for (int q = 0; q < kMaxPairs; ++q) {
-    int I = 0, J = 0;
-    if (q < u.pair_count) pair_ij(u.pair_begin + q, I, J);
-    pi_[q] = 16 * I + row;
-    pj_[q] = 16 * J + row;
-    acr[q] = dvec4{0, 0, 0, 0};
-    aci[q] = dvec4{0, 0, 0, 0};
-  }
-  int64_t jb = it.col_off + u.col_begin;
-  for (int64_t c = kq; c < ((u.ncols + 3) & ~int64_t(3)); c += 4) {
-    bool cv = c < u.ncols;
-    int64_t j = jb + c;
-#pragma unroll
-    for (int q = 0; q < kMaxPairs; ++q) {
-      if (q < u.pair_count) {
-        double2 a = cv ? ghat(s1, s2, j, pi_[q], r, zeta) : make_double2(0.0, 0.0);
-        double2 b = cv ? ghat(s1, s2, j, pj_[q], r, zeta) : make_double2(0.0, 0.0);
-        acr[q] = mfma_f64(a.x, b.x, acr[q]);
-        acr[q] = mfma_f64(a.y, b.y, acr[q]);
-        aci[q] = mfma_f64(a.y, b.x, aci[q]);
-        aci[q] = mfma_f64(-a.x, b.y, aci[q]);
+  double2* out = partial + u.slot_off;
+  if (u.a0 == u.b0) {
+    switch (u.na) {
+      case 1: gram_inner_wave<1, 1, true>(it, s1, s2, u, zeta, out); break;
+      case 2: gram_inner_wave<2, 2, true>(it, s1, s2, u, zeta, out); break;
+      case 3: gram_inner_wave<3, 3, true>(it, s1, s2, u, zeta, out); break;
+      default: gram_inner_wave<4, 4, true>(it, s1, s2, u, zeta, out); break;
+    }
+  } else {
+    if (u.na == 1) {
+      switch (u.nb) {
+        case 1: gram_inner_wave<1, 1, false>(it, s1, s2, u, zeta, out); break;
+        case 2: gram_inner_wave<1, 2, false>(it, s1, s2, u, zeta, out); break;
+        case 3: gram_inner_wave<1, 3, false>(it, s1, s2, u, zeta, out); break;
+        default: gram_inner_wave<1, 4, false>(it, s1, s2, u, zeta, out); break;
+      }
+    } else {
+      switch (u.nb) {
+        case 1: gram_inner_wave<2, 1, false>(it, s1, s2, u, zeta, out); break;
+        case 2: gram_inner_wave<2, 2, false>(it, s1, s2, u, zeta, out); break;
+        case 3: gram_inner_wave<2, 3, false>(it, s1, s2, u, zeta, out); break;
+        default: gram_inner_wave<2, 4, false>(it, s1, s2, u, zeta, out); break;
       }
     }
   }
-  double2* out = partial + u.slot_off;
+}
+
+// R^T of a non-leaf block row, one unit (column range) per wave:
+// R^T[j][kk] = sum_rho G_hat[rho][j] conj(Q_hat[rho][kk]); operands loaded
+// directly (G_hat one k-step ahead), Q_hat rows from L1/L2.
+template <int KT>
+__device__ void rprod_inner_wave(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
+                                 const UnitDev& u, double zeta) {
+  int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  int r = it.r, k = it.k;
+  int nks = (r + 3) / 4;
+  for (int64_t j0 = 0; j0 < u.ncols; j0 += 16) {
+    bool valid = j0 + row < u.ncols;
+    int64_t jc = it.col_off + u.col_begin + j0 + row;
+    dvec4 acr[KT], aci[KT];
 #pragma unroll
-  for (int q = 0; q < kMaxPairs; ++q)
-    if (q < u.pair_count)
+    for (int t = 0; t < KT; ++t) {
+      acr[t] = dvec4{0, 0, 0, 0};
+      aci[t] = dvec4{0, 0, 0, 0};
+    }
+    double2 a = valid ? ghat(s1, s2, jc, kq, r, zeta) : make_double2(0.0, 0.0);
+    for (int ks = 0; ks < nks; ++ks) {
+      int rho = 4 * ks + kq;
+      double2 an = (valid && ks + 1 < nks) ? ghat(s1, s2, jc, rho + 4, r, zeta)
+                                           : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(q * 4 + v) * 64 + lane] = make_double2(acr[q][v], aci[q][v]);
+      for (int t = 0; t < KT; ++t) {
+        int kk = 16 * t + row;
+        double2 q = (rho < r && kk < k) ? it.Q[(int64_t)rho * k + kk] : make_double2(0.0, 0.0);
+        acr[t] = mfma_f64(a.x, q.x, acr[t]);
+        acr[t] = mfma_f64(a.y, q.y, acr[t]);
+        aci[t] = mfma_f64(a.y, q.x, aci[t]);
+        aci[t] = mfma_f64(-a.x, q.y, aci[t]);
+      }
+      a = an;
+    }
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      int kk = 16 * t + row;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int64_t jl = j0 + f64_row(lane, v);
+        if (jl < u.ncols && kk < k)
+          it.R[(u.col_begin + jl) * k + kk] = make_double2(acr[t][v], aci[t][v]);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rprod_inner_w(const ItemDev* items, const UnitDev* units,
+                                                       int64_t nunits, double zeta) {
+  int w = threadIdx.x >> 6;
+  int64_t ui = (int64_t)blockIdx.x * 4 + w;
+  if (ui >= nunits) return;
+  const UnitDev u = units[ui];
+  const ItemDev& it = items[u.item];
+  if (it.k == 0) return;
+  const ItemDev& s1 = items[it.son[0]];
+  const ItemDev& s2 = items[it.son[1]];
+  switch ((it.k + 15) / 16) {
+    case 1: rprod_inner_wave<1>(it, s1, s2, u, zeta); break;
+    case 2: rprod_inner_wave<2>(it, s1, s2, u, zeta); break;
+    case 3: rprod_inner_wave<3>(it, s1, s2, u, zeta); break;
+    case 4: rprod_inner_wave<4>(it, s1, s2, u, zeta); break;
+    case 5: rprod_inner_wave<5>(it, s1, s2, u, zeta); break;
+    case 6: rprod_inner_wave<6>(it, s1, s2, u, zeta); break;
+    case 7: rprod_inner_wave<7>(it, s1, s2, u, zeta); break;
+    default: rprod_inner_wave<8>(it, s1, s2, u, zeta); break;
+  }
 }
 
 // R^T of a leaf block row: the workgroup's four waves share the item's factor
@@ -978,9 +1099,11 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
       acr[t] = dvec4{0, 0, 0, 0};
       aci[t] = dvec4{0, 0, 0, 0};
     }
+    double2 a = gen_entry<SRC>(g, rows[kq], cc, side);
     for (int ks = 0; ks < nks; ++ks) {
       int rho = 4 * ks + kq;
-      double2 a = gen_entry<SRC>(g, rows[rho], cc, side);
+      // next k-step's entry (rows array is padded past r)
+      double2 an = gen_entry<SRC>(g, rows[rho + 4], cc, side);
 #pragma unroll
       for (int t = 0; t < KT; ++t) {
         double2 q = Qs[rho * (16 * KT) + 16 * t + row];
@@ -990,6 +1113,12 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
         aci[t] = mfma_f64(a.y, q.x, aci[t]);
         aci[t] = mfma_f64(-a.x, q.y, aci[t]);
       }
+#pragma unroll
+      for (int q = 0; q < 4 * KT; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+      }
+      a = an;
     }
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
@@ -1009,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* 
                                                       const EntDev* ents, const UnitDev* units,
                                                       int side) {
   __shared__ double2 Qs[68 * 64];   // (r + 4) x (16 KT), zero padded rows past r
-  __shared__ RowData rows[64 + 4];
+  __shared__ RowData rows[64 + 8];
   const UnitDev u = units[blockIdx.x];
   const ItemDev& it = items[u.item];
   int r = it.r, k = it.k;
@@ -1020,7 +1149,7 @@ __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* 
     int i = e / ldq, kk = e - i * ldq;
     Qs[e] = (i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0);
   }
-  for (int i = threadIdx.x; i < 68; i += 256) rows[i] = row_data<SRC>(g, it, i, side);
+  for (int i = threadIdx.x; i < 72; i += 256) rows[i] = row_data<SRC>(g, it, i, side);
   __syncthreads();
   switch (kt) {
     case 1: rprod_leaf_wave<SRC, 1>(g, it, ents, side, u, Qs, rows); break;
@@ -1096,7 +1225,8 @@ void launch_rprod(int src, bool inner, const GeomDev& g, const ItemDev* items, c
   if (nunits == 0) return;
   dim3 grid((unsigned)nunits), blk(256);
   if (inner)
-    hipLaunchKernelGGL(k_rprod_inner, grid, blk, 0, st, items, units, zeta);
+    hipLaunchKernelGGL(k_rprod_inner_w, dim3(blocks_for(nunits, 4)), blk, 0, st, items, units,
+                       nunits, zeta);
   else if (src == SRC_HELMHOLTZ)
     hipLaunchKernelGGL(k_rprod_leaf_w<SRC_HELMHOLTZ>, grid, blk, 0, st, g, items, ents, units,
                        side);

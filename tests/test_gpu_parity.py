@@ -139,10 +139,15 @@ def test_near_field(problem, gpu):
     plan, ref = problem["plan"], problem["ref"]
     tr, bt = plan.tree, plan.blocks
     Gtp = gpu["Gt"][np.ix_(tr.perm, tr.perm)]
+    worst = 0.0
     for q in range(len(bt.near_t)):
         t, s = int(bt.near_t[q]), int(bt.near_s[q])
         blk = Gtp[np.ix_(tr.rows(t), tr.rows(s))]
-        assert np.allclose(blk, ref.near[q], rtol=0, atol=2e-15 * np.abs(ref.near[q]).max())
+        rel = np.abs(blk - ref.near[q]) / np.abs(ref.near[q])
+        worst = max(worst, float(rel.max()))
+    print(f"[gpu parity] near field max relative entry error {worst:.2e}", flush=True)
+    # each entry takes about ten roundings in FP64 on either side
+    assert worst <= 4e-15
 
 
 def test_global_error(problem, gpu):

@@ -122,3 +122,7 @@ def test_invalid_arguments():
     with pytest.raises(dh2.DH2Error) as e:
         dh2.tree_build(pts[:0], 1.0, o)
     assert e.value.code == -1
+    dup = np.vstack([pts, pts[17:18]])
+    with pytest.raises(dh2.DH2Error) as e:
+        dh2.tree_build(dup, 1.0, o)
+    assert e.value.code == -1 and "coincident" in str(e.value)
