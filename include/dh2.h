@@ -240,6 +240,12 @@ typedef struct {
   double t_gram_kernel;    /* summed device seconds of the Gram kernels      */
   int32_t groups;          /* subtree groups used                            */
   int32_t precision;
+  /* the leaf Gram kernel alone (the largest single kernel): algorithmic
+   * flops 4 r^2 N summed over its launches, summed device seconds measured
+   * with events on the call's stream, and the number of launches          */
+  double flops_gram_leaf, t_gram_leaf;
+  int32_t n_gram_leaf;
+  int32_t pad;
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_matrix m, dh2_stats* out);

@@ -428,6 +428,8 @@ struct PhaseTimer {
 struct SweepStats {
   double flops_gram = 0, flops_rprod = 0, flops_prj = 0;
   double t_gram = 0, t_prj = 0;
+  double flops_gram_leaf = 0, t_gram_leaf = 0;
+  int32_t n_gram_leaf = 0;
 };
 
 static int64_t npairs_of(int r) {
@@ -442,7 +444,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
   const ColumnSets& cs = B.cs[s];
   Side& S = M.side[s];
   DevMem& mem = *M.mem;
-  PhaseTimer tg(st), tp(st);
+  PhaseTimer tg(st), tp(st), tgl(st);
   double2* partial = nullptr;
   size_t partial_cap = 0;
 
@@ -530,7 +532,9 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
               units.push_back(u);
             }
             double rr = it.r;
-            ss.flops_gram += 4.0 * rr * rr * (double)std::min(width, it.N - c0);
+            double fl = 4.0 * rr * rr * (double)std::min(width, it.N - c0);
+            ss.flops_gram += fl;
+            if (it.leaf) ss.flops_gram_leaf += fl;
           }
         }
         if (pass == 0) nleafu = (int64_t)units.size();
@@ -546,8 +550,13 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       int32_t* d_ubegin = upload(mem, ubegin, st);
       tr_.mark("gram units", s, b, lv);
       tg.start();
-      launch_gram(M.src, false, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s, partial, st);
-      launch_check("gram (leaf)");
+      if (nleafu > 0) {
+        tgl.start();
+        launch_gram(M.src, false, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s, partial, st);
+        launch_check("gram (leaf)");
+        tgl.stop();
+        ss.n_gram_leaf += 1;
+      }
       launch_gram(M.src, true, g, S.d_items, S.d_ents, d_units + nleafu,
                   (int64_t)units.size() - nleafu, M.zeta, s, partial, st);
       launch_check("gram (non-leaf)");
@@ -672,6 +681,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
   mem.release(partial);
   ss.t_gram += tg.acc;
   ss.t_prj += tp.acc;
+  ss.t_gram_leaf += tgl.acc;
 }
 
 // expanded column bases, level by level from the leaves
@@ -944,6 +954,9 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   S.t_gram_kernel = ss_row.t_gram + ss_col.t_gram;
   S.groups = M.nbatch;
   S.precision = M.precision;
+  S.flops_gram_leaf = ss_row.flops_gram_leaf + ss_col.flops_gram_leaf;
+  S.t_gram_leaf = ss_row.t_gram_leaf + ss_col.t_gram_leaf;
+  S.n_gram_leaf = ss_row.n_gram_leaf + ss_col.n_gram_leaf;
   return Mp;
 }
 

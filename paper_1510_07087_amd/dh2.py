@@ -53,7 +53,9 @@ class Stats(C.Structure):
                 ("flops_row", C.c_double), ("flops_col", C.c_double),
                 ("flops_prj", C.c_double), ("flops_gram", C.c_double),
                 ("flops_rprod", C.c_double), ("t_gram_kernel", C.c_double),
-                ("groups", C.c_int32), ("precision", C.c_int32)]
+                ("groups", C.c_int32), ("precision", C.c_int32),
+                ("flops_gram_leaf", C.c_double), ("t_gram_leaf", C.c_double),
+                ("n_gram_leaf", C.c_int32), ("pad", C.c_int32)]
 
 
 EXPORTED = [
