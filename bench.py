@@ -155,6 +155,10 @@ def main():
         res[form] = dict(s=s, gflops=flops / s / 1e9, stats=st, rows_rel=rows_rel, rel_err=err)
         log(f"[bench] {form}: {s:.3f} s, {flops / s / 1e9:.1f} GFLOP/s, rows {rows_rel:.2e}, "
             f"err {err}")
+        log(f"[bench] {form} flops: gram leaf {st['flops_gram_leaf']:.4e} "
+            f"inner {st['flops_gram'] - st['flops_gram_leaf']:.4e}; rprod leaf "
+            f"{st['flops_rprod_leaf']:.4e} inner {st['flops_rprod'] - st['flops_rprod_leaf']:.4e}; "
+            f"projection {st['flops_prj']:.4e}")
         del m
     head = "mixed" if "mixed" in res else forms[0]
     r = res[head]

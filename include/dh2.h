@@ -246,6 +246,7 @@ typedef struct {
   double flops_gram_leaf, t_gram_leaf;
   int32_t n_gram_leaf;
   int32_t pad;
+  double flops_rprod_leaf;   /* R-product flops of leaf block rows */
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_matrix m, dh2_stats* out);

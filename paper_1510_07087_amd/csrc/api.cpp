@@ -257,7 +257,6 @@ dh2_status dh2_compress_helmholtz(dh2_blocks b, const double* w, double eps, con
     if (w)
       for (int64_t i = 0; i < n; ++i)
         if (!(w[i] > 0) || !std::isfinite(w[i])) fail(DH2_EINVAL, "weights must be finite and > 0");
-    if (opts->precision != DH2_FP64) fail(DH2_EUNSUPPORTED, "mixed precision not built yet");
     auto m = compress(b->d, SRC_HELMHOLTZ, nullptr, 0, w, eps, *opts, stream_of(stream));
     *out = new dh2_matrix_s{std::move(m)};
   })

@@ -28,7 +28,7 @@ struct ItemDev {
   int64_t ent_begin; // leaf: first column-set entry
   int64_t ent_end;
   int64_t col_off;   // non-leaf: offset of F_tc inside the sons' sets
-  double2* R;        // R^T (N x k, complex), in the arena of its level
+  void* R;           // R^T (N x k, complex FP64 or FP32), in the arena of its level
   double2* M;        // Gram (r x r, column-major)
   double2* Q;        // factor: r x k row-major (leaf: Q_tc, other: [E_t1c; E_t2c])
   double* sig;       // singular values (r)
@@ -64,7 +64,7 @@ struct UnitDev {
 
 // Projection task: S_b = omega_b * (R_tc restricted to the columns of s) * Wexp_sc.
 struct ProjDev {
-  const double2* R;   // R^T rows of the block (|s| x kt)
+  const void* R;      // R^T rows of the block (|s| x kt), complex FP64 or FP32
   const double2* W;   // expanded column basis (|s| x ks row-major)
   double2* S;         // output (kt x ks column-major)
   int32_t kt, ks;

@@ -428,7 +428,7 @@ struct PhaseTimer {
 struct SweepStats {
   double flops_gram = 0, flops_rprod = 0, flops_prj = 0;
   double t_gram = 0, t_prj = 0;
-  double flops_gram_leaf = 0, t_gram_leaf = 0;
+  double flops_gram_leaf = 0, t_gram_leaf = 0, flops_rprod_leaf = 0;
   int32_t n_gram_leaf = 0;
 };
 
@@ -447,6 +447,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
   PhaseTimer tg(st), tp(st), tgl(st);
   double2* partial = nullptr;
   size_t partial_cap = 0;
+  const bool mixed = M.precision == DH2_MIXED;
 
   Trace tr_;
   for (int32_t b = 0; b < M.nbatch; ++b) {
@@ -552,12 +553,13 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       tg.start();
       if (nleafu > 0) {
         tgl.start();
-        launch_gram(M.src, false, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s, partial, st);
+        launch_gram(M.src, false, mixed, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s,
+                    partial, st);
         launch_check("gram (leaf)");
         tgl.stop();
         ss.n_gram_leaf += 1;
       }
-      launch_gram(M.src, true, g, S.d_items, S.d_ents, d_units + nleafu,
+      launch_gram(M.src, true, mixed, g, S.d_items, S.d_ents, d_units + nleafu,
                   (int64_t)units.size() - nleafu, M.zeta, s, partial, st);
       launch_check("gram (non-leaf)");
       tg.stop();
@@ -578,11 +580,13 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       // coefficient matrices R of this level
       int64_t sumNk = 0;
       for (int32_t i = lo; i < hi; ++i) sumNk += S.items[i].N * S.items[i].k;
-      double2* Rarena = (double2*)mem.alloc(sumNk * sizeof(double2));
+      // R^T in complex FP64, or complex FP32 in the mixed form
+      size_t esz = mixed ? 2 * sizeof(float) : sizeof(double2);
+      char* Rarena = (char*)mem.alloc(sumNk * esz);
       {
         int64_t o = 0;
         for (int32_t i = lo; i < hi; ++i) {
-          S.items[i].R = Rarena + o;
+          S.items[i].R = Rarena + o * esz;
           o += S.items[i].N * S.items[i].k;
         }
       }
@@ -603,15 +607,16 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
             ru.push_back(u);
           }
           ss.flops_rprod += 8.0 * it.k * (double)it.r * (double)it.N;
+          if (it.leaf) ss.flops_rprod_leaf += 8.0 * it.k * (double)it.r * (double)it.N;
         }
         if (pass == 0) nleafr = (int64_t)ru.size();
       }
       UnitDev* d_ru = upload(mem, ru, st);
       tr_.mark("rprod units", s, b, lv);
-      launch_rprod(M.src, false, g, S.d_items, S.d_ents, d_ru, nleafr, M.zeta, s, st);
+      launch_rprod(M.src, false, mixed, g, S.d_items, S.d_ents, d_ru, nleafr, M.zeta, s, st);
       launch_check("rprod (leaf)");
-      launch_rprod(M.src, true, g, S.d_items, S.d_ents, d_ru + nleafr, (int64_t)ru.size() - nleafr,
-                   M.zeta, s, st);
+      launch_rprod(M.src, true, mixed, g, S.d_items, S.d_ents, d_ru + nleafr,
+                   (int64_t)ru.size() - nleafr, M.zeta, s, st);
       launch_check("rprod (non-leaf)");
       if (trace_on()) hip_check(hipStreamSynchronize(st), "trace sync");
       tr_.mark("rprod", s, b, lv);
@@ -642,7 +647,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
             int32_t wi = M.side[1].ext2int[we];
             int32_t ks = M.side[1].items[wi].k;
             ProjDev pd{};
-            pd.R = it.R + S.ent_col[q] * it.k;
+            pd.R = (const char*)it.R + S.ent_col[q] * it.k * esz;
             pd.W = M.side[1].wexp[wi];
             pd.S = Sarena + o;
             pd.kt = it.k;
@@ -657,11 +662,46 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
             if (it.k > 0 && ks > 0) tasks.push_back(pd);
           }
         }
-        ProjDev* d_tasks = upload(mem, tasks, st);
+        // tiled kernel for ks <= 64, one launch per (row tiles per pass,
+        // column tiles), each sorted by expanded basis for L2 reuse; the
+        // rest (ranks above 64) by the generic kernel
+        std::vector<ProjDev> sorted;
+        std::vector<std::array<int64_t, 3>> launches;  // ni, nj, count
+        {
+          std::vector<ProjDev> bucket[5][5];
+          for (const ProjDev& pd : tasks) {
+            int nj = (pd.ks + 15) / 16, ni = (pd.kt + 15) / 16;
+            if (nj > 4) {
+              bucket[0][0].push_back(pd);
+              continue;
+            }
+            ni = std::min(ni, project_rows_per_pass(mixed, nj));
+            bucket[ni][nj].push_back(pd);
+          }
+          for (int ni = 1; ni <= 4; ++ni)
+            for (int nj = 1; nj <= 4; ++nj) {
+              auto& v = bucket[ni][nj];
+              if (v.empty()) continue;
+              std::stable_sort(v.begin(), v.end(),
+                               [](const ProjDev& x, const ProjDev& y) { return x.W < y.W; });
+              sorted.insert(sorted.end(), v.begin(), v.end());
+              launches.push_back({ni, nj, (int64_t)v.size()});
+            }
+          sorted.insert(sorted.end(), bucket[0][0].begin(), bucket[0][0].end());
+          launches.push_back({0, 0, (int64_t)bucket[0][0].size()});
+        }
+        ProjDev* d_tasks = upload(mem, sorted, st);
         tr_.mark("proj tasks", s, b, lv);
         tp.start();
-        launch_project(d_tasks, (int64_t)tasks.size(), M.d_omega, st);
-        launch_check("project");
+        int64_t off = 0;
+        for (const auto& L : launches) {
+          if (L[0] > 0)
+            launch_project_tiled(mixed, (int)L[0], (int)L[1], d_tasks + off, L[2], M.d_omega, st);
+          else
+            launch_project(mixed, d_tasks + off, L[2], M.d_omega, st);
+          launch_check("project");
+          off += L[2];
+        }
         tp.stop();
         tr_.mark("project", s, b, lv);
         mem.release(d_tasks);
@@ -957,6 +997,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   S.flops_gram_leaf = ss_row.flops_gram_leaf + ss_col.flops_gram_leaf;
   S.t_gram_leaf = ss_row.t_gram_leaf + ss_col.t_gram_leaf;
   S.n_gram_leaf = ss_row.n_gram_leaf + ss_col.n_gram_leaf;
+  S.flops_rprod_leaf = ss_row.flops_rprod_leaf + ss_col.flops_rprod_leaf;
   return Mp;
 }
 

@@ -30,6 +30,27 @@ __device__ __forceinline__ dvec4 mfma_f64(double a, double b, dvec4 c) {
 // (16 x 4): lane l holds A[l % 16][l / 16]; operand B (4 x 16): B[l / 16][l % 16].
 __device__ __forceinline__ int f64_row(int lane, int v) { return (lane >> 4) + 4 * v; }
 
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ fvec4 mfma_f32(float a, float b, fvec4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Output layout of the FP32 16x16x4 MFMA (measured on gfx950): register v of
+// lane l holds row 4 (l / 16) + v, column l % 16; operands as for FP64.
+__device__ __forceinline__ int f32_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+
+// complex element of an R^T array stored in FP64 (MX false) or FP32 (MX true)
+template <bool MX>
+__device__ __forceinline__ double2 rload(const void* R, int64_t idx) {
+  if constexpr (MX) {
+    float2 v = reinterpret_cast<const float2*>(R)[idx];
+    return make_double2(v.x, v.y);
+  } else {
+    return reinterpret_cast<const double2*>(R)[idx];
+  }
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -82,6 +103,33 @@ __device__ __forceinline__ void sincos_phase(double x, double& s, double& c) {
     sincos_cw(x, s, c);
   else
     sincos(x, &s, &c);
+}
+
+// Mixed precision: the same Cody-Waite reduction in FP64 (two parts suffice
+// at FP32 accuracy), then Taylor polynomials of degree 11/10 in FP32
+// (truncation below 1e-10 on |y| <= pi/4).
+__device__ __forceinline__ void sincos_mixed(double x, float& s, float& c) {
+  double n = rint(x * 0.6366197723675814);
+  double y = fma(-n, 0x1.921fb544p+0, x);
+  y = fma(-n, 0x1.0b4611a6p-34, y);
+  float yf = (float)y;
+  float y2 = yf * yf;
+  float ps = -2.5052108e-08f;                // -1/11!
+  ps = fmaf(ps, y2, 2.7557319e-06f);          // 1/9!
+  ps = fmaf(ps, y2, -1.9841270e-04f);         // -1/7!
+  ps = fmaf(ps, y2, 8.3333333e-03f);          // 1/5!
+  ps = fmaf(ps, y2, -1.6666667e-01f);         // -1/3!
+  float sy = fmaf(ps * y2, yf, yf);
+  float pc = -2.7557319e-07f;                // -1/10!
+  pc = fmaf(pc, y2, 2.4801587e-05f);          // 1/8!
+  pc = fmaf(pc, y2, -1.3888889e-03f);         // -1/6!
+  pc = fmaf(pc, y2, 4.1666667e-02f);          // 1/4!
+  pc = fmaf(pc, y2, -0.5f);                   // -1/2!
+  float cy = fmaf(pc, y2, 1.0f);
+  int q = (int)((long long)n & 3);
+  float ss = (q & 1) ? cy : sy, cc = (q & 1) ? sy : cy;
+  s = (q & 2) ? -ss : ss;
+  c = ((q + 1) & 2) ? -cc : cc;
 }
 
 // 1/sqrt(r2) to about half an ulp: hardware estimate refined by one Newton
@@ -456,11 +504,6 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
 }
 
 // ---------------------------------------------------------------------------
-// R^T (N x k) of a block row: R_tc = Q^* A, i.e. R^T[j][kk] = sum_rho
-// A[rho][j] conj(Q[rho][kk]).  Output tiles (16 columns x 16 ranks) are split
-// over the waves.
-// ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
 // Expansion of the column basis: dst rows = src (rows x ks) * E (ks x k).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_expand(const ExpandDev* tasks) {
@@ -488,8 +531,38 @@ __global__ void k_copy_c(const double2* src, int64_t src_off, double2* dst, int6
 }
 
 // ---------------------------------------------------------------------------
-// Projection: S_b = omega_b * R_tc[o.. o+|s|)^T^T * Wexp_sc, one wave per block.
+// Projection: S_b = omega_b (R_tc restricted to the columns of s) Wexp_sc,
+// one wave per block; FP32 MFMA in the mixed form.
 // ---------------------------------------------------------------------------
+template <bool MX>
+struct SAcc;
+template <>
+struct SAcc<false> {
+  dvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+  __device__ __forceinline__ void mac(double2 a, double2 b) {  // a b
+    re = mfma_f64(a.x, b.x, re);
+    re = mfma_f64(-a.y, b.y, re);
+    im = mfma_f64(a.x, b.y, im);
+    im = mfma_f64(a.y, b.x, im);
+  }
+  __device__ __forceinline__ int row(int lane, int v) const { return f64_row(lane, v); }
+  __device__ __forceinline__ double2 get(int v) const { return make_double2(re[v], im[v]); }
+};
+template <>
+struct SAcc<true> {
+  fvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+  __device__ __forceinline__ void mac(double2 a, double2 b) {
+    float ar = (float)a.x, ai = (float)a.y, br = (float)b.x, bi = (float)b.y;
+    re = mfma_f32(ar, br, re);
+    re = mfma_f32(-ai, bi, re);
+    im = mfma_f32(ar, bi, im);
+    im = mfma_f32(ai, br, im);
+  }
+  __device__ __forceinline__ int row(int lane, int v) const { return f32_row(lane, v); }
+  __device__ __forceinline__ double2 get(int v) const { return make_double2(re[v], im[v]); }
+};
+
+template <bool MX>
 __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t ntasks,
                                                  const double* omega) {
   int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -500,30 +573,20 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
   if (kt == 0 || ks == 0) return;
   double om = omega[t.b];
   int nti = (kt + 15) / 16, ntj = (ks + 15) / 16;
-  const double2* Rb = t.R;
   const double2* Wb = t.W;
   double2* Sb = t.S;
   for (int ti16 = 0; ti16 < nti; ++ti16) {
-    dvec4 acr[8], aci[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      acr[q] = dvec4{0, 0, 0, 0};
-      aci[q] = dvec4{0, 0, 0, 0};
-    }
+    SAcc<MX> acc[8];
     int ii = ti16 * 16 + row;
     for (int j0 = 0; j0 < t.ns; j0 += 4) {
       int j = j0 + kq;
-      double2 a = (j < t.ns && ii < kt) ? Rb[(int64_t)j * kt + ii] : make_double2(0.0, 0.0);
+      double2 a = (j < t.ns && ii < kt) ? rload<MX>(t.R, (int64_t)j * kt + ii) : make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         if (q < ntj) {
           int jj = q * 16 + row;
           double2 b = (j < t.ns && jj < ks) ? Wb[(int64_t)j * ks + jj] : make_double2(0.0, 0.0);
-          // R W: re = ar br - ai bi, im = ar bi + ai br
-          acr[q] = mfma_f64(a.x, b.x, acr[q]);
-          acr[q] = mfma_f64(-a.y, b.y, acr[q]);
-          aci[q] = mfma_f64(a.x, b.y, aci[q]);
-          aci[q] = mfma_f64(a.y, b.x, aci[q]);
+          acc[q].mac(a, b);
         }
       }
     }
@@ -532,12 +595,131 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
       if (q < ntj) {
         int jj = q * 16 + row;
         for (int v = 0; v < 4; ++v) {
-          int i = ti16 * 16 + f64_row(lane, v);
-          if (i < kt && jj < ks) Sb[i + (int64_t)jj * kt] = make_double2(om * acr[q][v], om * aci[q][v]);
+          int i = ti16 * 16 + acc[q].row(lane, v);
+          double2 z = acc[q].get(v);
+          if (i < kt && jj < ks) Sb[i + (int64_t)jj * kt] = make_double2(om * z.x, om * z.y);
         }
       }
     }
   }
+}
+
+// Tiled projection for blocks with ks <= 64: one wave per (block, pass over
+// NI row tiles), all NI x NJ tile pairs accumulated in registers over one
+// sweep of the columns of s, operands loaded one k-step ahead.  Workgroups
+// are mapped so that the workgroups on one XCD take a contiguous range of
+// the (W-sorted) task list and share the expanded bases in their L2.
+template <bool MX>
+struct POp;
+template <>
+struct POp<false> {
+  double re, im, nim;
+};
+template <>
+struct POp<true> {
+  float re, im, nim;
+};
+
+template <bool MX>
+__device__ __forceinline__ POp<MX> pop_make(double2 v) {
+  POp<MX> o;
+  o.re = v.x;
+  o.im = v.y;
+  o.nim = -o.im;
+  return o;
+}
+
+template <bool MX>
+struct PAcc;
+template <>
+struct PAcc<false> {
+  dvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+  __device__ __forceinline__ void mac(const POp<false>& a, const POp<false>& b) {
+    re = mfma_f64(a.re, b.re, re);
+    re = mfma_f64(a.nim, b.im, re);
+    im = mfma_f64(a.re, b.im, im);
+    im = mfma_f64(a.im, b.re, im);
+  }
+  __device__ __forceinline__ int row(int lane, int v) const { return f64_row(lane, v); }
+  __device__ __forceinline__ double2 get(int v) const { return make_double2(re[v], im[v]); }
+};
+template <>
+struct PAcc<true> {
+  fvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+  __device__ __forceinline__ void mac(const POp<true>& a, const POp<true>& b) {
+    re = mfma_f32(a.re, b.re, re);
+    re = mfma_f32(a.nim, b.im, re);
+    im = mfma_f32(a.re, b.im, im);
+    im = mfma_f32(a.im, b.re, im);
+  }
+  __device__ __forceinline__ int row(int lane, int v) const { return f32_row(lane, v); }
+  __device__ __forceinline__ double2 get(int v) const { return make_double2(re[v], im[v]); }
+};
+
+template <bool MX, int NI, int NJ>
+__device__ void proj_wave(const ProjDev& t, int ti0, double om) {
+  int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  const int kt = t.kt, ks = t.ks, ns = t.ns;
+  PAcc<MX> acc[NI][NJ];
+  POp<MX> a[NI], b[NJ];
+  auto load = [&](int j, POp<MX>* aa, POp<MX>* bb) {
+#pragma unroll
+    for (int I = 0; I < NI; ++I) {
+      int ii = 16 * (ti0 + I) + row;
+      aa[I] = pop_make<MX>((j < ns && ii < kt) ? rload<MX>(t.R, (int64_t)j * kt + ii)
+                                                : make_double2(0.0, 0.0));
+    }
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) {
+      int jj = 16 * J + row;
+      bb[J] = pop_make<MX>((j < ns && jj < ks) ? t.W[(int64_t)j * ks + jj] : make_double2(0.0, 0.0));
+    }
+  };
+  load(kq, a, b);
+  for (int j0 = 0; j0 < ns; j0 += 4) {
+    POp<MX> an[NI], bn[NJ];
+    load(j0 + 4 + kq, an, bn);
+#pragma unroll
+    for (int I = 0; I < NI; ++I)
+#pragma unroll
+      for (int J = 0; J < NJ; ++J) acc[I][J].mac(a[I], b[J]);
+#pragma unroll
+    for (int I = 0; I < NI; ++I) a[I] = an[I];
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) b[J] = bn[J];
+  }
+  double2* Sb = t.S;
+#pragma unroll
+  for (int I = 0; I < NI; ++I)
+#pragma unroll
+    for (int J = 0; J < NJ; ++J) {
+      int jj = 16 * J + row;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i = 16 * (ti0 + I) + acc[I][J].row(lane, v);
+        double2 z = acc[I][J].get(v);
+        if (i < kt && jj < ks) Sb[i + (int64_t)jj * kt] = make_double2(om * z.x, om * z.y);
+      }
+    }
+}
+
+// Tasks of one launch share (NI, NJ): NJ = column tiles, NI = row tiles per
+// pass (the register budget allows at most 16 mixed or 8 FP64 tile pairs).
+template <bool MX, int NI, int NJ>
+__global__ __launch_bounds__(256) void k_project_tiled(const ProjDev* tasks, int64_t ntasks,
+                                                       const double* omega) {
+  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
+  // contiguous range of workgroup slots
+  unsigned nb = gridDim.x, b = blockIdx.x;
+  unsigned x = b & 7u, loc = b >> 3, q = nb >> 3, rmd = nb & 7u;
+  unsigned slot = x * q + (x < rmd ? x : rmd) + loc;
+  int64_t ti = (int64_t)slot * 4 + (threadIdx.x >> 6);
+  if (ti >= ntasks) return;
+  const ProjDev t = tasks[ti];
+  if (t.kt == 0 || t.ks == 0) return;
+  double om = omega[t.b];
+  int nti = (t.kt + 15) / 16;
+  for (int ti0 = 0; ti0 < nti; ti0 += NI) proj_wave<MX, NI, NJ>(t, ti0, om);
 }
 
 // ---------------------------------------------------------------------------
@@ -740,8 +922,9 @@ __global__ __launch_bounds__(256) void k_direct(GeomDev g, const int64_t* rows, 
 
 // ---------------------------------------------------------------------------
 // Wave-level pipelines.  Each wave owns a work unit and builds exactly the
-// MFMA operands it consumes: no block barriers, so entry generation (VALU)
-// of one k-step overlaps the MFMAs of the previous one.
+// MFMA operands it consumes: no block barriers.  MX selects the mixed form:
+// entries with FP32 polynomials, R stored in complex FP32, R-products on
+// FP32 MFMA; Gram matrices are accumulated in FP64 in both forms.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -806,7 +989,7 @@ __device__ __forceinline__ RowData row_data(const GeomDev& g, const ItemDev& it,
 }
 
 // entry of the weighted block row from staged row and column data
-template <int SRC>
+template <int SRC, bool MX>
 __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw, double4 cc,
                                              int side) {
   double f = rw.f * cc.w;
@@ -815,10 +998,17 @@ __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw
     double dx = rw.x - cc.x, dy = rw.y - cc.y, dz = rw.z - cc.z;
     double r2 = dx * dx + dy * dy + dz * dz;
     double ri = rsqrt_nr(r2);
-    double sn, cs;
-    sincos_phase(g.kappa * (r2 * ri), sn, cs);
-    double a = f * ri;
-    return make_double2(a * cs, side == 0 ? a * sn : -a * sn);
+    if constexpr (MX) {
+      float sn, cs;
+      sincos_mixed(g.kappa * (r2 * ri), sn, cs);
+      float a = (float)(f * ri);
+      return make_double2(a * cs, side == 0 ? a * sn : -a * sn);
+    } else {
+      double sn, cs;
+      sincos_phase(g.kappa * (r2 * ri), sn, cs);
+      double a = f * ri;
+      return make_double2(a * cs, side == 0 ? a * sn : -a * sn);
+    }
   } else {
     const double2* G = reinterpret_cast<const double2*>(g.G);
     int64_t i = (int64_t)__double_as_longlong(rw.x), j = (int64_t)__double_as_longlong(cc.x);
@@ -830,7 +1020,7 @@ __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw
 // Gram of a leaf block row, one unit per wave, all lower tile pairs.  The
 // entries of k-step s+1 are generated while the MFMAs of k-step s issue; the
 // scheduling hints interleave one MFMA with a group of VALU instructions.
-template <int SRC, int NT>
+template <int SRC, bool MX, int NT>
 __device__ void gram_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
                                const UnitDev& u, double2* out, double4* cl) {
   constexpr int NP = NT * (NT + 1) / 2;
@@ -854,7 +1044,7 @@ __device__ void gram_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev
     {
       double4 cc = cl[kq];
 #pragma unroll
-      for (int I = 0; I < NT; ++I) cur[I] = gen_entry<SRC>(g, rw[I], cc, side);
+      for (int I = 0; I < NT; ++I) cur[I] = gen_entry<SRC, MX>(g, rw[I], cc, side);
     }
     for (int ks = 0; ks < nks; ++ks) {
       double2 nxt[NT];
@@ -862,7 +1052,7 @@ __device__ void gram_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev
       bool more = ks + 1 < nks;
 #pragma unroll
       for (int I = 0; I < NT; ++I)
-        nxt[I] = more ? gen_entry<SRC>(g, rw[I], cn, side) : make_double2(0.0, 0.0);
+        nxt[I] = more ? gen_entry<SRC, MX>(g, rw[I], cn, side) : make_double2(0.0, 0.0);
       int p = 0;
 #pragma unroll
       for (int I = 0; I < NT; ++I) {
@@ -890,7 +1080,7 @@ __device__ void gram_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev
     for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[p][v], aci[p][v]);
 }
 
-template <int SRC>
+template <int SRC, bool MX>
 __global__ __launch_bounds__(256) void k_gram_leaf_w(GeomDev g, const ItemDev* items,
                                                      const EntDev* ents, const UnitDev* units,
                                                      int64_t nunits, int side, double2* partial) {
@@ -903,25 +1093,26 @@ __global__ __launch_bounds__(256) void k_gram_leaf_w(GeomDev g, const ItemDev* i
   int nt = (it.r + 15) / 16;
   double2* out = partial + u.slot_off;
   switch (nt) {
-    case 1: gram_leaf_wave<SRC, 1>(g, it, ents, side, u, out, cls[w]); break;
-    case 2: gram_leaf_wave<SRC, 2>(g, it, ents, side, u, out, cls[w]); break;
-    case 3: gram_leaf_wave<SRC, 3>(g, it, ents, side, u, out, cls[w]); break;
-    default: gram_leaf_wave<SRC, 4>(g, it, ents, side, u, out, cls[w]); break;
+    case 1: gram_leaf_wave<SRC, MX, 1>(g, it, ents, side, u, out, cls[w]); break;
+    case 2: gram_leaf_wave<SRC, MX, 2>(g, it, ents, side, u, out, cls[w]); break;
+    case 3: gram_leaf_wave<SRC, MX, 3>(g, it, ents, side, u, out, cls[w]); break;
+    default: gram_leaf_wave<SRC, MX, 4>(g, it, ents, side, u, out, cls[w]); break;
   }
 }
 
 // Row rho of G_hat_tc = zeta [R_t1c' ; R_t2c'] at column j (0 outside).
+template <bool MX>
 __device__ __forceinline__ double2 ghat(const ItemDev& s1, const ItemDev& s2, int64_t j, int rho,
                                         int r, double zeta) {
   if (rho >= r) return make_double2(0.0, 0.0);
-  double2 z = rho < s1.k ? s1.R[j * s1.k + rho] : s2.R[j * s2.k + (rho - s1.k)];
+  double2 z = rho < s1.k ? rload<MX>(s1.R, j * s1.k + rho) : rload<MX>(s2.R, j * s2.k + (rho - s1.k));
   return make_double2(z.x * zeta, z.y * zeta);
 }
 
 // Gram of a non-leaf block row, one unit (column range x tile block) per wave.
 // The wave loads the rows of its tiles for 4 columns per k-step (software
 // pipelined one k-step ahead) and accumulates the tile pairs of its block.
-template <int NA, int NB, bool DIAG>
+template <bool MX, int NA, int NB, bool DIAG>
 __device__ void gram_inner_wave(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
                                 const UnitDev& u, double zeta, double2* out) {
   constexpr int NP = DIAG ? NA * (NA + 1) / 2 : NA * NB;
@@ -942,10 +1133,10 @@ __device__ void gram_inner_wave(const ItemDev& it, const ItemDev& s1, const Item
     int64_t j = jb + c;
 #pragma unroll
     for (int I = 0; I < NA; ++I)
-      a[I] = cv ? ghat(s1, s2, j, 16 * (u.a0 + I) + row, r, zeta) : make_double2(0.0, 0.0);
+      a[I] = cv ? ghat<MX>(s1, s2, j, 16 * (u.a0 + I) + row, r, zeta) : make_double2(0.0, 0.0);
 #pragma unroll
     for (int J = 0; J < NL; ++J)
-      b[J] = cv ? ghat(s1, s2, j, 16 * (u.b0 + J) + row, r, zeta) : make_double2(0.0, 0.0);
+      b[J] = cv ? ghat<MX>(s1, s2, j, 16 * (u.b0 + J) + row, r, zeta) : make_double2(0.0, 0.0);
   };
   load(kq, ca, cb);
   for (int64_t c = kq; c < nc4; c += 4) {
@@ -976,6 +1167,7 @@ __device__ void gram_inner_wave(const ItemDev& it, const ItemDev& s1, const Item
     for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[p][v], aci[p][v]);
 }
 
+template <bool MX>
 __global__ __launch_bounds__(256) void k_gram_inner_w(const ItemDev* items, const UnitDev* units,
                                                       int64_t nunits, double zeta,
                                                       double2* partial) {
@@ -989,34 +1181,68 @@ __global__ __launch_bounds__(256) void k_gram_inner_w(const ItemDev* items, cons
   double2* out = partial + u.slot_off;
   if (u.a0 == u.b0) {
     switch (u.na) {
-      case 1: gram_inner_wave<1, 1, true>(it, s1, s2, u, zeta, out); break;
-      case 2: gram_inner_wave<2, 2, true>(it, s1, s2, u, zeta, out); break;
-      case 3: gram_inner_wave<3, 3, true>(it, s1, s2, u, zeta, out); break;
-      default: gram_inner_wave<4, 4, true>(it, s1, s2, u, zeta, out); break;
+      case 1: gram_inner_wave<MX, 1, 1, true>(it, s1, s2, u, zeta, out); break;
+      case 2: gram_inner_wave<MX, 2, 2, true>(it, s1, s2, u, zeta, out); break;
+      case 3: gram_inner_wave<MX, 3, 3, true>(it, s1, s2, u, zeta, out); break;
+      default: gram_inner_wave<MX, 4, 4, true>(it, s1, s2, u, zeta, out); break;
     }
   } else {
     if (u.na == 1) {
       switch (u.nb) {
-        case 1: gram_inner_wave<1, 1, false>(it, s1, s2, u, zeta, out); break;
-        case 2: gram_inner_wave<1, 2, false>(it, s1, s2, u, zeta, out); break;
-        case 3: gram_inner_wave<1, 3, false>(it, s1, s2, u, zeta, out); break;
-        default: gram_inner_wave<1, 4, false>(it, s1, s2, u, zeta, out); break;
+        case 1: gram_inner_wave<MX, 1, 1, false>(it, s1, s2, u, zeta, out); break;
+        case 2: gram_inner_wave<MX, 1, 2, false>(it, s1, s2, u, zeta, out); break;
+        case 3: gram_inner_wave<MX, 1, 3, false>(it, s1, s2, u, zeta, out); break;
+        default: gram_inner_wave<MX, 1, 4, false>(it, s1, s2, u, zeta, out); break;
       }
     } else {
       switch (u.nb) {
-        case 1: gram_inner_wave<2, 1, false>(it, s1, s2, u, zeta, out); break;
-        case 2: gram_inner_wave<2, 2, false>(it, s1, s2, u, zeta, out); break;
-        case 3: gram_inner_wave<2, 3, false>(it, s1, s2, u, zeta, out); break;
-        default: gram_inner_wave<2, 4, false>(it, s1, s2, u, zeta, out); break;
+        case 1: gram_inner_wave<MX, 2, 1, false>(it, s1, s2, u, zeta, out); break;
+        case 2: gram_inner_wave<MX, 2, 2, false>(it, s1, s2, u, zeta, out); break;
+        case 3: gram_inner_wave<MX, 2, 3, false>(it, s1, s2, u, zeta, out); break;
+        default: gram_inner_wave<MX, 2, 4, false>(it, s1, s2, u, zeta, out); break;
       }
     }
   }
 }
 
+// One complex multiply-accumulate of the R-product on MFMA:
+// acc += A^T conj(Q) (re = ar qr + ai qi, im = ai qr - ar qi).
+template <bool MX>
+struct RAcc;
+template <>
+struct RAcc<false> {
+  dvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+  __device__ __forceinline__ void mac(double2 a, double2 q) {
+    re = mfma_f64(a.x, q.x, re);
+    re = mfma_f64(a.y, q.y, re);
+    im = mfma_f64(a.y, q.x, im);
+    im = mfma_f64(-a.x, q.y, im);
+  }
+  __device__ __forceinline__ int row(int lane, int v) const { return f64_row(lane, v); }
+  __device__ __forceinline__ void store(void* R, int64_t idx, int v) const {
+    reinterpret_cast<double2*>(R)[idx] = make_double2(re[v], im[v]);
+  }
+};
+template <>
+struct RAcc<true> {
+  fvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+  __device__ __forceinline__ void mac(double2 a, double2 q) {
+    float ar = (float)a.x, ai = (float)a.y, qr = (float)q.x, qi = (float)q.y;
+    re = mfma_f32(ar, qr, re);
+    re = mfma_f32(ai, qi, re);
+    im = mfma_f32(ai, qr, im);
+    im = mfma_f32(-ar, qi, im);
+  }
+  __device__ __forceinline__ int row(int lane, int v) const { return f32_row(lane, v); }
+  __device__ __forceinline__ void store(void* R, int64_t idx, int v) const {
+    reinterpret_cast<float2*>(R)[idx] = make_float2(re[v], im[v]);
+  }
+};
+
 // R^T of a non-leaf block row, one unit (column range) per wave:
 // R^T[j][kk] = sum_rho G_hat[rho][j] conj(Q_hat[rho][kk]); operands loaded
 // directly (G_hat one k-step ahead), Q_hat rows from L1/L2.
-template <int KT>
+template <bool MX, int KT>
 __device__ void rprod_inner_wave(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
                                  const UnitDev& u, double zeta) {
   int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
@@ -1025,25 +1251,17 @@ __device__ void rprod_inner_wave(const ItemDev& it, const ItemDev& s1, const Ite
   for (int64_t j0 = 0; j0 < u.ncols; j0 += 16) {
     bool valid = j0 + row < u.ncols;
     int64_t jc = it.col_off + u.col_begin + j0 + row;
-    dvec4 acr[KT], aci[KT];
-#pragma unroll
-    for (int t = 0; t < KT; ++t) {
-      acr[t] = dvec4{0, 0, 0, 0};
-      aci[t] = dvec4{0, 0, 0, 0};
-    }
-    double2 a = valid ? ghat(s1, s2, jc, kq, r, zeta) : make_double2(0.0, 0.0);
+    RAcc<MX> acc[KT];
+    double2 a = valid ? ghat<MX>(s1, s2, jc, kq, r, zeta) : make_double2(0.0, 0.0);
     for (int ks = 0; ks < nks; ++ks) {
       int rho = 4 * ks + kq;
-      double2 an = (valid && ks + 1 < nks) ? ghat(s1, s2, jc, rho + 4, r, zeta)
+      double2 an = (valid && ks + 1 < nks) ? ghat<MX>(s1, s2, jc, rho + 4, r, zeta)
                                            : make_double2(0.0, 0.0);
 #pragma unroll
       for (int t = 0; t < KT; ++t) {
         int kk = 16 * t + row;
         double2 q = (rho < r && kk < k) ? it.Q[(int64_t)rho * k + kk] : make_double2(0.0, 0.0);
-        acr[t] = mfma_f64(a.x, q.x, acr[t]);
-        acr[t] = mfma_f64(a.y, q.y, acr[t]);
-        aci[t] = mfma_f64(a.y, q.x, aci[t]);
-        aci[t] = mfma_f64(-a.x, q.y, aci[t]);
+        acc[t].mac(a, q);
       }
       a = an;
     }
@@ -1052,14 +1270,14 @@ __device__ void rprod_inner_wave(const ItemDev& it, const ItemDev& s1, const Ite
       int kk = 16 * t + row;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int64_t jl = j0 + f64_row(lane, v);
-        if (jl < u.ncols && kk < k)
-          it.R[(u.col_begin + jl) * k + kk] = make_double2(acr[t][v], aci[t][v]);
+        int64_t jl = j0 + acc[t].row(lane, v);
+        if (jl < u.ncols && kk < k) acc[t].store(it.R, (u.col_begin + jl) * k + kk, v);
       }
     }
   }
 }
 
+template <bool MX>
 __global__ __launch_bounds__(256) void k_rprod_inner_w(const ItemDev* items, const UnitDev* units,
                                                        int64_t nunits, double zeta) {
   int w = threadIdx.x >> 6;
@@ -1071,20 +1289,20 @@ __global__ __launch_bounds__(256) void k_rprod_inner_w(const ItemDev* items, con
   const ItemDev& s1 = items[it.son[0]];
   const ItemDev& s2 = items[it.son[1]];
   switch ((it.k + 15) / 16) {
-    case 1: rprod_inner_wave<1>(it, s1, s2, u, zeta); break;
-    case 2: rprod_inner_wave<2>(it, s1, s2, u, zeta); break;
-    case 3: rprod_inner_wave<3>(it, s1, s2, u, zeta); break;
-    case 4: rprod_inner_wave<4>(it, s1, s2, u, zeta); break;
-    case 5: rprod_inner_wave<5>(it, s1, s2, u, zeta); break;
-    case 6: rprod_inner_wave<6>(it, s1, s2, u, zeta); break;
-    case 7: rprod_inner_wave<7>(it, s1, s2, u, zeta); break;
-    default: rprod_inner_wave<8>(it, s1, s2, u, zeta); break;
+    case 1: rprod_inner_wave<MX, 1>(it, s1, s2, u, zeta); break;
+    case 2: rprod_inner_wave<MX, 2>(it, s1, s2, u, zeta); break;
+    case 3: rprod_inner_wave<MX, 3>(it, s1, s2, u, zeta); break;
+    case 4: rprod_inner_wave<MX, 4>(it, s1, s2, u, zeta); break;
+    case 5: rprod_inner_wave<MX, 5>(it, s1, s2, u, zeta); break;
+    case 6: rprod_inner_wave<MX, 6>(it, s1, s2, u, zeta); break;
+    case 7: rprod_inner_wave<MX, 7>(it, s1, s2, u, zeta); break;
+    default: rprod_inner_wave<MX, 8>(it, s1, s2, u, zeta); break;
   }
 }
 
 // R^T of a leaf block row: the workgroup's four waves share the item's factor
 // Q (in LDS) and take 16-column groups in turn.
-template <int SRC, int KT>
+template <int SRC, bool MX, int KT>
 __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
                                 const UnitDev& u, const double2* Qs, const RowData* rows) {
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
@@ -1093,26 +1311,14 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
   for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
     int64_t j = u.col_begin + j0 + row;
     double4 cc = column_data<SRC>(g, it, ents, side, j, j0 + row < u.ncols);
-    dvec4 acr[KT], aci[KT];
-#pragma unroll
-    for (int t = 0; t < KT; ++t) {
-      acr[t] = dvec4{0, 0, 0, 0};
-      aci[t] = dvec4{0, 0, 0, 0};
-    }
-    double2 a = gen_entry<SRC>(g, rows[kq], cc, side);
+    RAcc<MX> acc[KT];
+    double2 a = gen_entry<SRC, MX>(g, rows[kq], cc, side);
     for (int ks = 0; ks < nks; ++ks) {
       int rho = 4 * ks + kq;
       // next k-step's entry (rows array is padded past r)
-      double2 an = gen_entry<SRC>(g, rows[rho + 4], cc, side);
+      double2 an = gen_entry<SRC, MX>(g, rows[rho + 4], cc, side);
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        double2 q = Qs[rho * (16 * KT) + 16 * t + row];
-        // A^T conj(Q): re = ar qr + ai qi, im = ai qr - ar qi
-        acr[t] = mfma_f64(a.x, q.x, acr[t]);
-        acr[t] = mfma_f64(a.y, q.y, acr[t]);
-        aci[t] = mfma_f64(a.y, q.x, aci[t]);
-        aci[t] = mfma_f64(-a.x, q.y, aci[t]);
-      }
+      for (int t = 0; t < KT; ++t) acc[t].mac(a, Qs[rho * (16 * KT) + 16 * t + row]);
 #pragma unroll
       for (int q = 0; q < 4 * KT; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -1125,15 +1331,14 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
       int kk = 16 * t + row;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int64_t jl = j0 + f64_row(lane, v);
-        if (jl < u.ncols && kk < k)
-          it.R[(u.col_begin + jl) * k + kk] = make_double2(acr[t][v], aci[t][v]);
+        int64_t jl = j0 + acc[t].row(lane, v);
+        if (jl < u.ncols && kk < k) acc[t].store(it.R, (u.col_begin + jl) * k + kk, v);
       }
     }
   }
 }
 
-template <int SRC>
+template <int SRC, bool MX>
 __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* items,
                                                       const EntDev* ents, const UnitDev* units,
                                                       int side) {
@@ -1152,10 +1357,10 @@ __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* 
   for (int i = threadIdx.x; i < 72; i += 256) rows[i] = row_data<SRC>(g, it, i, side);
   __syncthreads();
   switch (kt) {
-    case 1: rprod_leaf_wave<SRC, 1>(g, it, ents, side, u, Qs, rows); break;
-    case 2: rprod_leaf_wave<SRC, 2>(g, it, ents, side, u, Qs, rows); break;
-    case 3: rprod_leaf_wave<SRC, 3>(g, it, ents, side, u, Qs, rows); break;
-    default: rprod_leaf_wave<SRC, 4>(g, it, ents, side, u, Qs, rows); break;
+    case 1: rprod_leaf_wave<SRC, MX, 1>(g, it, ents, side, u, Qs, rows); break;
+    case 2: rprod_leaf_wave<SRC, MX, 2>(g, it, ents, side, u, Qs, rows); break;
+    case 3: rprod_leaf_wave<SRC, MX, 3>(g, it, ents, side, u, Qs, rows); break;
+    default: rprod_leaf_wave<SRC, MX, 4>(g, it, ents, side, u, Qs, rows); break;
   }
 }
 
@@ -1183,19 +1388,29 @@ void launch_entry_scale(EntDev* ent, int64_t nent, const double* omega, double z
                      omega, zeta);
 }
 
-void launch_gram(int src, bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
-                 const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
-                 hipStream_t st) {
+void launch_gram(int src, bool inner, bool mixed, const GeomDev& g, const ItemDev* items,
+                 const EntDev* ents, const UnitDev* units, int64_t nunits, double zeta, int side,
+                 double2* partial, hipStream_t st) {
   if (nunits == 0) return;
   dim3 grid(blocks_for(nunits, 4)), blk(256);
-  if (inner)
-    hipLaunchKernelGGL(k_gram_inner_w, grid, blk, 0, st, items, units, nunits, zeta, partial);
-  else if (src == SRC_HELMHOLTZ)
-    hipLaunchKernelGGL(k_gram_leaf_w<SRC_HELMHOLTZ>, grid, blk, 0, st, g, items, ents, units,
+  if (inner) {
+    if (mixed)
+      hipLaunchKernelGGL(k_gram_inner_w<true>, grid, blk, 0, st, items, units, nunits, zeta,
+                         partial);
+    else
+      hipLaunchKernelGGL(k_gram_inner_w<false>, grid, blk, 0, st, items, units, nunits, zeta,
+                         partial);
+  } else if (src == SRC_HELMHOLTZ) {
+    if (mixed)
+      hipLaunchKernelGGL((k_gram_leaf_w<SRC_HELMHOLTZ, true>), grid, blk, 0, st, g, items, ents,
+                         units, nunits, side, partial);
+    else
+      hipLaunchKernelGGL((k_gram_leaf_w<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents,
+                         units, nunits, side, partial);
+  } else {
+    hipLaunchKernelGGL((k_gram_leaf_w<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents, units,
                        nunits, side, partial);
-  else
-    hipLaunchKernelGGL(k_gram_leaf_w<SRC_DENSE>, grid, blk, 0, st, g, items, ents, units, nunits,
-                       side, partial);
+  }
 }
 
 void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
@@ -1220,18 +1435,31 @@ void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, double eps
                      status);
 }
 
-void launch_rprod(int src, bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
-                  const UnitDev* units, int64_t nunits, double zeta, int side, hipStream_t st) {
+void launch_rprod(int src, bool inner, bool mixed, const GeomDev& g, const ItemDev* items,
+                  const EntDev* ents, const UnitDev* units, int64_t nunits, double zeta, int side,
+                  hipStream_t st) {
   if (nunits == 0) return;
-  dim3 grid((unsigned)nunits), blk(256);
-  if (inner)
-    hipLaunchKernelGGL(k_rprod_inner_w, dim3(blocks_for(nunits, 4)), blk, 0, st, items, units,
-                       nunits, zeta);
-  else if (src == SRC_HELMHOLTZ)
-    hipLaunchKernelGGL(k_rprod_leaf_w<SRC_HELMHOLTZ>, grid, blk, 0, st, g, items, ents, units,
-                       side);
-  else
-    hipLaunchKernelGGL(k_rprod_leaf_w<SRC_DENSE>, grid, blk, 0, st, g, items, ents, units, side);
+  dim3 blk(256);
+  if (inner) {
+    dim3 grid(blocks_for(nunits, 4));
+    if (mixed)
+      hipLaunchKernelGGL(k_rprod_inner_w<true>, grid, blk, 0, st, items, units, nunits, zeta);
+    else
+      hipLaunchKernelGGL(k_rprod_inner_w<false>, grid, blk, 0, st, items, units, nunits, zeta);
+  } else {
+    dim3 grid((unsigned)nunits);
+    if (src == SRC_HELMHOLTZ) {
+      if (mixed)
+        hipLaunchKernelGGL((k_rprod_leaf_w<SRC_HELMHOLTZ, true>), grid, blk, 0, st, g, items, ents,
+                           units, side);
+      else
+        hipLaunchKernelGGL((k_rprod_leaf_w<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items,
+                           ents, units, side);
+    } else {
+      hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents,
+                         units, side);
+    }
+  }
 }
 
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st) {
@@ -1246,10 +1474,52 @@ void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t ds
                      dst_off, count);
 }
 
-void launch_project(const ProjDev* tasks, int64_t ntasks, const double* omega, hipStream_t st) {
+void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const double* omega,
+                    hipStream_t st) {
   if (ntasks == 0) return;
-  hipLaunchKernelGGL(k_project, dim3(blocks_for(ntasks, 4)), dim3(256), 0, st, tasks, ntasks,
-                     omega);
+  if (mixed)
+    hipLaunchKernelGGL(k_project<true>, dim3(blocks_for(ntasks, 4)), dim3(256), 0, st, tasks,
+                       ntasks, omega);
+  else
+    hipLaunchKernelGGL(k_project<false>, dim3(blocks_for(ntasks, 4)), dim3(256), 0, st, tasks,
+                       ntasks, omega);
+}
+
+int project_rows_per_pass(bool mixed, int ntj) { return (mixed || ntj <= 2) ? 4 : 2; }
+
+template <bool MX, int NJ>
+static void launch_pt(int ni, const ProjDev* tasks, int64_t ntasks, const double* omega,
+                      hipStream_t st) {
+  dim3 grid(blocks_for(ntasks, 4)), blk(256);
+  switch (ni) {
+    case 1: hipLaunchKernelGGL((k_project_tiled<MX, 1, NJ>), grid, blk, 0, st, tasks, ntasks, omega); break;
+    case 2: hipLaunchKernelGGL((k_project_tiled<MX, 2, NJ>), grid, blk, 0, st, tasks, ntasks, omega); break;
+    case 3: hipLaunchKernelGGL((k_project_tiled<MX, 3, NJ>), grid, blk, 0, st, tasks, ntasks, omega); break;
+    default:
+      if constexpr (MX || NJ <= 2)
+        hipLaunchKernelGGL((k_project_tiled<MX, 4, NJ>), grid, blk, 0, st, tasks, ntasks, omega);
+      break;
+  }
+}
+
+void launch_project_tiled(bool mixed, int ni, int nj, const ProjDev* tasks, int64_t ntasks,
+                          const double* omega, hipStream_t st) {
+  if (ntasks == 0) return;
+  if (mixed) {
+    switch (nj) {
+      case 1: launch_pt<true, 1>(ni, tasks, ntasks, omega, st); break;
+      case 2: launch_pt<true, 2>(ni, tasks, ntasks, omega, st); break;
+      case 3: launch_pt<true, 3>(ni, tasks, ntasks, omega, st); break;
+      default: launch_pt<true, 4>(ni, tasks, ntasks, omega, st); break;
+    }
+  } else {
+    switch (nj) {
+      case 1: launch_pt<false, 1>(ni, tasks, ntasks, omega, st); break;
+      case 2: launch_pt<false, 2>(ni, tasks, ntasks, omega, st); break;
+      case 3: launch_pt<false, 3>(ni, tasks, ntasks, omega, st); break;
+      default: launch_pt<false, 4>(ni, tasks, ntasks, omega, st); break;
+    }
+  }
 }
 
 void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,

@@ -12,20 +12,27 @@ void launch_block_norm(int src, const GeomDev& g, const int64_t* t_off, const in
                        hipStream_t st);
 void launch_entry_scale(EntDev* ent, int64_t nent, const double* omega, double zeta,
                         hipStream_t st);
-void launch_gram(int src, bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
-                 const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
-                 hipStream_t st);
+void launch_gram(int src, bool inner, bool mixed, const GeomDev& g, const ItemDev* items,
+                 const EntDev* ents, const UnitDev* units, int64_t nunits, double zeta, int side,
+                 double2* partial, hipStream_t st);
 void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
                         const int32_t* ubegin, const UnitDev* units, const double2* partial,
                         hipStream_t st);
 void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, double eps, int max_sweeps,
                    int32_t* status, hipStream_t st);
-void launch_rprod(int src, bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
-                  const UnitDev* units, int64_t nunits, double zeta, int side, hipStream_t st);
+void launch_rprod(int src, bool inner, bool mixed, const GeomDev& g, const ItemDev* items,
+                  const EntDev* ents, const UnitDev* units, int64_t nunits, double zeta, int side,
+                  hipStream_t st);
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
                    int64_t count, hipStream_t st);
-void launch_project(const ProjDev* tasks, int64_t ntasks, const double* omega, hipStream_t st);
+void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const double* omega,
+                    hipStream_t st);
+// blocks with ks <= 64: every task of one launch has ceil(ks/16) = nj and is
+// processed in passes of ni = min(ceil(kt/16), project_rows_per_pass) row tiles
+int project_rows_per_pass(bool mixed, int nj);
+void launch_project_tiled(bool mixed, int ni, int nj, const ProjDev* tasks, int64_t ntasks,
+                          const double* omega, hipStream_t st);
 void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
                  const int64_t* s_off, const int64_t* s_len, const int64_t* out_off,
                  int64_t nblocks, double2* out, hipStream_t st);

@@ -55,7 +55,8 @@ class Stats(C.Structure):
                 ("flops_rprod", C.c_double), ("t_gram_kernel", C.c_double),
                 ("groups", C.c_int32), ("precision", C.c_int32),
                 ("flops_gram_leaf", C.c_double), ("t_gram_leaf", C.c_double),
-                ("n_gram_leaf", C.c_int32), ("pad", C.c_int32)]
+                ("n_gram_leaf", C.c_int32), ("pad", C.c_int32),
+                ("flops_rprod_leaf", C.c_double)]
 
 
 EXPORTED = [

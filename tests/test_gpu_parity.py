@@ -14,6 +14,17 @@ Tolerances (derived from the arithmetic):
 * Global relative spectral error <= 1.1 eps.
 * FP64 matrix-vector products agree with the dense reconstruction of the
   exported representation to 1e-10.
+
+Mixed form (entries with FP32 phase polynomials, R and the R-products in
+complex FP32, Gram, factor and truncation in FP64): an entry carries about
+three FP32 roundings (phase polynomial, amplitude, product; 2^-24 each), so
+the weighted block row moves by ||dA||_2 <= ||dA||_F <= 3 2^-24 ||A||_F, and
+by Weyl's theorem every singular value by at most as much.  The FP32
+R-product adds roundings of the same size that average out over its short
+sums (at most 128 terms).  The test allows
+|sigma_gpu - sigma_oracle| <= 2e-7 ||A||_F for sigma > eps; ranks may differ
+only where the oracle's sigma lies within that band around eps.  The
+Davis-Kahan bound uses the Gram perturbation 2 ||A||_2 ||dA||_2.
 """
 import math
 
@@ -43,9 +54,9 @@ def problem():
     return dict(p=p, w=w, kappa=kappa, leaf=leaf, plan=plan, M=M, ref=ref, G=G)
 
 
-def _gpu_compress(problem, dense):
+def _gpu_compress(problem, dense, mixed=False):
     from paper_1510_07087_amd import dh2
-    o = dh2.opts(leaf_size=problem["leaf"])
+    o = dh2.opts(leaf_size=problem["leaf"], precision=dh2.MIXED if mixed else dh2.FP64)
     t = dh2.tree_build(problem["p"], problem["kappa"], o)
     b = dh2.blocks_build(t, o)
     if dense:
@@ -58,10 +69,10 @@ def _gpu_compress(problem, dense):
     return m, None
 
 
-@pytest.fixture(scope="module", params=["helmholtz", "dense"])
+@pytest.fixture(scope="module", params=["helmholtz", "dense", "mixed"])
 def gpu(request, problem):
     print(f"[gpu parity] compress mode={request.param} n=2048", flush=True)
-    m, Gd = _gpu_compress(problem, request.param == "dense")
+    m, Gd = _gpu_compress(problem, request.param == "dense", request.param == "mixed")
     from dh2_export import exported_bases, exported_dense
     plan = problem["plan"]
     Gt, V, W, S = exported_dense(m, plan)
@@ -70,14 +81,21 @@ def gpu(request, problem):
     return dict(m=m, Gd=Gd, Gt=Gt, V=V, W=W, S=S, dv=dv, dw=dw, mode=request.param)
 
 
-def _tol_lambda(sig_ref):
+MIXED_SIGMA = 2e-7   # |d sigma| / ||A||_F in the mixed form
+
+
+def _tol_lambda(sig_ref, mode="helmholtz"):
     fro2 = float(np.sum(sig_ref ** 2))
+    if mode == "mixed":
+        return 2.0 * float(sig_ref[0]) * MIXED_SIGMA * np.sqrt(fro2) + 1e-13 * fro2
     return 1e-13 * fro2
 
 
 def test_singular_values_and_ranks(problem, gpu):
     ref = problem["ref"]
+    mixed = gpu["mode"] == "mixed"
     n_checked = n_tie = 0
+    worst = 0.0
     for basis_ref, data in ((ref.V, gpu["dv"]), (ref.W, gpu["dw"])):
         for key, sig_ref in basis_ref.sigma.items():
             k, mat, sig = data[key]
@@ -86,15 +104,25 @@ def test_singular_values_and_ranks(problem, gpu):
             s_ref = np.zeros(len(sig))
             s_ref[:min(r, len(sig))] = sig_ref[:len(sig)]
             big = s_ref > EPS
-            d = np.abs(sig[big] ** 2 - s_ref[big] ** 2)
-            assert np.all(d <= tl + 1e-10 * s_ref[big] ** 2), (key, d.max(), tl)
-            tie = np.any(np.abs(sig_ref ** 2 - EPS ** 2) <= tl + 1e-10 * EPS ** 2)
+            if mixed:
+                fro = float(np.sqrt(np.sum(sig_ref ** 2)))
+                d = np.abs(sig[big] - s_ref[big]) / fro
+                if d.size:
+                    worst = max(worst, float(d.max()))
+                assert np.all(d <= MIXED_SIGMA), (key, d.max())
+                tie = np.any(np.abs(sig_ref - EPS) <= MIXED_SIGMA * fro)
+            else:
+                d = np.abs(sig[big] ** 2 - s_ref[big] ** 2)
+                assert np.all(d <= tl + 1e-10 * s_ref[big] ** 2), (key, d.max(), tl)
+                tie = np.any(np.abs(sig_ref ** 2 - EPS ** 2) <= tl + 1e-10 * EPS ** 2)
             if tie:
                 n_tie += 1
                 assert abs(k - basis_ref.k[key]) <= 1
             else:
                 assert k == basis_ref.k[key], (key, k, basis_ref.k[key])
             n_checked += 1
+    if mixed:
+        print(f"[gpu parity] mixed: max |d sigma| / ||A||_F = {worst:.2e}", flush=True)
     assert n_checked > 500
     assert n_tie < n_checked // 20
 
@@ -109,7 +137,7 @@ def test_leaf_projectors(problem, gpu):
             s = basis_ref.sigma[key]
             gap = s[k - 1] ** 2 - (s[k] ** 2 if k < len(s) else 0.0)
             P = Qg @ Qg.conj().T - Qo @ Qo.conj().T
-            assert np.linalg.norm(P, 2) <= 10 * _tol_lambda(s) / gap + 1e-10
+            assert np.linalg.norm(P, 2) <= 10 * _tol_lambda(s, gpu["mode"]) / gap + 1e-10
 
 
 def test_orthonormal_nested(problem, gpu):
