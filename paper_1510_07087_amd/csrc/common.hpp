@@ -17,6 +17,7 @@ struct GeomDev {
   const double* G;        // dense complex128, ORIGINAL order, row-major (interleaved)
   const int64_t* perm;    // position -> original index
   int64_t ldg;            // leading dimension of G in complex elements
+  const double* cbox;     // per cluster: lo[3], hi[3], largest weight, 0 (bounds of entries)
   int64_t n;
   double kappa;
 };
@@ -32,6 +33,7 @@ struct ItemDev {
   double2* M;        // Gram (r x r, column-major)
   double2* Q;        // factor: r x k row-major (leaf: Q_tc, other: [E_t1c; E_t2c])
   double* sig;       // singular values (r)
+  double4* cols;     // leaf: per-column data of F_tc for the current level (x, y, z, factor)
   int32_t m;         // rows of the cluster
   int32_t r;         // rows of the factor (m or k1+k2)
   int32_t k;         // rank (filled by the factorisation)
@@ -49,6 +51,8 @@ struct EntDev {
   int32_t b;          // admissible block
   int32_t d;          // level difference
   double scale;       // 1 / (omega_b zeta^d)
+  int32_t s;          // column cluster
+  int32_t pad;
 };
 
 // A contiguous column range of one block row, processed by one workgroup.

@@ -340,6 +340,12 @@ static void build_side(MatrixData& M, int s, const std::vector<int32_t>& batch_o
     }
   }
   S.ents.clear();
+  {
+    size_t nent = 0;
+    for (int32_t e = 0; e < ni; ++e)
+      if (tr.leaf(cs.item_t[e])) nent += (size_t)(cs.begin[e + 1] - cs.begin[e]);
+    S.ents.reserve(nent);
+  }
   std::vector<int32_t> son_ext(2 * (size_t)ni, -1);
   int32_t nb = M.nbatch;
   S.range.assign(nb, std::vector<std::pair<int32_t, int32_t>>(tr.depth + 1, {0, 0}));
@@ -369,6 +375,7 @@ static void build_side(MatrixData& M, int s, const std::vector<int32_t>& batch_o
         ed.b = ce.b;
         ed.d = ce.d;
         ed.scale = 0.0;
+        ed.s = ce.s;
         S.ents.push_back(ed);
       }
       it.ent_end = (int64_t)S.ents.size();
@@ -469,6 +476,26 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         sum_r2 += (int64_t)it.r * it.r;
         sum_r += it.r;
       }
+      // column data of the leaf block rows of this level (read by the Gram and
+      // R-product kernels)
+      std::vector<int32_t> leaf_ids;
+      int64_t sum_leafN = 0;
+      for (int32_t i = lo; i < hi; ++i)
+        if (S.items[i].leaf && S.items[i].N > 0) {
+          leaf_ids.push_back(i);
+          sum_leafN += S.items[i].N;
+        }
+      double4* colbuf = sum_leafN ? (double4*)mem.alloc(sum_leafN * sizeof(double4)) : nullptr;
+      {
+        int64_t o = 0;
+        for (int32_t i = lo; i < hi; ++i) {
+          S.items[i].cols = nullptr;
+          if (S.items[i].leaf && S.items[i].N > 0) {
+            S.items[i].cols = colbuf + o;
+            o += S.items[i].N;
+          }
+        }
+      }
       double2* Marena = (double2*)mem.alloc(sum_r2 * sizeof(double2));
       double2* Qarena = (double2*)mem.alloc(sum_r2 * sizeof(double2));
       double* sarena = (double*)mem.alloc(sum_r * sizeof(double));
@@ -486,12 +513,17 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         }
       }
       copy_to(S.d_items + lo, S.items.data() + lo, n, st);
+      int32_t* d_leaf_ids = upload(mem, leaf_ids, st);
+      launch_leaf_cols(M.src, g, S.d_items, d_leaf_ids, (int32_t)leaf_ids.size(), S.d_ents, s, st);
+      launch_check("leaf columns");
       tr_.mark("arenas", s, b, lv);
       // Gram units: leaf items first, then non-leaf items
       int64_t totalN = 0;
       for (int32_t i = lo; i < hi; ++i) totalN += S.items[i].N;
-      // one Gram unit per wave: aim for about 8 waves of work per SIMD
-      int64_t width = std::max<int64_t>(256, std::min<int64_t>(2048, totalN / 8192));
+      // FP64: one Gram unit per wave, about 8 waves of work per SIMD; mixed:
+      // one unit per workgroup of 8 waves (int8 slicing, 64-column chunks)
+      int64_t width = mixed ? std::max<int64_t>(512, std::min<int64_t>(8192, totalN / 1024))
+                            : std::max<int64_t>(256, std::min<int64_t>(2048, totalN / 8192));
       width = (width + 63) / 64 * 64;
       std::vector<UnitDev> units;
       std::vector<int32_t> litems, ubegin;
@@ -551,16 +583,24 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       int32_t* d_ubegin = upload(mem, ubegin, st);
       tr_.mark("gram units", s, b, lv);
       tg.start();
+      const bool i8 = mixed && M.src == SRC_HELMHOLTZ;
       if (nleafu > 0) {
         tgl.start();
-        launch_gram(M.src, false, mixed, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s,
-                    partial, st);
+        if (i8)
+          launch_gram_i8(false, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s, partial, st);
+        else
+          launch_gram(M.src, false, mixed, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s,
+                      partial, st);
         launch_check("gram (leaf)");
         tgl.stop();
         ss.n_gram_leaf += 1;
       }
-      launch_gram(M.src, true, mixed, g, S.d_items, S.d_ents, d_units + nleafu,
-                  (int64_t)units.size() - nleafu, M.zeta, s, partial, st);
+      if (i8)
+        launch_gram_i8(true, g, S.d_items, S.d_ents, d_units + nleafu,
+                       (int64_t)units.size() - nleafu, M.zeta, s, partial, st);
+      else
+        launch_gram(M.src, true, mixed, g, S.d_items, S.d_ents, d_units + nleafu,
+                    (int64_t)units.size() - nleafu, M.zeta, s, partial, st);
       launch_check("gram (non-leaf)");
       tg.stop();
       tr_.mark("gram", s, b, lv);
@@ -711,6 +751,9 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       mem.release(d_litems);
       mem.release(d_ubegin);
       mem.release(d_ru);
+      mem.release(d_leaf_ids);
+      mem.release(colbuf);
+      for (int32_t i = lo; i < hi; ++i) S.items[i].cols = nullptr;
       mem.release(R_prev);
       R_prev = Rarena;
       tr_.mark("level end", s, b, lv);
@@ -806,8 +849,29 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   }
   M.d_pts = upload(mem, pp, st);
   M.d_perm = upload(mem, tr.perm, st);
+  {
+    // cluster boxes and largest weights (bounds of the entry magnitudes)
+    std::vector<double> cb(8 * (size_t)tr.nc(), 0.0);
+    for (int32_t t = tr.nc() - 1; t >= 0; --t) {
+      for (int a = 0; a < 3; ++a) {
+        cb[8 * t + a] = tr.lo[3 * t + a];
+        cb[8 * t + 3 + a] = tr.hi[3 * t + a];
+      }
+      double wm = 0.0;
+      if (tr.leaf(t)) {
+        for (int64_t p = tr.off[t]; p < tr.off[t] + tr.size[t]; ++p)
+          wm = std::max(wm, std::fabs(M.w[tr.perm[p]]));
+      } else {
+        wm = std::max(cb[8 * tr.son1[t] + 6], cb[8 * tr.son2[t] + 6]);
+      }
+      cb[8 * t + 6] = wm;
+    }
+    M.d_cbox = upload(mem, cb, st);
+  }
   GeomDev g{};
   g.pts = M.d_pts;
+  g.cbox = M.d_cbox;
+  g.cbox = M.d_cbox;
   g.G = (const double*)G;
   g.perm = M.d_perm;
   g.ldg = ld;
@@ -860,8 +924,11 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     for (int32_t t = 0; t < tr.nc(); ++t) batch_of[t] = group[t] >= 0 ? gb[group[t]] : 0;
   }
 
+  Trace trc;
+  trc.mark("setup", -1, -1, -1);
   build_side(M, 0, batch_of);
   build_side(M, 1, batch_of);
+  trc.mark("build sides", -1, -1, -1);
   M.S_ptr.assign(nadm, nullptr);
   M.S_rows.assign(nadm, 0);
   M.S_cols.assign(nadm, 0);
@@ -901,6 +968,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   }
   hip_check(hipEventRecord(e1, st), "event");
   hip_check(hipEventSynchronize(e1), "event");
+  trc.mark("weights", -1, -1, -1);
   float ms_w = 0;
   hip_check(hipEventElapsedTime(&ms_w, e0, e1), "event");
 
@@ -955,6 +1023,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   hip_check(hipEventSynchronize(e1), "event");
   float ms_near = 0;
   hip_check(hipEventElapsedTime(&ms_near, e0, e1), "event");
+  trc.mark("sweeps+near", -1, -1, -1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   mem.release(d_status);
@@ -998,6 +1067,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   S.t_gram_leaf = ss_row.t_gram_leaf + ss_col.t_gram_leaf;
   S.n_gram_leaf = ss_row.n_gram_leaf + ss_col.n_gram_leaf;
   S.flops_rprod_leaf = ss_row.flops_rprod_leaf + ss_col.flops_rprod_leaf;
+  trc.mark("finish", -1, -1, -1);
   return Mp;
 }
 
@@ -1168,6 +1238,7 @@ void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st
 static GeomDev geom(MatrixData& M, const void* G, int64_t ld) {
   GeomDev g{};
   g.pts = M.d_pts;
+  g.cbox = M.d_cbox;
   g.G = (const double*)G;
   g.perm = M.d_perm;
   g.ldg = ld;

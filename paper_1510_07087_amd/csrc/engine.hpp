@@ -87,6 +87,7 @@ struct MatrixData {
   int32_t lmin = 0;
   // device geometry
   double* d_pts = nullptr;     // permuted n x 4
+  double* d_cbox = nullptr;    // per cluster: box and largest weight
   int64_t* d_perm = nullptr;
   std::vector<double> w;       // original-order weights
   Side side[2];

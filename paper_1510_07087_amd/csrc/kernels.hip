@@ -932,36 +932,30 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Column j of a leaf block row: permuted position and scale 1/(omega_b zeta^d).
-__device__ __forceinline__ void leaf_column(const ItemDev& it, const EntDev* ents, int64_t j,
-                                            int64_t& pos, double& scale) {
-  int64_t lo = it.ent_begin, hi = it.ent_end - 1;
-  while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
-    if (ents[mid].col_start <= j)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  pos = ents[lo].pos + (j - ents[lo].col_start);
-  scale = ents[lo].scale;
-}
-
-// Staged column data: x, y, z and the column factor.  Helmholtz: factor =
-// scale * (side 0 ? w_j : 1) / (4 pi); dense: factor = scale, index in .x.
+// Column data of the leaf block rows of one level, written once per level:
+// one workgroup per item walks its column-set entries.  Column j of the
+// weighted block row carries (x, y, z, factor): Helmholtz factor =
+// scale * (side 0 ? w_j : 1) / (4 pi), scale = 1 / (omega_b zeta^d); dense:
+// the original index in x and factor = scale.
 template <int SRC>
-__device__ __forceinline__ double4 column_data(const GeomDev& g, const ItemDev& it,
-                                               const EntDev* ents, int side, int64_t j,
-                                               bool valid) {
-  if (!valid) return make_double4(0.0, 0.0, 0.0, 0.0);
-  int64_t pos;
-  double sc;
-  leaf_column(it, ents, j, pos, sc);
-  if constexpr (SRC == SRC_HELMHOLTZ) {
-    const double* p = g.pts + 4 * pos;
-    return make_double4(p[0], p[1], p[2], sc * (side == 0 ? p[3] : 1.0) * kInv4Pi);
-  } else {
-    return make_double4(__longlong_as_double((long long)g.perm[pos]), 0.0, 0.0, sc);
+__global__ __launch_bounds__(256) void k_leaf_cols(GeomDev g, const ItemDev* items,
+                                                   const int32_t* litems, const EntDev* ents,
+                                                   int side) {
+  const ItemDev& it = items[litems[blockIdx.x]];
+  double4* out = it.cols;
+  for (int64_t e = it.ent_begin; e < it.ent_end; ++e) {
+    const EntDev en = ents[e];
+    for (int64_t q = threadIdx.x; q < en.len; q += 256) {
+      int64_t pos = en.pos + q;
+      double4 v;
+      if constexpr (SRC == SRC_HELMHOLTZ) {
+        const double* p = g.pts + 4 * pos;
+        v = make_double4(p[0], p[1], p[2], en.scale * (side == 0 ? p[3] : 1.0) * kInv4Pi);
+      } else {
+        v = make_double4(__longlong_as_double((long long)g.perm[pos]), 0.0, 0.0, en.scale);
+      }
+      out[en.col_start + q] = v;
+    }
   }
 }
 
@@ -1034,11 +1028,15 @@ __device__ void gram_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev
     acr[p] = dvec4{0, 0, 0, 0};
     aci[p] = dvec4{0, 0, 0, 0};
   }
+  double4 cnext = lane < u.ncols ? it.cols[u.col_begin + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
   for (int64_t c0 = 0; c0 < u.ncols; c0 += 64) {
     int64_t left = u.ncols - c0;
     wave_sync();
-    cl[lane] = column_data<SRC>(g, it, ents, side, u.col_begin + c0 + lane, lane < left);
+    cl[lane] = cnext;
     wave_sync();
+    // prefetch the next chunk's column data
+    cnext = c0 + 64 + lane < u.ncols ? it.cols[u.col_begin + c0 + 64 + lane]
+                                     : make_double4(0.0, 0.0, 0.0, 0.0);
     int nks = left >= 64 ? 16 : (int)((left + 3) / 4);
     double2 cur[NT];
     {
@@ -1310,7 +1308,7 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
   int nks = (r + 3) / 4;
   for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
     int64_t j = u.col_begin + j0 + row;
-    double4 cc = column_data<SRC>(g, it, ents, side, j, j0 + row < u.ncols);
+    double4 cc = j0 + row < u.ncols ? it.cols[j] : make_double4(0.0, 0.0, 0.0, 0.0);
     RAcc<MX> acc[KT];
     double2 a = gen_entry<SRC, MX>(g, rows[kq], cc, side);
     for (int ks = 0; ks < nks; ++ks) {
@@ -1361,6 +1359,353 @@ __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* 
     case 2: rprod_leaf_wave<SRC, MX, 2>(g, it, ents, side, u, Qs, rows); break;
     case 3: rprod_leaf_wave<SRC, MX, 3>(g, it, ents, side, u, Qs, rows); break;
     default: rprod_leaf_wave<SRC, MX, 4>(g, it, ents, side, u, Qs, rows); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrices of the mixed form on int8 MFMA (error-free slicing).
+// Each real component x of row i of the block row is written as
+//   x = 2^(E_i - 7) (q1 + q2 2^-7 + q3 2^-14 + q4 2^-21) + rest,
+// with integer slices |q| <= 127 taken by truncation (every step exact in
+// FP32) and E_i the exponent of a bound of the row's largest component over
+// the unit, so |rest| < 2^(E_i - 28).  Products of slices accumulate exactly
+// in int32 (16x16x64 MFMA); slice pairs with p + q <= 7 are kept (the
+// dropped ones are below 2^-42 of the product of the row maxima), summed per
+// p + q, and converted to FP64 once per unit.  The complex Gram
+// A A^* = (Ar Ar^T + Ai Ai^T) + i (Ai Ar^T - Ar Ai^T) takes four real
+// products per 16 x 16 tile pair.  One workgroup of 8 waves per unit: all
+// threads generate (leaf) or load (non-leaf) and slice the next 64 columns
+// into LDS while the waves run the MFMAs of the current 64 columns.
+// ---------------------------------------------------------------------------
+typedef int ivec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ ivec4 mfma_i8(ivec4 a, ivec4 b, ivec4 c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
+constexpr int kI8Tiles = 6;                           // complex row tiles per unit
+constexpr int kI8Slab = 1024;                         // one slice of one tile: 16 rows x 64 B
+constexpr int kI8Buf = kI8Tiles * 2 * 4 * kI8Slab;    // tiles x components x slices
+constexpr int kI8Prod = 40;                           // real tile products per unit
+constexpr size_t kI8Lds = 2 * (size_t)kI8Buf + 3 * 64 * sizeof(double4) +
+                          kI8Tiles * 16 * (sizeof(RowData) + 2 * sizeof(int));
+
+__device__ __forceinline__ int i8_off(int T, int comp, int p, int g, int i) {
+  return ((((T * 2 + comp) * 4 + p) * 4 + g) * 16 + i) * 16;
+}
+
+// four int8 slices of 8 values scaled by sc (|v sc| < 128), packed two dwords each
+__device__ __forceinline__ void i8_slice8(const float* v, float sc, uint2* out) {
+  unsigned lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    float y = v[q] * sc;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      float t = truncf(y);
+      y = (y - t) * 128.0f;
+      unsigned b = (unsigned)((int)t & 0xff);
+      if (q < 4)
+        lo[p] |= b << (8 * q);
+      else
+        hi[p] |= b << (8 * (q - 4));
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) out[p] = make_uint2(lo[p], hi[p]);
+}
+
+template <int KIND>  // 0: generated leaf block rows, 1: non-leaf block rows from the sons' R
+__global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items,
+                                                 const EntDev* ents, const UnitDev* units,
+                                                 int side, double zeta2, double2* partial) {
+  extern __shared__ __align__(16) char lds[];
+  char* slices = lds;
+  double4* cold = reinterpret_cast<double4*>(lds + 2 * kI8Buf);  // 3 x 64 columns
+  RowData* rowd = reinterpret_cast<RowData*>(cold + 3 * 64);
+  int* rexp = reinterpret_cast<int*>(rowd + kI8Tiles * 16);
+  unsigned* rmaxb = reinterpret_cast<unsigned*>(rexp + kI8Tiles * 16);
+
+  const UnitDev u = units[blockIdx.x];
+  const ItemDev& it = items[u.item];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const bool diag = u.a0 == u.b0;
+  const int na = u.na, nb = u.nb;
+  const int ntile = diag ? na : na + nb;
+  const int npair = diag ? na * (na + 1) / 2 : na * nb;
+  const int nprod = 4 * npair;
+  const int r = it.r;
+  const int64_t ncols = u.ncols;
+  const int nch = (int)((ncols + 63) >> 6);
+  auto row0 = [&](int T) { return 16 * (T < na ? u.a0 + T : u.b0 + (T - na)); };
+
+  // ---- row data and row bounds ----
+  for (int e = tid; e < ntile * 16; e += 512) {
+    rmaxb[e] = 0u;
+    if constexpr (KIND == 0) rowd[e] = row_data<SRC_HELMHOLTZ>(g, it, row0(e >> 4) + (e & 15), side);
+  }
+  auto stage_cols = [&](int c, int buf) {
+    if constexpr (KIND == 0) {
+      if (tid < 64) {
+        int64_t j = (int64_t)c * 64 + tid;
+        cold[buf * 64 + tid] = (c < nch && j < ncols) ? it.cols[u.col_begin + j]
+                                                      : make_double4(0.0, 0.0, 0.0, 0.0);
+      }
+    }
+  };
+  // source of the non-leaf rows: row rho of [R_t1c'; R_t2c'] (zeta applied to the Gram)
+  auto inner_src = [&](int rho, int& ld) -> const float2* {
+    const ItemDev& s1 = items[it.son[0]];
+    const ItemDev& s2 = items[it.son[1]];
+    ld = 1;
+    if (rho < s1.k) {
+      ld = s1.k;
+      return reinterpret_cast<const float2*>(s1.R) + rho;
+    }
+    if (rho < r) {
+      ld = s2.k;
+      return reinterpret_cast<const float2*>(s2.R) + (rho - s1.k);
+    }
+    return nullptr;
+  };
+  __syncthreads();
+  if constexpr (KIND == 0) {
+    // leaf rows: |entry| <= |f_i| scale_e wfac_e / (4 pi dist(x_i, box of s_e)) over
+    // the column-set entries that meet the unit's column range
+    __shared__ int64_t s_e0, s_e1;
+    if (tid == 0) {
+      int64_t lo = it.ent_begin, hi = it.ent_end - 1;
+      while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (ents[mid].col_start <= u.col_begin) lo = mid;
+        else hi = mid - 1;
+      }
+      s_e0 = lo;
+      int64_t last = u.col_begin + ncols - 1;
+      hi = it.ent_end - 1;
+      while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (ents[mid].col_start <= last) lo = mid;
+        else hi = mid - 1;
+      }
+      s_e1 = lo + 1;
+    }
+    __syncthreads();
+    const int64_t e0 = s_e0, ne = s_e1 - s_e0;
+    const int nrow = ntile * 16;
+    for (int64_t q = tid; q < ne * nrow; q += 512) {
+      int rl = (int)(q % nrow);
+      const EntDev en = ents[e0 + q / nrow];
+      const RowData rw = rowd[rl];
+      if (rw.f == 0.0) continue;
+      const double* cb = g.cbox + 8 * en.s;
+      double d2 = 0.0;
+      double xs[3] = {rw.x, rw.y, rw.z};
+#pragma unroll
+      for (int a3 = 0; a3 < 3; ++a3) {
+        double t = fmax(0.0, fmax(cb[a3] - xs[a3], xs[a3] - cb[3 + a3]));
+        d2 += t * t;
+      }
+      // admissible blocks are separated from the row cluster, so d2 > 0
+      double wf = side == 0 ? cb[6] : 1.0;
+      float bnd = (float)(fabs(rw.f) * en.scale * wf * kInv4Pi / sqrt(d2));
+      atomicMax(&rmaxb[rl], __float_as_uint(bnd));
+    }
+  } else {
+    // non-leaf rows: largest |component| of the FP32 values over the unit.
+    // Thread t reads row t % nrow of every (512 / nrow)-th column (coalesced
+    // along the rows of one column)
+    const int nrow = ntile * 16, stride = 512 / nrow;
+    if (tid < stride * nrow) {
+      int rl = tid % nrow;
+      int64_t jphase = tid / nrow;
+      int ld;
+      const float2* src = inner_src(row0(rl >> 4) + (rl & 15), ld);
+      float mx = 0.0f;
+      if (src) {
+        const float2* base = src + (it.col_off + u.col_begin) * ld;
+        int64_t j = jphase;
+        for (; j + 7 * stride < ncols; j += 8 * stride) {
+          float2 v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = base[(j + q * stride) * ld];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
+        }
+        for (; j < ncols; j += stride) {
+          float2 v = base[j * ld];
+          mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
+      }
+      if (mx > 0.0f) atomicMax(&rmaxb[rl], __float_as_uint(mx));
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < ntile * 16; e += 512) {
+    float m = __uint_as_float(rmaxb[e]) * 1.01f;
+    int E = m > 0.0f ? ilogbf(m) + 1 : -100000;
+    rexp[e] = E > -100 ? E : -100000;   // rows below 2^-100 are taken as zero
+  }
+  __syncthreads();
+
+  // ---- produce: entries of chunk c, sliced into buffer buf ----
+  // non-leaf: the raw values of a chunk are loaded into registers one
+  // iteration before they are sliced
+  float2 raw[2][8];
+  auto load_raw = [&](int c) {
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      int cb = tid + 512 * h2;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) raw[h2][q] = make_float2(0.0f, 0.0f);
+      if (cb < ntile * 128 && c < nch) {
+        int i = cb & 15, hh = (cb >> 4) & 1, gg = (cb >> 5) & 3, T = cb >> 7;
+        int ld;
+        const float2* src = inner_src(row0(T) + i, ld);
+        int64_t j0 = (int64_t)c * 64 + 16 * gg + 8 * hh;
+        if (src) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (j0 + q < ncols) raw[h2][q] = src[(it.col_off + u.col_begin + j0 + q) * ld];
+        }
+      }
+    }
+  };
+  auto produce = [&](int c, int buf) {
+    char* S = slices + buf * kI8Buf;
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      int cb = tid + 512 * h2;
+      if (cb < ntile * 128) {
+        int i = cb & 15, hh = (cb >> 4) & 1, gg = (cb >> 5) & 3, T = cb >> 7;
+        int E = rexp[T * 16 + i];
+        float sc = E > -100000 ? ldexpf(1.0f, 7 - E) : 0.0f;
+        float vr[8], vi[8];
+        if constexpr (KIND == 0) {
+          const RowData rw = rowd[T * 16 + i];
+          const double4* cc = cold + (c % 3) * 64 + 16 * gg + 8 * hh;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            double2 v = gen_entry<SRC_HELMHOLTZ, true>(g, rw, cc[q], side);
+            vr[q] = (float)v.x;
+            vi[q] = (float)v.y;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            vr[q] = raw[h2][q].x;
+            vi[q] = raw[h2][q].y;
+          }
+        }
+        uint2 pr[4], pi[4];
+        i8_slice8(vr, sc, pr);
+        i8_slice8(vi, sc, pi);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          *reinterpret_cast<uint2*>(S + i8_off(T, 0, p, gg, i) + 8 * hh) = pr[p];
+          *reinterpret_cast<uint2*>(S + i8_off(T, 1, p, gg, i) + 8 * hh) = pi[p];
+        }
+      }
+    }
+  };
+
+  ivec4 acc[5][6];
+#pragma unroll
+  for (int s = 0; s < 5; ++s)
+#pragma unroll
+    for (int l = 0; l < 6; ++l) acc[s][l] = ivec4{0, 0, 0, 0};
+  // product q = 4 pair + type; type 0: re re, 1: im im, 2: im re, 3: re im
+  auto tiles_of = [&](int q, int& TA, int& TB, int& cA, int& cB) {
+    int pair = q >> 2, type = q & 3;
+    if (diag) {
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= pair) ++I;
+      TA = I;
+      TB = pair - I * (I + 1) / 2;
+    } else {
+      TA = pair / nb;
+      TB = na + pair % nb;
+    }
+    cA = (type == 1 || type == 2) ? 1 : 0;
+    cB = (type == 1 || type == 3) ? 1 : 0;
+  };
+  auto consume = [&](int buf) {
+    const char* S = slices + buf * kI8Buf;
+    int gg = lane >> 4, i = lane & 15;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      int q = w + 8 * s;
+      if (q < nprod) {
+        int TA, TB, cA, cB;
+        tiles_of(q, TA, TB, cA, cB);
+        ivec4 a[4], b[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          a[p] = *reinterpret_cast<const ivec4*>(S + i8_off(TA, cA, p, gg, i));
+          b[p] = *reinterpret_cast<const ivec4*>(S + i8_off(TB, cB, p, gg, i));
+        }
+        acc[s][0] = mfma_i8(a[0], b[0], acc[s][0]);
+        acc[s][1] = mfma_i8(a[0], b[1], acc[s][1]);
+        acc[s][1] = mfma_i8(a[1], b[0], acc[s][1]);
+        acc[s][2] = mfma_i8(a[0], b[2], acc[s][2]);
+        acc[s][2] = mfma_i8(a[1], b[1], acc[s][2]);
+        acc[s][2] = mfma_i8(a[2], b[0], acc[s][2]);
+        acc[s][3] = mfma_i8(a[0], b[3], acc[s][3]);
+        acc[s][3] = mfma_i8(a[1], b[2], acc[s][3]);
+        acc[s][3] = mfma_i8(a[2], b[1], acc[s][3]);
+        acc[s][3] = mfma_i8(a[3], b[0], acc[s][3]);
+        acc[s][4] = mfma_i8(a[1], b[3], acc[s][4]);
+        acc[s][4] = mfma_i8(a[2], b[2], acc[s][4]);
+        acc[s][4] = mfma_i8(a[3], b[1], acc[s][4]);
+        acc[s][5] = mfma_i8(a[2], b[3], acc[s][5]);
+        acc[s][5] = mfma_i8(a[3], b[2], acc[s][5]);
+      }
+    }
+  };
+
+  // ---- pipeline over the chunks ----
+  stage_cols(0, 0);
+  stage_cols(1, 1);
+  if constexpr (KIND == 1) load_raw(0);
+  __syncthreads();
+  produce(0, 0);
+  if constexpr (KIND == 1) load_raw(1);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    stage_cols(c + 2, (c + 2) % 3);
+    if (c + 1 < nch) produce(c + 1, (c + 1) & 1);
+    if constexpr (KIND == 1) load_raw(c + 2);
+    consume(c & 1);
+    __syncthreads();
+  }
+
+  // ---- FP64 conversion: real tile products to LDS, then complex pairs ----
+  double* conv = reinterpret_cast<double*>(lds);  // nprod x 256, over the slice buffers
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    int q = w + 8 * s;
+    if (q < nprod) {
+      int TA, TB, cA, cB;
+      tiles_of(q, TA, TB, cA, cB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int row = 4 * (lane >> 4) + v, col = lane & 15;
+        double x = 0.0;
+#pragma unroll
+        for (int l = 5; l >= 0; --l) x = x * 0.0078125 + (double)acc[s][l][v];
+        int Ea = rexp[TA * 16 + row], Eb = rexp[TB * 16 + col];
+        x = (Ea > -100000 && Eb > -100000) ? ldexp(x, Ea + Eb - 14) : 0.0;
+        conv[q * 256 + row * 16 + col] = x;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < npair * 256; e += 512) {
+    int p = e >> 8, v = (e >> 6) & 3, l = e & 63;
+    int row = (l >> 4) + 4 * v, col = l & 15, o = row * 16 + col;
+    double re = conv[(4 * p) * 256 + o] + conv[(4 * p + 1) * 256 + o];
+    double im = conv[(4 * p + 2) * 256 + o] - conv[(4 * p + 3) * 256 + o];
+    partial[u.slot_off + e] = make_double2(re * zeta2, im * zeta2);
   }
 }
 
@@ -1433,6 +1778,37 @@ void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, double eps
   }
   hipLaunchKernelGGL(k_factor, dim3(nl), dim3(256), lds, st, items, litems, eps, max_sweeps,
                      status);
+}
+
+void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int32_t* litems,
+                      int32_t nl, const EntDev* ents, int side, hipStream_t st) {
+  if (nl == 0) return;
+  if (src == SRC_HELMHOLTZ)
+    hipLaunchKernelGGL(k_leaf_cols<SRC_HELMHOLTZ>, dim3(nl), dim3(256), 0, st, g, items, litems,
+                       ents, side);
+  else
+    hipLaunchKernelGGL(k_leaf_cols<SRC_DENSE>, dim3(nl), dim3(256), 0, st, g, items, litems, ents,
+                       side);
+}
+
+void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
+                    const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
+                    hipStream_t st) {
+  if (nunits == 0) return;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_gram_i8<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)kI8Lds);
+    hipFuncSetAttribute((const void*)k_gram_i8<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)kI8Lds);
+    attr_set = true;
+  }
+  if (inner)
+    hipLaunchKernelGGL(k_gram_i8<1>, dim3((unsigned)nunits), dim3(512), kI8Lds, st, g, items,
+                       ents, units, side, zeta * zeta, partial);
+  else
+    hipLaunchKernelGGL(k_gram_i8<0>, dim3((unsigned)nunits), dim3(512), kI8Lds, st, g, items,
+                       ents, units, side, 1.0, partial);
 }
 
 void launch_rprod(int src, bool inner, bool mixed, const GeomDev& g, const ItemDev* items,

@@ -20,6 +20,14 @@ void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
                         hipStream_t st);
 void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, double eps, int max_sweeps,
                    int32_t* status, hipStream_t st);
+// Column data (x, y, z, factor) of the listed leaf items into their it.cols.
+void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int32_t* litems,
+                      int32_t nl, const EntDev* ents, int side, hipStream_t st);
+// Mixed form: Gram units of one workgroup each on int8 MFMA (leaf block rows
+// generated, non-leaf block rows from the sons' FP32 R).
+void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
+                    const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
+                    hipStream_t st);
 void launch_rprod(int src, bool inner, bool mixed, const GeomDev& g, const ItemDev* items,
                   const EntDev* ents, const UnitDev* units, int64_t nunits, double zeta, int side,
                   hipStream_t st);
