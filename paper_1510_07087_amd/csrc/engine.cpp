@@ -606,8 +606,25 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       tr_.mark("gram", s, b, lv);
       launch_gram_reduce(S.d_items, d_litems, n, d_ubegin, d_units, partial, st);
       launch_check("gram reduce");
-      launch_factor(S.d_items, d_litems, n, M.eps, 60, d_status, st);
-      launch_check("factor");
+      // factor launches by size class (LDS per workgroup follows the largest r)
+      {
+        std::vector<int32_t> fl[2];
+        int32_t rm[2] = {0, 0};
+        for (int32_t i = lo; i < hi; ++i) {
+          int c = S.items[i].r > 64 ? 1 : 0;
+          fl[c].push_back(i);
+          rm[c] = std::max(rm[c], S.items[i].r);
+        }
+        std::vector<int32_t> all(fl[0]);
+        all.insert(all.end(), fl[1].begin(), fl[1].end());
+        int32_t* d_fl = upload(mem, all, st);
+        launch_factor(S.d_items, d_fl, (int32_t)fl[0].size(), rm[0], M.eps, 60, d_status, st);
+        launch_factor(S.d_items, d_fl + fl[0].size(), (int32_t)fl[1].size(), rm[1], M.eps, 60,
+                      d_status, st);
+        launch_check("factor");
+        hip_check(hipStreamSynchronize(st), "factor sync");
+        mem.release(d_fl);
+      }
       copy_from(S.items.data() + lo, S.d_items + lo, n, st);
       int32_t status = 0;
       copy_from(&status, d_status, 1, st);
@@ -631,32 +648,51 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         }
       }
       copy_to(S.d_items + lo, S.items.data() + lo, n, st);
+      // R-product units: one workgroup per 1024 columns; leaf units first,
+      // then non-leaf units grouped by ceil(k / 16)
       std::vector<UnitDev> ru;
       int64_t nleafr = 0;
-      for (int pass = 0; pass < 2; ++pass) {
-        // leaf units are shared by a workgroup, non-leaf units by one wave
-        int64_t rwidth = pass == 0 ? 1024 : 512;
+      std::vector<std::array<int64_t, 3>> rlaunch;  // kt, count, lds bytes
+      {
+        const int64_t rwidth = 1024;
+        std::vector<UnitDev> inner_by_kt[9];
+        size_t lds_kt[9] = {0};
         for (int32_t i = lo; i < hi; ++i) {
           const ItemDev& it = S.items[i];
-          if ((pass == 0) != (it.leaf != 0) || it.k == 0) continue;
+          if (it.k == 0) continue;
+          int kt = (it.k + 15) / 16;
+          if (!it.leaf) lds_kt[kt] = std::max(lds_kt[kt], rprod_inner_lds(mixed, it.r, it.k));
           for (int64_t c0 = 0; c0 < it.N; c0 += rwidth) {
             UnitDev u{};
             u.item = i;
             u.col_begin = c0;
             u.ncols = std::min(rwidth, it.N - c0);
-            ru.push_back(u);
+            (it.leaf ? ru : inner_by_kt[kt]).push_back(u);
           }
           ss.flops_rprod += 8.0 * it.k * (double)it.r * (double)it.N;
           if (it.leaf) ss.flops_rprod_leaf += 8.0 * it.k * (double)it.r * (double)it.N;
         }
-        if (pass == 0) nleafr = (int64_t)ru.size();
+        nleafr = (int64_t)ru.size();
+        for (int kt = 1; kt <= 8; ++kt) {
+          if (inner_by_kt[kt].empty()) continue;
+          if (lds_kt[kt] > 160 * 1024)
+            fail(DH2_EUNSUPPORTED, "transfer matrix too large for the R-product workgroup");
+          rlaunch.push_back({kt, (int64_t)inner_by_kt[kt].size(), (int64_t)lds_kt[kt]});
+          ru.insert(ru.end(), inner_by_kt[kt].begin(), inner_by_kt[kt].end());
+        }
       }
       UnitDev* d_ru = upload(mem, ru, st);
       tr_.mark("rprod units", s, b, lv);
-      launch_rprod(M.src, false, mixed, g, S.d_items, S.d_ents, d_ru, nleafr, M.zeta, s, st);
+      launch_rprod_leaf(M.src, mixed, g, S.d_items, S.d_ents, d_ru, nleafr, s, st);
       launch_check("rprod (leaf)");
-      launch_rprod(M.src, true, mixed, g, S.d_items, S.d_ents, d_ru + nleafr,
-                   (int64_t)ru.size() - nleafr, M.zeta, s, st);
+      {
+        int64_t off = nleafr;
+        for (const auto& L : rlaunch) {
+          launch_rprod_inner(mixed, (int)L[0], S.d_items, d_ru + off, L[1], M.zeta, (size_t)L[2],
+                             st);
+          off += L[1];
+        }
+      }
       launch_check("rprod (non-leaf)");
       if (trace_on()) hip_check(hipStreamSynchronize(st), "trace sync");
       tr_.mark("rprod", s, b, lv);

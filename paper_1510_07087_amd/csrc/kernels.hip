@@ -11,6 +11,8 @@
 // row (Section 6: the basis is formed by the first k left singular vectors).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cmath>
 #include <cstdint>
 
@@ -281,20 +283,23 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const ItemDev* items, const
 // zeros past the factor), Q = first k columns of U (row-major r x k),
 // k = #{sigma > eps}.
 // ---------------------------------------------------------------------------
-constexpr int kEigLds = 9216;  // double2 elements of X (144 KiB)
+constexpr int kEigLds = 9216;  // largest X in double2 elements (144 KiB)
+constexpr int kFacThreads = 1024;
+constexpr size_t kRprodLdsMax = 160 * 1024;
 
 __device__ __forceinline__ double wave_sum(double v, int width) {
   for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* litems, double eps,
-                                                int max_sweeps, int32_t* status) {
+__global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const int32_t* litems,
+                                                        double eps, int max_sweeps, int cap,
+                                                        int32_t* status) {
   extern __shared__ double2 X[];  // column-major r x pmax
   __shared__ double d[kMaxR];
   __shared__ int done[kMaxR];
-  __shared__ double bval[4];
-  __shared__ int bidx[4];
+  __shared__ double bval[kFacThreads / 64];
+  __shared__ int bidx[kFacThreads / 64];
   __shared__ int s_piv;
   __shared__ double s_dmax;
   __shared__ int s_p;
@@ -312,12 +317,12 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
     return;
   }
   // X holds ncap columns; the pairing needs an even column count pe <= ncap
-  int ncap = kEigLds / r;
+  int ncap = cap / r;
   int pmax = r < ncap ? r : ncap;
   if ((pmax & 1) && pmax + 1 > ncap) --pmax;
 
   double dmax0 = 0.0;
-  for (int i = tid; i < r; i += 256) {
+  for (int i = tid; i < r; i += kFacThreads) {
     d[i] = Mi[i + (int64_t)i * r].x;
     done[i] = 0;
   }
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
     // argmax of d over rows not yet pivoted
     double bv = -1.0;
     int bi = -1;
-    for (int i = tid; i < r; i += 256)
+    for (int i = tid; i < r; i += kFacThreads)
       if (!done[i] && d[i] > bv) {
         bv = d[i];
         bi = i;
@@ -352,7 +357,7 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
     if (tid == 0) {
       double v = bval[0];
       int ix = bidx[0];
-      for (int q = 1; q < 4; ++q)
+      for (int q = 1; q < kFacThreads / 64; ++q)
         if (bval[q] > v || (bval[q] == v && bidx[q] >= 0 && (ix < 0 || bidx[q] < ix))) {
           v = bval[q];
           ix = bidx[q];
@@ -365,26 +370,37 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
     double dm = s_dmax;
     if (piv < 0 || !(dm > tau)) break;
     double sq = sqrt(dm), inv = 1.0 / sq;
-    for (int i = tid; i < r; i += 256) {
-      double2 v;
-      if (i == piv) {
-        v = make_double2(sq, 0.0);
-      } else if (done[i]) {
-        v = make_double2(0.0, 0.0);
-      } else {
-        double2 a = Mi[i + (int64_t)piv * r];
-        for (int q = 0; q < j; ++q) {
+    // column j: 16 lanes per row share the sum over the previous columns
+    for (int i0 = 0; i0 < r; i0 += kFacThreads / 16) {
+      int i = i0 + (tid >> 4), part = tid & 15;
+      double2 a = make_double2(0.0, 0.0);
+      if (i < r && i != piv && !done[i]) {
+        for (int q = part; q < j; q += 16) {
           double2 x = X[q * r + i], y = X[q * r + piv];
-          // a -= x * conj(y)
-          a.x -= x.x * y.x + x.y * y.y;
-          a.y -= x.y * y.x - x.x * y.y;
+          // a += x * conj(y)
+          a.x += x.x * y.x + x.y * y.y;
+          a.y += x.y * y.x - x.x * y.y;
         }
-        v = make_double2(a.x * inv, a.y * inv);
       }
-      X[j * r + i] = v;
+      for (int o = 8; o > 0; o >>= 1) {
+        a.x += __shfl_xor(a.x, o, 64);
+        a.y += __shfl_xor(a.y, o, 64);
+      }
+      if (i < r && part == 0) {
+        double2 v;
+        if (i == piv) {
+          v = make_double2(sq, 0.0);
+        } else if (done[i]) {
+          v = make_double2(0.0, 0.0);
+        } else {
+          double2 mm = Mi[i + (int64_t)piv * r];
+          v = make_double2((mm.x - a.x) * inv, (mm.y - a.y) * inv);
+        }
+        X[j * r + i] = v;
+      }
     }
     __syncthreads();
-    for (int i = tid; i < r; i += 256) {
+    for (int i = tid; i < r; i += kFacThreads) {
       if (i == piv) {
         done[i] = 1;
         d[i] = 0.0;
@@ -407,14 +423,14 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
   __syncthreads();
   p = s_p;
   int pe = p + (p & 1);
-  for (int i = tid; i < r; i += 256)
+  for (int i = tid; i < r; i += kFacThreads)
     if (pe > p) X[p * r + i] = make_double2(0.0, 0.0);
   __syncthreads();
 
   // ---- one-sided Jacobi on the columns of X (r x pe) ----
   int npair = pe / 2;
   int g = 1;
-  while (g * 2 * npair <= 256 && g < 64) g *= 2;
+  while (g * 2 * npair <= kFacThreads && g < 64) g *= 2;
   int pair = tid / g, gl = tid % g;
   int sweep = 0;
   if (pe >= 2) {
@@ -463,7 +479,7 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
   }
 
   // ---- singular values, ordering, rank ----
-  for (int q = tid; q < pe; q += 256) {
+  for (int q = tid; q < pe; q += kFacThreads) {
     double s2 = 0;
     for (int i = 0; i < r; ++i) {
       double2 x = X[q * r + i];
@@ -472,7 +488,7 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
     s_norm[q] = sqrt(s2);
   }
   __syncthreads();
-  for (int q = tid; q < pe; q += 256) {
+  for (int q = tid; q < pe; q += kFacThreads) {
     int rk = 0;
     double v = s_norm[q];
     for (int q2 = 0; q2 < pe; ++q2) {
@@ -486,12 +502,12 @@ __global__ __launch_bounds__(256) void k_factor(ItemDev* items, const int32_t* l
   for (int q = 0; q < pe; ++q)
     if (s_norm[q] > eps) ++k;
   double* sg = it.sig;
-  for (int q = tid; q < r; q += 256) sg[q] = 0.0;
+  for (int q = tid; q < r; q += kFacThreads) sg[q] = 0.0;
   __syncthreads();
-  for (int q = tid; q < pe; q += 256)
+  for (int q = tid; q < pe; q += kFacThreads)
     if (s_rank[q] < r) sg[s_rank[q]] = s_norm[q];  // the zero pad column may rank r
   double2* Q = it.Q;  // row-major r x k
-  for (int e = tid; e < pe * r; e += 256) {
+  for (int e = tid; e < pe * r; e += kFacThreads) {
     int q = e / r, i = e - q * r;
     int rk = s_rank[q];
     if (rk < k) {
@@ -1204,7 +1220,19 @@ __global__ __launch_bounds__(256) void k_gram_inner_w(const ItemDev* items, cons
 }
 
 // One complex multiply-accumulate of the R-product on MFMA:
-// acc += A^T conj(Q) (re = ar qr + ai qi, im = ai qr - ar qi).
+// acc += A^T conj(Q) (re = ar qr + ai qi, im = ai qr - ar qi).  Operands are
+// complex FP64, or complex FP32 in the mixed form.
+template <bool MX>
+using ROp = typename std::conditional<MX, float2, double2>::type;
+
+template <bool MX>
+__device__ __forceinline__ ROp<MX> rop(double2 v) {
+  if constexpr (MX)
+    return make_float2((float)v.x, (float)v.y);
+  else
+    return v;
+}
+
 template <bool MX>
 struct RAcc;
 template <>
@@ -1217,51 +1245,59 @@ struct RAcc<false> {
     im = mfma_f64(-a.x, q.y, im);
   }
   __device__ __forceinline__ int row(int lane, int v) const { return f64_row(lane, v); }
-  __device__ __forceinline__ void store(void* R, int64_t idx, int v) const {
-    reinterpret_cast<double2*>(R)[idx] = make_double2(re[v], im[v]);
+  __device__ __forceinline__ void store(void* R, int64_t idx, int v, double sc = 1.0) const {
+    reinterpret_cast<double2*>(R)[idx] = make_double2(re[v] * sc, im[v] * sc);
   }
 };
 template <>
 struct RAcc<true> {
   fvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-  __device__ __forceinline__ void mac(double2 a, double2 q) {
-    float ar = (float)a.x, ai = (float)a.y, qr = (float)q.x, qi = (float)q.y;
-    re = mfma_f32(ar, qr, re);
-    re = mfma_f32(ai, qi, re);
-    im = mfma_f32(ai, qr, im);
-    im = mfma_f32(-ar, qi, im);
+  __device__ __forceinline__ void mac(float2 a, float2 q) {
+    re = mfma_f32(a.x, q.x, re);
+    re = mfma_f32(a.y, q.y, re);
+    im = mfma_f32(a.y, q.x, im);
+    im = mfma_f32(-a.x, q.y, im);
   }
   __device__ __forceinline__ int row(int lane, int v) const { return f32_row(lane, v); }
-  __device__ __forceinline__ void store(void* R, int64_t idx, int v) const {
-    reinterpret_cast<float2*>(R)[idx] = make_float2(re[v], im[v]);
+  __device__ __forceinline__ void store(void* R, int64_t idx, int v, double sc = 1.0) const {
+    float f = (float)sc;
+    reinterpret_cast<float2*>(R)[idx] = make_float2(re[v] * f, im[v] * f);
   }
 };
 
-// R^T of a non-leaf block row, one unit (column range) per wave:
-// R^T[j][kk] = sum_rho G_hat[rho][j] conj(Q_hat[rho][kk]); operands loaded
-// directly (G_hat one k-step ahead), Q_hat rows from L1/L2.
+// R^T of a non-leaf block row, one workgroup per unit (column range): the
+// four waves share Q_hat (in the compute precision) in LDS and take 16-column
+// groups in turn.  R^T[j][kk] = zeta sum_rho [R_t1c'; R_t2c'][rho][j]
+// conj(Q_hat[rho][kk]); the sons' values are loaded two k-steps ahead.
 template <bool MX, int KT>
-__device__ void rprod_inner_wave(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
-                                 const UnitDev& u, double zeta) {
-  int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
-  int r = it.r, k = it.k;
-  int nks = (r + 3) / 4;
-  for (int64_t j0 = 0; j0 < u.ncols; j0 += 16) {
-    bool valid = j0 + row < u.ncols;
-    int64_t jc = it.col_off + u.col_begin + j0 + row;
+__device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
+                               const UnitDev& u, double zeta, const ROp<MX>* Qs) {
+  using OT = ROp<MX>;
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  const int r = it.r, k = it.k, k1 = s1.k, k2 = s2.k;
+  const int nks = (r + 3) / 4;
+  constexpr int ldq = 16 * KT;
+  const OT* R1 = reinterpret_cast<const OT*>(s1.R);
+  const OT* R2 = reinterpret_cast<const OT*>(s2.R);
+  for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
+    const bool valid = j0 + row < u.ncols;
+    const int64_t jc = it.col_off + u.col_begin + j0 + row;
+    auto ld = [&](int rho) -> OT {
+      OT z;
+      z.x = 0;
+      z.y = 0;
+      if (!valid || rho >= r) return z;
+      return rho < k1 ? R1[jc * k1 + rho] : R2[jc * k2 + (rho - k1)];
+    };
     RAcc<MX> acc[KT];
-    double2 a = valid ? ghat<MX>(s1, s2, jc, kq, r, zeta) : make_double2(0.0, 0.0);
+    OT a0 = ld(kq), a1 = ld(kq + 4);
     for (int ks = 0; ks < nks; ++ks) {
       int rho = 4 * ks + kq;
-      double2 an = (valid && ks + 1 < nks) ? ghat<MX>(s1, s2, jc, rho + 4, r, zeta)
-                                           : make_double2(0.0, 0.0);
+      OT a2 = ld(rho + 8);
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        int kk = 16 * t + row;
-        double2 q = (rho < r && kk < k) ? it.Q[(int64_t)rho * k + kk] : make_double2(0.0, 0.0);
-        acc[t].mac(a, q);
-      }
-      a = an;
+      for (int t = 0; t < KT; ++t) acc[t].mac(a0, Qs[rho * ldq + 16 * t + row]);
+      a0 = a1;
+      a1 = a2;
     }
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
@@ -1269,40 +1305,37 @@ __device__ void rprod_inner_wave(const ItemDev& it, const ItemDev& s1, const Ite
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int64_t jl = j0 + acc[t].row(lane, v);
-        if (jl < u.ncols && kk < k) acc[t].store(it.R, (u.col_begin + jl) * k + kk, v);
+        if (jl < u.ncols && kk < k) acc[t].store(it.R, (u.col_begin + jl) * k + kk, v, zeta);
       }
     }
   }
 }
 
-template <bool MX>
-__global__ __launch_bounds__(256) void k_rprod_inner_w(const ItemDev* items, const UnitDev* units,
-                                                       int64_t nunits, double zeta) {
-  int w = threadIdx.x >> 6;
-  int64_t ui = (int64_t)blockIdx.x * 4 + w;
-  if (ui >= nunits) return;
-  const UnitDev u = units[ui];
+// every unit of one launch has ceil(k / 16) = KT
+template <bool MX, int KT>
+__global__ __launch_bounds__(256) void k_rprod_inner_g(const ItemDev* items, const UnitDev* units,
+                                                       double zeta) {
+  extern __shared__ __align__(16) char rlds[];
+  using OT = ROp<MX>;
+  OT* Qs = reinterpret_cast<OT*>(rlds);
+  const UnitDev u = units[blockIdx.x];
   const ItemDev& it = items[u.item];
-  if (it.k == 0) return;
-  const ItemDev& s1 = items[it.son[0]];
-  const ItemDev& s2 = items[it.son[1]];
-  switch ((it.k + 15) / 16) {
-    case 1: rprod_inner_wave<MX, 1>(it, s1, s2, u, zeta); break;
-    case 2: rprod_inner_wave<MX, 2>(it, s1, s2, u, zeta); break;
-    case 3: rprod_inner_wave<MX, 3>(it, s1, s2, u, zeta); break;
-    case 4: rprod_inner_wave<MX, 4>(it, s1, s2, u, zeta); break;
-    case 5: rprod_inner_wave<MX, 5>(it, s1, s2, u, zeta); break;
-    case 6: rprod_inner_wave<MX, 6>(it, s1, s2, u, zeta); break;
-    case 7: rprod_inner_wave<MX, 7>(it, s1, s2, u, zeta); break;
-    default: rprod_inner_wave<MX, 8>(it, s1, s2, u, zeta); break;
+  const int r = it.r, k = it.k;
+  if (k == 0 || (k + 15) / 16 != KT) return;
+  constexpr int ldq = 16 * KT;
+  for (int e = threadIdx.x; e < (r + 4) * ldq; e += 256) {
+    int i = e / ldq, kk = e - i * ldq;
+    Qs[e] = rop<MX>((i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0));
   }
+  __syncthreads();
+  rprod_inner_wg<MX, KT>(it, items[it.son[0]], items[it.son[1]], u, zeta, Qs);
 }
 
 // R^T of a leaf block row: the workgroup's four waves share the item's factor
-// Q (in LDS) and take 16-column groups in turn.
+// Q (in LDS, compute precision) and take 16-column groups in turn.
 template <int SRC, bool MX, int KT>
 __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
-                                const UnitDev& u, const double2* Qs, const RowData* rows) {
+                                const UnitDev& u, const ROp<MX>* Qs, const RowData* rows) {
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   int r = it.r, k = it.k;
   int nks = (r + 3) / 4;
@@ -1310,11 +1343,11 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
     int64_t j = u.col_begin + j0 + row;
     double4 cc = j0 + row < u.ncols ? it.cols[j] : make_double4(0.0, 0.0, 0.0, 0.0);
     RAcc<MX> acc[KT];
-    double2 a = gen_entry<SRC, MX>(g, rows[kq], cc, side);
+    auto a = rop<MX>(gen_entry<SRC, MX>(g, rows[kq], cc, side));
     for (int ks = 0; ks < nks; ++ks) {
       int rho = 4 * ks + kq;
       // next k-step's entry (rows array is padded past r)
-      double2 an = gen_entry<SRC, MX>(g, rows[rho + 4], cc, side);
+      auto an = rop<MX>(gen_entry<SRC, MX>(g, rows[rho + 4], cc, side));
 #pragma unroll
       for (int t = 0; t < KT; ++t) acc[t].mac(a, Qs[rho * (16 * KT) + 16 * t + row]);
 #pragma unroll
@@ -1340,7 +1373,7 @@ template <int SRC, bool MX>
 __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* items,
                                                       const EntDev* ents, const UnitDev* units,
                                                       int side) {
-  __shared__ double2 Qs[68 * 64];   // (r + 4) x (16 KT), zero padded rows past r
+  __shared__ ROp<MX> Qs[68 * 64];   // (r + 4) x (16 KT), zero padded rows past r
   __shared__ RowData rows[64 + 8];
   const UnitDev u = units[blockIdx.x];
   const ItemDev& it = items[u.item];
@@ -1350,7 +1383,7 @@ __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* 
   int ldq = 16 * kt;
   for (int e = threadIdx.x; e < (r + 4) * ldq; e += 256) {
     int i = e / ldq, kk = e - i * ldq;
-    Qs[e] = (i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0);
+    Qs[e] = rop<MX>((i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0));
   }
   for (int i = threadIdx.x; i < 72; i += 256) rows[i] = row_data<SRC>(g, it, i, side);
   __syncthreads();
@@ -1766,18 +1799,19 @@ void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
                      partial);
 }
 
-void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, double eps, int max_sweeps,
-                   int32_t* status, hipStream_t st) {
+void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rmax, double eps,
+                   int max_sweeps, int32_t* status, hipStream_t st) {
   if (nl == 0) return;
   static bool attr_set = false;
-  size_t lds = (size_t)kEigLds * sizeof(double2);
   if (!attr_set) {
     hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
+                        (int)(kEigLds * sizeof(double2)));
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_factor, dim3(nl), dim3(256), lds, st, items, litems, eps, max_sweeps,
-                     status);
+  // X needs r columns plus one for the even pairing
+  int cap = std::min(kEigLds, std::max(2, rmax * (rmax + 1)));
+  hipLaunchKernelGGL(k_factor, dim3(nl), dim3(kFacThreads), (size_t)cap * sizeof(double2), st,
+                     items, litems, eps, max_sweeps, cap, status);
 }
 
 void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int32_t* litems,
@@ -1811,31 +1845,64 @@ void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const En
                        ents, units, side, 1.0, partial);
 }
 
-void launch_rprod(int src, bool inner, bool mixed, const GeomDev& g, const ItemDev* items,
-                  const EntDev* ents, const UnitDev* units, int64_t nunits, double zeta, int side,
-                  hipStream_t st) {
-  if (nunits == 0) return;
-  dim3 blk(256);
-  if (inner) {
-    dim3 grid(blocks_for(nunits, 4));
-    if (mixed)
-      hipLaunchKernelGGL(k_rprod_inner_w<true>, grid, blk, 0, st, items, units, nunits, zeta);
-    else
-      hipLaunchKernelGGL(k_rprod_inner_w<false>, grid, blk, 0, st, items, units, nunits, zeta);
-  } else {
-    dim3 grid((unsigned)nunits);
-    if (src == SRC_HELMHOLTZ) {
-      if (mixed)
-        hipLaunchKernelGGL((k_rprod_leaf_w<SRC_HELMHOLTZ, true>), grid, blk, 0, st, g, items, ents,
-                           units, side);
-      else
-        hipLaunchKernelGGL((k_rprod_leaf_w<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items,
-                           ents, units, side);
-    } else {
-      hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents,
-                         units, side);
-    }
+size_t rprod_inner_lds(bool mixed, int r, int k) {
+  int kt = (k + 15) / 16;
+  return (size_t)(r + 4) * 16 * kt * (mixed ? sizeof(float2) : sizeof(double2));
+}
+
+template <bool MX, int KT>
+static void launch_rpi(const ItemDev* items, const UnitDev* units, int64_t nunits, double zeta,
+                       size_t lds, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_rprod_inner_g<MX, KT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRprodLdsMax);
+    attr_set = true;
   }
+  hipLaunchKernelGGL((k_rprod_inner_g<MX, KT>), dim3((unsigned)nunits), dim3(256), lds, st, items,
+                     units, zeta);
+}
+
+template <bool MX>
+static void launch_rpi_kt(int kt, const ItemDev* items, const UnitDev* units, int64_t nunits,
+                          double zeta, size_t lds, hipStream_t st) {
+  switch (kt) {
+    case 1: launch_rpi<MX, 1>(items, units, nunits, zeta, lds, st); break;
+    case 2: launch_rpi<MX, 2>(items, units, nunits, zeta, lds, st); break;
+    case 3: launch_rpi<MX, 3>(items, units, nunits, zeta, lds, st); break;
+    case 4: launch_rpi<MX, 4>(items, units, nunits, zeta, lds, st); break;
+    case 5: launch_rpi<MX, 5>(items, units, nunits, zeta, lds, st); break;
+    case 6: launch_rpi<MX, 6>(items, units, nunits, zeta, lds, st); break;
+    case 7: launch_rpi<MX, 7>(items, units, nunits, zeta, lds, st); break;
+    default: launch_rpi<MX, 8>(items, units, nunits, zeta, lds, st); break;
+  }
+}
+
+void launch_rprod_leaf(int src, bool mixed, const GeomDev& g, const ItemDev* items,
+                       const EntDev* ents, const UnitDev* units, int64_t nunits, int side,
+                       hipStream_t st) {
+  if (nunits == 0) return;
+  dim3 blk(256), grid((unsigned)nunits);
+  if (src == SRC_HELMHOLTZ) {
+    if (mixed)
+      hipLaunchKernelGGL((k_rprod_leaf_w<SRC_HELMHOLTZ, true>), grid, blk, 0, st, g, items, ents,
+                         units, side);
+    else
+      hipLaunchKernelGGL((k_rprod_leaf_w<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents,
+                         units, side);
+  } else {
+    hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents,
+                       units, side);
+  }
+}
+
+void launch_rprod_inner(bool mixed, int kt, const ItemDev* items, const UnitDev* units,
+                        int64_t nunits, double zeta, size_t lds, hipStream_t st) {
+  if (nunits == 0) return;
+  if (mixed)
+    launch_rpi_kt<true>(kt, items, units, nunits, zeta, lds, st);
+  else
+    launch_rpi_kt<false>(kt, items, units, nunits, zeta, lds, st);
 }
 
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st) {

@@ -18,8 +18,8 @@ void launch_gram(int src, bool inner, bool mixed, const GeomDev& g, const ItemDe
 void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
                         const int32_t* ubegin, const UnitDev* units, const double2* partial,
                         hipStream_t st);
-void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, double eps, int max_sweeps,
-                   int32_t* status, hipStream_t st);
+void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rmax, double eps,
+                   int max_sweeps, int32_t* status, hipStream_t st);
 // Column data (x, y, z, factor) of the listed leaf items into their it.cols.
 void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int32_t* litems,
                       int32_t nl, const EntDev* ents, int side, hipStream_t st);
@@ -28,9 +28,15 @@ void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int
 void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
                     const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
                     hipStream_t st);
-void launch_rprod(int src, bool inner, bool mixed, const GeomDev& g, const ItemDev* items,
-                  const EntDev* ents, const UnitDev* units, int64_t nunits, double zeta, int side,
-                  hipStream_t st);
+// LDS bytes of the non-leaf R-product workgroup for an item (r rows, rank k)
+size_t rprod_inner_lds(bool mixed, int r, int k);
+// R-products: one workgroup per unit; non-leaf launches hold units of items
+// with ceil(k / 16) = kt only
+void launch_rprod_leaf(int src, bool mixed, const GeomDev& g, const ItemDev* items,
+                       const EntDev* ents, const UnitDev* units, int64_t nunits, int side,
+                       hipStream_t st);
+void launch_rprod_inner(bool mixed, int kt, const ItemDev* items, const UnitDev* units,
+                        int64_t nunits, double zeta, size_t lds, hipStream_t st);
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
                    int64_t count, hipStream_t st);
