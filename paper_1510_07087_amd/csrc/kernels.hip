@@ -999,14 +999,16 @@ __device__ __forceinline__ RowData row_data(const GeomDev& g, const ItemDev& it,
 }
 
 // entry of the weighted block row from staged row and column data
+// Entry of the weighted block row from staged row and column data.  No
+// branch: padding rows and columns carry factor 0 (the distance is clamped so
+// that 0 * 1/r stays 0), which lets the compiler interleave several entries.
 template <int SRC, bool MX>
 __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw, double4 cc,
                                              int side) {
   double f = rw.f * cc.w;
-  if (f == 0.0) return make_double2(0.0, 0.0);
   if constexpr (SRC == SRC_HELMHOLTZ) {
     double dx = rw.x - cc.x, dy = rw.y - cc.y, dz = rw.z - cc.z;
-    double r2 = dx * dx + dy * dy + dz * dz;
+    double r2 = fmax(dx * dx + dy * dy + dz * dz, 1e-300);
     double ri = rsqrt_nr(r2);
     if constexpr (MX) {
       float sn, cs;
@@ -1025,6 +1027,19 @@ __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw
     double2 v = side == 0 ? G[i * g.ldg + j] : G[j * g.ldg + i];
     return make_double2(v.x * f, (side == 0 ? v.y : -v.y) * f);
   }
+}
+
+// Mixed form, Helmholtz: the same entry as complex FP32.
+__device__ __forceinline__ float2 gen_entry_mx(const GeomDev& g, const RowData& rw, double4 cc,
+                                               int side) {
+  double f = rw.f * cc.w;
+  double dx = rw.x - cc.x, dy = rw.y - cc.y, dz = rw.z - cc.z;
+  double r2 = fmax(dx * dx + dy * dy + dz * dz, 1e-300);
+  double ri = rsqrt_nr(r2);
+  float sn, cs;
+  sincos_mixed(g.kappa * (r2 * ri), sn, cs);
+  float a = (float)(f * ri);
+  return make_float2(a * cs, side == 0 ? a * sn : -a * sn);
 }
 
 // Gram of a leaf block row, one unit per wave, all lower tile pairs.  The
@@ -1427,21 +1442,23 @@ __device__ __forceinline__ int i8_off(int T, int comp, int p, int g, int i) {
   return ((((T * 2 + comp) * 4 + p) * 4 + g) * 16 + i) * 16;
 }
 
-// four int8 slices of 8 values scaled by sc (|v sc| < 128), packed two dwords each
+// Four int8 slices of 8 values, packed two dwords each.  sc = 2^(28 - E)
+// with |v| < 2^E, so Y = trunc(v sc) fits 28 bits and
+// Y = q1 2^21 + q2 2^14 + q3 2^7 + q4 exactly, with q1 = floor(Y / 2^21) in
+// [-128, 127] and q2, q3, q4 in [0, 127] (two's complement bit fields).
 __device__ __forceinline__ void i8_slice8(const float* v, float sc, uint2* out) {
   unsigned lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    float y = v[q] * sc;
+    int Y = (int)(v[q] * sc);
+    unsigned u = (unsigned)Y;
+    unsigned b[4] = {(unsigned)(Y >> 21) & 0xffu, (u >> 14) & 0x7fu, (u >> 7) & 0x7fu, u & 0x7fu};
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      float t = truncf(y);
-      y = (y - t) * 128.0f;
-      unsigned b = (unsigned)((int)t & 0xff);
       if (q < 4)
-        lo[p] |= b << (8 * q);
+        lo[p] |= b[p] << (8 * q);
       else
-        hi[p] |= b << (8 * (q - 4));
+        hi[p] |= b[p] << (8 * (q - 4));
     }
   }
 #pragma unroll
@@ -1525,24 +1542,28 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
     }
     __syncthreads();
     const int64_t e0 = s_e0, ne = s_e1 - s_e0;
-    const int nrow = ntile * 16;
-    for (int64_t q = tid; q < ne * nrow; q += 512) {
-      int rl = (int)(q % nrow);
-      const EntDev en = ents[e0 + q / nrow];
+    const int nrow = ntile * 16, stride = 512 / nrow;
+    if (tid < stride * nrow) {
+      const int rl = tid % nrow;
       const RowData rw = rowd[rl];
-      if (rw.f == 0.0) continue;
-      const double* cb = g.cbox + 8 * en.s;
-      double d2 = 0.0;
-      double xs[3] = {rw.x, rw.y, rw.z};
+      float mx = 0.0f;
+      if (rw.f != 0.0) {
+        for (int64_t q = tid / nrow; q < ne; q += stride) {
+          const EntDev en = ents[e0 + q];
+          const double* cb = g.cbox + 8 * en.s;
+          double d2 = 0.0;
+          double xs[3] = {rw.x, rw.y, rw.z};
 #pragma unroll
-      for (int a3 = 0; a3 < 3; ++a3) {
-        double t = fmax(0.0, fmax(cb[a3] - xs[a3], xs[a3] - cb[3 + a3]));
-        d2 += t * t;
+          for (int a3 = 0; a3 < 3; ++a3) {
+            double t = fmax(0.0, fmax(cb[a3] - xs[a3], xs[a3] - cb[3 + a3]));
+            d2 += t * t;
+          }
+          // admissible blocks are separated from the row cluster, so d2 > 0
+          double wf = side == 0 ? cb[6] : 1.0;
+          mx = fmaxf(mx, (float)(fabs(rw.f) * en.scale * wf * kInv4Pi / sqrt(d2)));
+        }
       }
-      // admissible blocks are separated from the row cluster, so d2 > 0
-      double wf = side == 0 ? cb[6] : 1.0;
-      float bnd = (float)(fabs(rw.f) * en.scale * wf * kInv4Pi / sqrt(d2));
-      atomicMax(&rmaxb[rl], __float_as_uint(bnd));
+      if (mx > 0.0f) atomicMax(&rmaxb[rl], __float_as_uint(mx));
     }
   } else {
     // non-leaf rows: largest |component| of the FP32 values over the unit.
@@ -1612,16 +1633,16 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
       if (cb < ntile * 128) {
         int i = cb & 15, hh = (cb >> 4) & 1, gg = (cb >> 5) & 3, T = cb >> 7;
         int E = rexp[T * 16 + i];
-        float sc = E > -100000 ? ldexpf(1.0f, 7 - E) : 0.0f;
+        float sc = E > -100000 ? ldexpf(1.0f, 28 - E) : 0.0f;
         float vr[8], vi[8];
         if constexpr (KIND == 0) {
           const RowData rw = rowd[T * 16 + i];
           const double4* cc = cold + (c % 3) * 64 + 16 * gg + 8 * hh;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            double2 v = gen_entry<SRC_HELMHOLTZ, true>(g, rw, cc[q], side);
-            vr[q] = (float)v.x;
-            vi[q] = (float)v.y;
+            float2 v = gen_entry_mx(g, rw, cc[q], side);
+            vr[q] = v.x;
+            vi[q] = v.y;
           }
         } else {
 #pragma unroll
