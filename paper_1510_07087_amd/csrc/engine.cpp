@@ -969,8 +969,10 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   M.S_rows.assign(nadm, 0);
   M.S_cols.assign(nadm, 0);
 
-  int32_t* d_status = (int32_t*)mem.alloc(sizeof(int32_t));
-  hip_check(hipMemsetAsync(d_status, 0, sizeof(int32_t), st), "memset");
+  // status[0]: error bits of the factorisation; status[1], status[2]: Jacobi
+  // sweeps and factorisations (statistics)
+  int32_t* d_status = (int32_t*)mem.alloc(4 * sizeof(int32_t));
+  hip_check(hipMemsetAsync(d_status, 0, 4 * sizeof(int32_t), st), "memset");
 
   // block weights and column scales
   hip_check(hipEventRecord(e0, st), "event");
@@ -1062,6 +1064,12 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   trc.mark("sweeps+near", -1, -1, -1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (trace_on()) {
+    int32_t stat[4];
+    copy_from(stat, d_status, 4, st);
+    std::fprintf(stderr, "[dh2 trace] factorisations %d, mean Jacobi sweeps %.2f\n", stat[2],
+                 stat[2] ? (double)stat[1] / stat[2] : 0.0);
+  }
   mem.release(d_status);
   // the dense matrix is borrowed only for this call
   M.omega.resize(nadm);

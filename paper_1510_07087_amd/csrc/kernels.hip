@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const ItemDev* items, const
 // k = #{sigma > eps}.
 // ---------------------------------------------------------------------------
 constexpr int kEigLds = 9216;  // largest X in double2 elements (144 KiB)
-constexpr int kFacThreads = 1024;
+constexpr int kFacThreads = 256;
 constexpr size_t kRprodLdsMax = 160 * 1024;
 
 __device__ __forceinline__ double wave_sum(double v, int width) {
@@ -298,8 +298,8 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
   extern __shared__ double2 X[];  // column-major r x pmax
   __shared__ double d[kMaxR];
   __shared__ int done[kMaxR];
-  __shared__ double bval[kFacThreads / 64];
-  __shared__ int bidx[kFacThreads / 64];
+  __shared__ double bval[4];
+  __shared__ int bidx[4];
   __shared__ int s_piv;
   __shared__ double s_dmax;
   __shared__ int s_p;
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
   if ((pmax & 1) && pmax + 1 > ncap) --pmax;
 
   double dmax0 = 0.0;
-  for (int i = tid; i < r; i += kFacThreads) {
+  for (int i = tid; i < r; i += 256) {
     d[i] = Mi[i + (int64_t)i * r].x;
     done[i] = 0;
   }
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
     // argmax of d over rows not yet pivoted
     double bv = -1.0;
     int bi = -1;
-    for (int i = tid; i < r; i += kFacThreads)
+    for (int i = tid; i < r; i += 256)
       if (!done[i] && d[i] > bv) {
         bv = d[i];
         bi = i;
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
     if (tid == 0) {
       double v = bval[0];
       int ix = bidx[0];
-      for (int q = 1; q < kFacThreads / 64; ++q)
+      for (int q = 1; q < 4; ++q)
         if (bval[q] > v || (bval[q] == v && bidx[q] >= 0 && (ix < 0 || bidx[q] < ix))) {
           v = bval[q];
           ix = bidx[q];
@@ -370,37 +370,26 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
     double dm = s_dmax;
     if (piv < 0 || !(dm > tau)) break;
     double sq = sqrt(dm), inv = 1.0 / sq;
-    // column j: 16 lanes per row share the sum over the previous columns
-    for (int i0 = 0; i0 < r; i0 += kFacThreads / 16) {
-      int i = i0 + (tid >> 4), part = tid & 15;
-      double2 a = make_double2(0.0, 0.0);
-      if (i < r && i != piv && !done[i]) {
-        for (int q = part; q < j; q += 16) {
+    for (int i = tid; i < r; i += 256) {
+      double2 v;
+      if (i == piv) {
+        v = make_double2(sq, 0.0);
+      } else if (done[i]) {
+        v = make_double2(0.0, 0.0);
+      } else {
+        double2 a = Mi[i + (int64_t)piv * r];
+        for (int q = 0; q < j; ++q) {
           double2 x = X[q * r + i], y = X[q * r + piv];
-          // a += x * conj(y)
-          a.x += x.x * y.x + x.y * y.y;
-          a.y += x.y * y.x - x.x * y.y;
+          // a -= x * conj(y)
+          a.x -= x.x * y.x + x.y * y.y;
+          a.y -= x.y * y.x - x.x * y.y;
         }
+        v = make_double2(a.x * inv, a.y * inv);
       }
-      for (int o = 8; o > 0; o >>= 1) {
-        a.x += __shfl_xor(a.x, o, 64);
-        a.y += __shfl_xor(a.y, o, 64);
-      }
-      if (i < r && part == 0) {
-        double2 v;
-        if (i == piv) {
-          v = make_double2(sq, 0.0);
-        } else if (done[i]) {
-          v = make_double2(0.0, 0.0);
-        } else {
-          double2 mm = Mi[i + (int64_t)piv * r];
-          v = make_double2((mm.x - a.x) * inv, (mm.y - a.y) * inv);
-        }
-        X[j * r + i] = v;
-      }
+      X[j * r + i] = v;
     }
     __syncthreads();
-    for (int i = tid; i < r; i += kFacThreads) {
+    for (int i = tid; i < r; i += 256) {
       if (i == piv) {
         done[i] = 1;
         d[i] = 0.0;
@@ -423,14 +412,14 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
   __syncthreads();
   p = s_p;
   int pe = p + (p & 1);
-  for (int i = tid; i < r; i += kFacThreads)
+  for (int i = tid; i < r; i += 256)
     if (pe > p) X[p * r + i] = make_double2(0.0, 0.0);
   __syncthreads();
 
   // ---- one-sided Jacobi on the columns of X (r x pe) ----
   int npair = pe / 2;
   int g = 1;
-  while (g * 2 * npair <= kFacThreads && g < 64) g *= 2;
+  while (g * 2 * npair <= 256 && g < 64) g *= 2;
   int pair = tid / g, gl = tid % g;
   int sweep = 0;
   if (pe >= 2) {
@@ -476,10 +465,14 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
       if (!rot) break;
     }
     if (sweep == max_sweeps && tid == 0) atomicMax(status, 2);
+    if (tid == 0) {
+      atomicAdd(status + 1, sweep + 1);
+      atomicAdd(status + 2, 1);
+    }
   }
 
   // ---- singular values, ordering, rank ----
-  for (int q = tid; q < pe; q += kFacThreads) {
+  for (int q = tid; q < pe; q += 256) {
     double s2 = 0;
     for (int i = 0; i < r; ++i) {
       double2 x = X[q * r + i];
@@ -488,7 +481,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
     s_norm[q] = sqrt(s2);
   }
   __syncthreads();
-  for (int q = tid; q < pe; q += kFacThreads) {
+  for (int q = tid; q < pe; q += 256) {
     int rk = 0;
     double v = s_norm[q];
     for (int q2 = 0; q2 < pe; ++q2) {
@@ -502,12 +495,12 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
   for (int q = 0; q < pe; ++q)
     if (s_norm[q] > eps) ++k;
   double* sg = it.sig;
-  for (int q = tid; q < r; q += kFacThreads) sg[q] = 0.0;
+  for (int q = tid; q < r; q += 256) sg[q] = 0.0;
   __syncthreads();
-  for (int q = tid; q < pe; q += kFacThreads)
+  for (int q = tid; q < pe; q += 256)
     if (s_rank[q] < r) sg[s_rank[q]] = s_norm[q];  // the zero pad column may rank r
   double2* Q = it.Q;  // row-major r x k
-  for (int e = tid; e < pe * r; e += kFacThreads) {
+  for (int e = tid; e < pe * r; e += 256) {
     int q = e / r, i = e - q * r;
     int rk = s_rank[q];
     if (rk < k) {
