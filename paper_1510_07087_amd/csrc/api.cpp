@@ -313,9 +313,9 @@ dh2_status dh2_basis_export(dh2_matrix m, int32_t side, int32_t* nitems, int64_t
     const Side& S = m->d->side[side];
     int64_t ns = 0, nm = 0;
     for (int32_t e = 0; e < S.nitems; ++e) {
-      const ItemDev& it = S.items[S.ext2int[e]];
-      if (item_t) item_t[e] = S.t[S.ext2int[e]];
-      if (item_c) item_c[e] = S.c[S.ext2int[e]];
+      const ItemDev& it = S.items[S.P->ext2int[e]];
+      if (item_t) item_t[e] = S.P->t[S.P->ext2int[e]];
+      if (item_c) item_c[e] = S.P->c[S.P->ext2int[e]];
       if (item_k) item_k[e] = it.k;
       if (item_r) item_r[e] = it.r;
       if (sig_off) sig_off[e] = ns;

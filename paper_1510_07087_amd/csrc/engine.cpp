@@ -292,12 +292,13 @@ static int32_t first_adm_level(const BlocksData& B) {
   return l;
 }
 
-static void build_side(MatrixData& M, int s, const std::vector<int32_t>& batch_of_cluster) {
-  const BlocksData& B = *M.blk;
+static std::shared_ptr<SidePlan> build_side_plan(const BlocksData& B, int s, int32_t nb,
+                                                 const std::vector<int32_t>& batch_of_cluster) {
+  auto SP = std::make_shared<SidePlan>();
+  SidePlan& S = *SP;
   const ClusterTree& tr = B.tree->tr;
   const Directions& dr = B.tree->dr;
   const ColumnSets& cs = B.cs[s];
-  Side& S = M.side[s];
   int32_t ni = cs.nitems();
   S.nitems = ni;
   // internal order: (batch, level descending, external index)
@@ -313,7 +314,7 @@ static void build_side(MatrixData& M, int s, const std::vector<int32_t>& batch_o
   S.int2ext = order;
   S.ext2int.assign(ni, -1);
   for (int32_t i = 0; i < ni; ++i) S.ext2int[order[i]] = i;
-  S.items.assign(ni, ItemDev{});
+  S.items0.assign(ni, ItemDev{});
   S.t.resize(ni);
   S.c.resize(ni);
   S.ent_col.assign(cs.ent.size(), 0);
@@ -347,12 +348,11 @@ static void build_side(MatrixData& M, int s, const std::vector<int32_t>& batch_o
     S.ents.reserve(nent);
   }
   std::vector<int32_t> son_ext(2 * (size_t)ni, -1);
-  int32_t nb = M.nbatch;
   S.range.assign(nb, std::vector<std::pair<int32_t, int32_t>>(tr.depth + 1, {0, 0}));
   for (int32_t i = 0; i < ni; ++i) {
     int32_t e = order[i];
     int32_t t = cs.item_t[e], c = cs.item_c[e];
-    ItemDev& it = S.items[i];
+    ItemDev& it = S.items0[i];
     S.t[i] = t;
     S.c[i] = c;
     it.row_off = tr.off[t];
@@ -395,17 +395,73 @@ static void build_side(MatrixData& M, int s, const std::vector<int32_t>& batch_o
     else rg.second = i + 1;
   }
   for (int32_t i = 0; i < ni; ++i)
-    if (!S.items[i].leaf)
+    if (!S.items0[i].leaf)
       for (int q = 0; q < 2; ++q) {
         int32_t so = S.ext2int[son_ext[2 * (size_t)i + q]];
-        S.items[i].son[q] = so;
+        S.items0[i].son[q] = so;
         // the kernels read columns col_off .. col_off+N of the son's R
-        if (S.items[i].col_off + S.items[i].N > S.items[so].N ||
-            S.items[so].level != S.items[i].level + 1)
+        if (S.items0[i].col_off + S.items0[i].N > S.items0[so].N ||
+            S.items0[so].level != S.items0[i].level + 1)
           fail(DH2_EDEVICE, "internal: inconsistent column sets");
       }
-  S.wexp.assign(ni, nullptr);
+  return SP;
 }
+
+// Projection tasks of the row sweep per (batch, level), sorted by column item.
+static std::vector<std::vector<ProjPlan>> build_proj_plan(const BlocksData& B, const SidePlan& R,
+                                                          const SidePlan& C, int32_t nb) {
+  const ClusterTree& tr = B.tree->tr;
+  const ColumnSets& cs = B.cs[0];
+  std::vector<std::vector<ProjPlan>> out((size_t)nb * (tr.depth + 1));
+  for (int32_t b = 0; b < nb; ++b)
+    for (int32_t lv = 0; lv <= tr.depth; ++lv) {
+      auto [lo, hi] = R.range[b][lv];
+      auto& v = out[(size_t)b * (tr.depth + 1) + lv];
+      for (int32_t i = lo; i < hi; ++i) {
+        int32_t e = R.int2ext[i];
+        for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) {
+          const ColEntry& ce = cs.ent[q];
+          if (ce.d != 0) continue;
+          int32_t we = B.cs[1].find(ce.s, R.c[i]);
+          if (we < 0) fail(DH2_EDEVICE, "internal: column item missing");
+          v.push_back(ProjPlan{i, C.ext2int[we], ce.b, (int32_t)tr.size[ce.s], R.ent_col[q]});
+        }
+      }
+      std::stable_sort(v.begin(), v.end(),
+                       [](const ProjPlan& x, const ProjPlan& y) { return x.witem < y.witem; });
+    }
+  return out;
+}
+
+PlanCache::~PlanCache() {
+  for (int s = 0; s < 2; ++s)
+    if (d_ents[s]) (void)hipFree(d_ents[s]);
+}
+
+// The plan cache of a block tree for nb batches (built on first use).
+static std::shared_ptr<PlanCache> plan_cache(const BlocksData& B, int32_t nb,
+                                             const std::vector<int32_t>& batch_of) {
+  std::lock_guard<std::mutex> lk(B.cache_mu);
+  if (B.cache && B.cache->nbatch == nb) return B.cache;
+  auto C = std::make_shared<PlanCache>();
+  C->nbatch = nb;
+  auto s0 = build_side_plan(B, 0, nb, batch_of);
+  auto s1 = build_side_plan(B, 1, nb, batch_of);
+  C->proj = build_proj_plan(B, *s0, *s1, nb);
+  C->side[0] = s0;
+  C->side[1] = s1;
+  for (int s = 0; s < 2; ++s) {
+    const auto& ents = C->side[s]->ents;
+    if (ents.empty()) continue;
+    hip_check(hipMalloc(&C->d_ents[s], ents.size() * sizeof(EntDev)), "hipMalloc (plan)");
+    hip_check(hipMemcpy(C->d_ents[s], ents.data(), ents.size() * sizeof(EntDev),
+                        hipMemcpyHostToDevice),
+              "upload (plan)");
+  }
+  B.cache = C;
+  return C;
+}
+
 
 // ---------------------------------------------------------------------------
 // compression
@@ -448,7 +504,6 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
                   int32_t* d_status) {
   const BlocksData& B = *M.blk;
   const ClusterTree& tr = B.tree->tr;
-  const ColumnSets& cs = B.cs[s];
   Side& S = M.side[s];
   DevMem& mem = *M.mem;
   PhaseTimer tg(st), tp(st), tgl(st);
@@ -460,7 +515,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
   for (int32_t b = 0; b < M.nbatch; ++b) {
     void* R_prev = nullptr;
     for (int32_t lv = tr.depth; lv >= 0; --lv) {
-      auto [lo, hi] = S.range[b][lv];
+      auto [lo, hi] = S.P->range[b][lv];
       if (lo == hi) continue;
       int32_t n = hi - lo;
       tr_.mark("level start", s, b, lv);
@@ -698,73 +753,59 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       tr_.mark("rprod", s, b, lv);
       // projection of the admissible blocks of this level (row sweep)
       if (s == 0) {
-        std::vector<ProjDev> tasks;
+        // tasks in the plan's order (sorted by column item), coupling
+        // matrices in that order; tiled kernel for ks <= 64, one launch per
+        // (row tiles per pass, column tiles); ranks above 64 by the generic
+        // kernel
+        const auto& pl = M.plan->proj[(size_t)b * (tr.depth + 1) + lv];
         int64_t sumS = 0;
-        for (int32_t i = lo; i < hi; ++i) {
-          int32_t e = S.int2ext[i];
-          for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) {
-            const ColEntry& ce = cs.ent[q];
-            if (ce.d != 0) continue;
-            int32_t we = B.cs[1].find(ce.s, S.c[i]);
-            int32_t wi = M.side[1].ext2int[we];
-            sumS += (int64_t)S.items[i].k * M.side[1].items[wi].k;
-          }
-        }
-        double2* Sarena = (double2*)mem.alloc(sumS * sizeof(double2));
+        for (const ProjPlan& q : pl)
+          sumS += (int64_t)S.items[q.item].k * M.side[1].items[q.witem].k;
+        double2* Sarena = (double2*)mem.alloc(std::max<int64_t>(1, sumS) * sizeof(double2));
         S.keep.push_back(Sarena);
+        std::vector<uint8_t> key(pl.size(), 255);
+        int64_t count[17] = {0};
+        std::vector<ProjDev> tasks(pl.size());
         int64_t o = 0;
-        for (int32_t i = lo; i < hi; ++i) {
-          int32_t e = S.int2ext[i];
-          const ItemDev& it = S.items[i];
-          for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) {
-            const ColEntry& ce = cs.ent[q];
-            if (ce.d != 0) continue;
-            int32_t we = B.cs[1].find(ce.s, S.c[i]);
-            int32_t wi = M.side[1].ext2int[we];
-            int32_t ks = M.side[1].items[wi].k;
-            ProjDev pd{};
-            pd.R = (const char*)it.R + S.ent_col[q] * it.k * esz;
-            pd.W = M.side[1].wexp[wi];
-            pd.S = Sarena + o;
-            pd.kt = it.k;
-            pd.ks = ks;
-            pd.ns = (int32_t)tr.size[ce.s];
-            pd.b = ce.b;
-            M.S_ptr[ce.b] = Sarena + o;
-            M.S_rows[ce.b] = it.k;
-            M.S_cols[ce.b] = ks;
-            o += (int64_t)it.k * ks;
-            ss.flops_prj += 8.0 * it.k * (double)ks * (double)pd.ns;
-            if (it.k > 0 && ks > 0) tasks.push_back(pd);
-          }
+        for (size_t x = 0; x < pl.size(); ++x) {
+          const ProjPlan& q = pl[x];
+          const ItemDev& it = S.items[q.item];
+          int32_t ks = M.side[1].items[q.witem].k;
+          ProjDev& pd = tasks[x];
+          pd.R = (const char*)it.R + q.col * it.k * esz;
+          pd.W = M.side[1].wexp[q.witem];
+          pd.S = Sarena + o;
+          pd.kt = it.k;
+          pd.ks = ks;
+          pd.ns = q.ns;
+          pd.b = q.b;
+          M.S_ptr[q.b] = Sarena + o;
+          M.S_rows[q.b] = it.k;
+          M.S_cols[q.b] = ks;
+          o += (int64_t)it.k * ks;
+          ss.flops_prj += 8.0 * it.k * (double)ks * (double)q.ns;
+          if (it.k == 0 || ks == 0) continue;
+          int nj = (ks + 15) / 16, ni = (it.k + 15) / 16;
+          int kx = 16;  // generic kernel
+          if (nj <= 4) kx = (std::min(ni, project_rows_per_pass(mixed, nj)) - 1) * 4 + (nj - 1);
+          key[x] = (uint8_t)kx;
+          ++count[kx];
         }
-        // tiled kernel for ks <= 64, one launch per (row tiles per pass,
-        // column tiles), each sorted by expanded basis for L2 reuse; the
-        // rest (ranks above 64) by the generic kernel
+        // stable counting sort by launch class
         std::vector<ProjDev> sorted;
         std::vector<std::array<int64_t, 3>> launches;  // ni, nj, count
         {
-          std::vector<ProjDev> bucket[5][5];
-          for (const ProjDev& pd : tasks) {
-            int nj = (pd.ks + 15) / 16, ni = (pd.kt + 15) / 16;
-            if (nj > 4) {
-              bucket[0][0].push_back(pd);
-              continue;
-            }
-            ni = std::min(ni, project_rows_per_pass(mixed, nj));
-            bucket[ni][nj].push_back(pd);
+          int64_t start[17], run = 0;
+          for (int kx = 0; kx < 17; ++kx) {
+            start[kx] = run;
+            run += count[kx];
+            if (count[kx] == 0) continue;
+            if (kx < 16) launches.push_back({kx / 4 + 1, kx % 4 + 1, count[kx]});
+            else launches.push_back({0, 0, count[kx]});
           }
-          for (int ni = 1; ni <= 4; ++ni)
-            for (int nj = 1; nj <= 4; ++nj) {
-              auto& v = bucket[ni][nj];
-              if (v.empty()) continue;
-              std::stable_sort(v.begin(), v.end(),
-                               [](const ProjDev& x, const ProjDev& y) { return x.W < y.W; });
-              sorted.insert(sorted.end(), v.begin(), v.end());
-              launches.push_back({ni, nj, (int64_t)v.size()});
-            }
-          sorted.insert(sorted.end(), bucket[0][0].begin(), bucket[0][0].end());
-          launches.push_back({0, 0, (int64_t)bucket[0][0].size()});
+          sorted.resize(run);
+          for (size_t x = 0; x < pl.size(); ++x)
+            if (key[x] != 255) sorted[start[key[x]]++] = tasks[x];
         }
         ProjDev* d_tasks = upload(mem, sorted, st);
         tr_.mark("proj tasks", s, b, lv);
@@ -812,7 +853,7 @@ static void expand_side(MatrixData& M, int s, hipStream_t st) {
     std::vector<int32_t> idx;
     int64_t total = 0;
     for (int32_t b = 0; b < M.nbatch; ++b)
-      for (int32_t i = S.range[b][lv].first; i < S.range[b][lv].second; ++i) {
+      for (int32_t i = S.P->range[b][lv].first; i < S.P->range[b][lv].second; ++i) {
         idx.push_back(i);
         if (!S.items[i].leaf) total += (int64_t)S.items[i].m * S.items[i].k;
       }
@@ -962,9 +1003,15 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
 
   Trace trc;
   trc.mark("setup", -1, -1, -1);
-  build_side(M, 0, batch_of);
-  build_side(M, 1, batch_of);
-  trc.mark("build sides", -1, -1, -1);
+  M.plan = plan_cache(*blk, nb, batch_of);
+  for (int s = 0; s < 2; ++s) {
+    Side& S = M.side[s];
+    S.P = M.plan->side[s];
+    S.nitems = S.P->nitems;
+    S.items = S.P->items0;
+    S.wexp.assign(S.nitems, nullptr);
+  }
+  trc.mark("plan", -1, -1, -1);
   M.S_ptr.assign(nadm, nullptr);
   M.S_rows.assign(nadm, 0);
   M.S_cols.assign(nadm, 0);
@@ -994,8 +1041,14 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     for (int s = 0; s < 2; ++s) {
       Side& S = M.side[s];
       S.d_items = upload(mem, S.items, st);
-      S.d_ents = upload(mem, S.ents, st);
-      launch_entry_scale(S.d_ents, (int64_t)S.ents.size(), M.d_omega, M.zeta, st);
+      // per-matrix copy of the plan's column entries (their scales depend on omega)
+      size_t nent = S.P->ents.size();
+      S.d_ents = (EntDev*)mem.alloc(std::max<size_t>(1, nent) * sizeof(EntDev));
+      if (nent)
+        hip_check(hipMemcpyAsync(S.d_ents, M.plan->d_ents[s], nent * sizeof(EntDev),
+                                 hipMemcpyDeviceToDevice, st),
+                  "entries copy");
+      launch_entry_scale(S.d_ents, (int64_t)nent, M.d_omega, M.zeta, st);
       launch_check("entry scales");
     }
     hip_check(hipStreamSynchronize(st), "weights sync");
@@ -1141,8 +1194,8 @@ static void build_mv(MatrixData& M, hipStream_t st) {
       int32_t t = s == 0 ? bt.adm_t[b] : bt.adm_s[b];
       int32_t o = s == 0 ? bt.adm_s[b] : bt.adm_t[b];
       int32_t c = bt.adm_c[b];
-      int32_t me = S.ext2int[B.cs[s].find(t, c)];
-      int32_t pe = M.side[1 - s].ext2int[B.cs[1 - s].find(o, c)];
+      int32_t me = S.P->ext2int[B.cs[s].find(t, c)];
+      int32_t pe = M.side[1 - s].P->ext2int[B.cs[1 - s].find(o, c)];
       lst[me].push_back({(int32_t)b, pe});
     }
     std::vector<int64_t> cb(S.nitems + 1, 0);
@@ -1176,14 +1229,14 @@ static void build_mv(MatrixData& M, hipStream_t st) {
       std::vector<int64_t> fb{0};
       for (int32_t i = 0; i < S.nitems; ++i) {
         if (S.items[i].level != l) continue;
-        int32_t t = S.t[i], c = S.c[i];
+        int32_t t = S.P->t[i], c = S.P->c[i];
         int32_t fa = tr.father[t];
         std::vector<std::pair<int32_t, int32_t>> fl;
         if (fa >= 0) {
           const auto& sdl = dr.sd[tr.level[fa]];
           const ColumnSets& cs = B.cs[s];
           for (int32_t e = cs.first[fa]; e < cs.first[fa] + cs.count[fa]; ++e)
-            if (sdl[cs.item_c[e]] == c) fl.push_back({S.ext2int[e], tr.son1[fa] == t ? 0 : 1});
+            if (sdl[cs.item_c[e]] == c) fl.push_back({S.P->ext2int[e], tr.son1[fa] == t ? 0 : 1});
         }
         if (fl.empty()) continue;
         items.push_back(i);
@@ -1224,10 +1277,10 @@ static void build_mv(MatrixData& M, hipStream_t st) {
       L.len = (int32_t)tr.size[t];
       // items of t are contiguous in internal order
       int32_t cnt = B.cs[s].count[t];
-      L.item_first = cnt ? S.ext2int[B.cs[s].first[t]] : 0;
+      L.item_first = cnt ? S.P->ext2int[B.cs[s].first[t]] : 0;
       L.item_count = cnt;
       for (int32_t q = 1; q < cnt; ++q)
-        if (S.ext2int[B.cs[s].first[t] + q] != L.item_first + q) fail(DH2_EDEVICE, "internal: leaf items not contiguous");
+        if (S.P->ext2int[B.cs[s].first[t] + q] != L.item_first + q) fail(DH2_EDEVICE, "internal: leaf items not contiguous");
       L.near_begin = (int64_t)refs.size();
       for (auto& pr : nl[t]) refs.push_back(NearRefDev{pr.first, pr.second});
       L.near_end = (int64_t)refs.size();

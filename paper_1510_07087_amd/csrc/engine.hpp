@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,27 +50,56 @@ struct TreeData {
   dh2_opts opts;
 };
 
+struct PlanCache;
+
 struct BlocksData {
   std::shared_ptr<TreeData> tree;
   BlockTree bt;
   ColumnSets cs[2];
   dh2_opts opts;
+  // plan data of the compression for the last batch count used
+  mutable std::mutex cache_mu;
+  mutable std::shared_ptr<PlanCache> cache;
 };
 
-// One basis (side 0: rows of G, side 1: rows of G^*), items in internal
-// order: sorted by (batch, level descending, cluster, direction).
-struct Side {
+// Plan-derived data of one basis for a given batch count (side 0: rows of G,
+// side 1: rows of G^*), items in internal order: sorted by (batch, level
+// descending, cluster, direction).  Built once per block tree and batch count.
+struct SidePlan {
   int32_t nitems = 0;
-  std::vector<ItemDev> items;       // host mirror of the device array
-  ItemDev* d_items = nullptr;
+  std::vector<ItemDev> items0;      // plan fields of every item
   std::vector<int32_t> ext2int;     // column-set order -> internal
   std::vector<int32_t> int2ext;
   std::vector<int32_t> t, c;        // per internal item
-  std::vector<EntDev> ents;         // leaf entries (device copy below)
-  EntDev* d_ents = nullptr;
+  std::vector<EntDev> ents;         // leaf column-set entries (scale filled per matrix)
   std::vector<int64_t> ent_col;     // per column-set entry: column start inside its item
   // (batch, level) ranges of internal items
   std::vector<std::vector<std::pair<int32_t, int32_t>>> range;  // [batch][level] -> [lo,hi)
+};
+
+// Projection task of the row sweep: admissible block b = (t, s) of row item
+// `item` whose column basis is item `witem` of side 1; per (batch, level),
+// sorted by witem (expanded bases shared in L2).
+struct ProjPlan {
+  int32_t item, witem, b, ns;
+  int64_t col;  // first column of s inside the row item
+};
+
+struct PlanCache {
+  int32_t nbatch = -1;
+  std::shared_ptr<const SidePlan> side[2];
+  std::vector<std::vector<ProjPlan>> proj;  // [batch * (depth + 1) + level]
+  EntDev* d_ents[2] = {nullptr, nullptr};   // device copies of side[s]->ents
+  ~PlanCache();
+};
+
+// One basis of a matrix under compression.
+struct Side {
+  std::shared_ptr<const SidePlan> P;
+  int32_t nitems = 0;
+  std::vector<ItemDev> items;       // host mirror of the device array
+  ItemDev* d_items = nullptr;
+  EntDev* d_ents = nullptr;
   std::vector<void*> keep;          // Q and sigma arenas
   // expanded basis (column side): per internal item pointer, rows x k row-major
   std::vector<double2*> wexp;
@@ -79,6 +109,7 @@ struct MatvecPlan;
 
 struct MatrixData {
   std::shared_ptr<BlocksData> blk;
+  std::shared_ptr<PlanCache> plan;
   std::unique_ptr<DevMem> mem;
   int src = SRC_HELMHOLTZ;
   int precision = DH2_FP64;
