@@ -436,6 +436,7 @@ static std::vector<std::vector<ProjPlan>> build_proj_plan(const BlocksData& B, c
 PlanCache::~PlanCache() {
   for (int s = 0; s < 2; ++s)
     if (d_ents[s]) (void)hipFree(d_ents[s]);
+  if (d_adm) (void)hipFree(d_adm);
 }
 
 // The plan cache of a block tree for nb batches (built on first use).
@@ -456,6 +457,20 @@ static std::shared_ptr<PlanCache> plan_cache(const BlocksData& B, int32_t nb,
     hip_check(hipMalloc(&C->d_ents[s], ents.size() * sizeof(EntDev)), "hipMalloc (plan)");
     hip_check(hipMemcpy(C->d_ents[s], ents.data(), ents.size() * sizeof(EntDev),
                         hipMemcpyHostToDevice),
+              "upload (plan)");
+  }
+  {
+    const ClusterTree& tr = B.tree->tr;
+    int64_t nadm = (int64_t)B.bt.adm_t.size();
+    std::vector<int64_t> adm(4 * (size_t)std::max<int64_t>(1, nadm), 0);
+    for (int64_t b = 0; b < nadm; ++b) {
+      adm[b] = tr.off[B.bt.adm_t[b]];
+      adm[nadm + b] = tr.size[B.bt.adm_t[b]];
+      adm[2 * nadm + b] = tr.off[B.bt.adm_s[b]];
+      adm[3 * nadm + b] = tr.size[B.bt.adm_s[b]];
+    }
+    hip_check(hipMalloc(&C->d_adm, adm.size() * sizeof(int64_t)), "hipMalloc (plan)");
+    hip_check(hipMemcpy(C->d_adm, adm.data(), adm.size() * sizeof(int64_t), hipMemcpyHostToDevice),
               "upload (plan)");
   }
   B.cache = C;
@@ -1024,17 +1039,10 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   // block weights and column scales
   hip_check(hipEventRecord(e0, st), "event");
   {
-    std::vector<int64_t> to(nadm), tl(nadm), so(nadm), sl(nadm);
-    for (int64_t b = 0; b < nadm; ++b) {
-      to[b] = tr.off[bt.adm_t[b]];
-      tl[b] = tr.size[bt.adm_t[b]];
-      so[b] = tr.off[bt.adm_s[b]];
-      sl[b] = tr.size[bt.adm_s[b]];
-    }
-    int64_t* d_to = upload(mem, to, st);
-    int64_t* d_tl = upload(mem, tl, st);
-    int64_t* d_so = upload(mem, so, st);
-    int64_t* d_sl = upload(mem, sl, st);
+    const int64_t* d_to = M.plan->d_adm;
+    const int64_t* d_tl = d_to + nadm;
+    const int64_t* d_so = d_to + 2 * nadm;
+    const int64_t* d_sl = d_to + 3 * nadm;
     M.d_omega = (double*)mem.alloc(std::max<int64_t>(1, nadm) * sizeof(double));
     launch_block_norm(src, g, d_to, d_tl, d_so, d_sl, nadm, M.d_omega, st);
     launch_check("block norms");
@@ -1052,10 +1060,6 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
       launch_check("entry scales");
     }
     hip_check(hipStreamSynchronize(st), "weights sync");
-    mem.release(d_to);
-    mem.release(d_tl);
-    mem.release(d_so);
-    mem.release(d_sl);
   }
   hip_check(hipEventRecord(e1, st), "event");
   hip_check(hipEventSynchronize(e1), "event");

@@ -90,6 +90,7 @@ struct PlanCache {
   std::shared_ptr<const SidePlan> side[2];
   std::vector<std::vector<ProjPlan>> proj;  // [batch * (depth + 1) + level]
   EntDev* d_ents[2] = {nullptr, nullptr};   // device copies of side[s]->ents
+  int64_t* d_adm = nullptr;                 // admissible blocks: t_off, t_len, s_off, s_len
   ~PlanCache();
 };
 

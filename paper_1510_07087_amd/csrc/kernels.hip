@@ -193,28 +193,31 @@ __global__ __launch_bounds__(256) void k_block_norm(GeomDev g, const int64_t* t_
   __shared__ double red[256];
   int64_t b = blockIdx.x;
   if (b >= nblocks) return;
-  int64_t to = t_off[b], tl = t_len[b], so = s_off[b], sl = s_len[b];
+  const int64_t to = t_off[b], tl = t_len[b], so = s_off[b], sl = s_len[b];
+  // four row groups x 64 column lanes
+  const int ty = threadIdx.x >> 6, tx = threadIdx.x & 63;
   double acc = 0.0;
-  int64_t tot = tl * sl;
-  for (int64_t e = threadIdx.x; e < tot; e += 256) {
-    int64_t i = to + e / sl, j = so + e % sl;
-    double v;
+  for (int64_t i = to + ty; i < to + tl; i += 4) {
     if constexpr (SRC == SRC_HELMHOLTZ) {
       const double* xi = g.pts + 4 * i;
-      const double* xj = g.pts + 4 * j;
-      double dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
-      double a = xj[3] * kInv4Pi;
-      v = a * a / (dx * dx + dy * dy + dz * dz);
+      const double x0 = xi[0], x1 = xi[1], x2 = xi[2];
+      for (int64_t j = so + tx; j < so + sl; j += 64) {
+        const double* xj = g.pts + 4 * j;
+        double dx = x0 - xj[0], dy = x1 - xj[1], dz = x2 - xj[2];
+        double a = xj[3] * kInv4Pi;
+        acc += a * a / (dx * dx + dy * dy + dz * dz);
+      }
     } else {
-      double2 z = dense_entry(g, i, j, 0);
-      v = z.x * z.x + z.y * z.y;
+      for (int64_t j = so + tx; j < so + sl; j += 64) {
+        double2 z = dense_entry(g, i, j, 0);
+        acc += z.x * z.x + z.y * z.y;
+      }
     }
-    acc += v;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) omega[b] = sqrt(red[0]);
