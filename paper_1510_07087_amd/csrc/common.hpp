@@ -34,6 +34,7 @@ struct ItemDev {
   double2* Q;        // factor: r x k row-major (leaf: Q_tc, other: [E_t1c; E_t2c])
   double* sig;       // singular values (r)
   double4* cols;     // leaf: per-column data of F_tc for the current level (x, y, z, factor)
+  float* rmax;       // mixed form: largest |component| of every row of R (k values)
   int32_t m;         // rows of the cluster
   int32_t r;         // rows of the factor (m or k1+k2)
   int32_t k;         // rank (filled by the factorisation)

@@ -707,16 +707,24 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       // coefficient matrices R of this level
       int64_t sumNk = 0;
       for (int32_t i = lo; i < hi; ++i) sumNk += S.items[i].N * S.items[i].k;
-      // R^T in complex FP64, or complex FP32 in the mixed form
+      // R^T in complex FP64, or complex FP32 in the mixed form followed by the
+      // row maxima of every R (k floats per item, for the parents' int8 Gram)
       size_t esz = mixed ? 2 * sizeof(float) : sizeof(double2);
-      char* Rarena = (char*)mem.alloc(sumNk * esz);
+      int64_t sumk = 0;
+      for (int32_t i = lo; i < hi; ++i) sumk += S.items[i].k;
+      size_t rbytes = ((size_t)sumNk * esz + 255) / 256 * 256;
+      size_t mbytes = mixed ? (size_t)sumk * sizeof(float) : 0;
+      char* Rarena = (char*)mem.alloc(rbytes + mbytes);
       {
-        int64_t o = 0;
+        int64_t o = 0, ok = 0;
         for (int32_t i = lo; i < hi; ++i) {
           S.items[i].R = Rarena + o * esz;
+          S.items[i].rmax = mixed ? (float*)(Rarena + rbytes) + ok : nullptr;
           o += S.items[i].N * S.items[i].k;
+          ok += S.items[i].k;
         }
       }
+      if (mbytes) hip_check(hipMemsetAsync(Rarena + rbytes, 0, mbytes, st), "row maxima clear");
       copy_to(S.d_items + lo, S.items.data() + lo, n, st);
       // R-product units: one workgroup per 1024 columns; leaf units first,
       // then non-leaf units grouped by ceil(k / 16)
@@ -745,7 +753,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         nleafr = (int64_t)ru.size();
         for (int kt = 1; kt <= 8; ++kt) {
           if (inner_by_kt[kt].empty()) continue;
-          if (lds_kt[kt] > 160 * 1024)
+          if (lds_kt[kt] > rprod_inner_lds_max())
             fail(DH2_EUNSUPPORTED, "transfer matrix too large for the R-product workgroup");
           rlaunch.push_back({kt, (int64_t)inner_by_kt[kt].size(), (int64_t)lds_kt[kt]});
           ru.insert(ru.end(), inner_by_kt[kt].begin(), inner_by_kt[kt].end());

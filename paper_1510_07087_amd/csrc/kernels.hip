@@ -288,7 +288,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const ItemDev* items, const
 // ---------------------------------------------------------------------------
 constexpr int kEigLds = 9216;  // largest X in double2 elements (144 KiB)
 constexpr int kFacThreads = 256;
-constexpr size_t kRprodLdsMax = 160 * 1024;
+// dynamic LDS of the non-leaf R-product (160 KiB per CU minus its static LDS)
+constexpr size_t kRprodLdsMax = 159 * 1024;
 
 __device__ __forceinline__ double wave_sum(double v, int width) {
   for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -1276,13 +1277,35 @@ struct RAcc<true> {
   }
 };
 
+// Mixed form: largest |component| of the stored R values of tile t (rows
+// kk = 16 t + lane % 16) into the workgroup's LDS maxima.
+template <bool MX>
+__device__ __forceinline__ void rmax_tile(const RAcc<MX>& acc, int64_t j0, int64_t ncols, int kk,
+                                          int k, unsigned* s_rmax) {
+  if constexpr (MX) {
+    int lane = threadIdx.x & 63;
+    float m = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (j0 + acc.row(lane, v) < ncols) m = fmaxf(m, fmaxf(fabsf(acc.re[v]), fabsf(acc.im[v])));
+    if (kk < k && m > 0.0f) atomicMax(s_rmax + kk, __float_as_uint(m));
+  }
+}
+
+// Merge the workgroup's LDS maxima into it.rmax (after a barrier).
+__device__ __forceinline__ void rmax_flush(const ItemDev& it, const unsigned* s_rmax) {
+  for (int kk = threadIdx.x; kk < it.k; kk += blockDim.x)
+    if (s_rmax[kk]) atomicMax(reinterpret_cast<unsigned*>(it.rmax) + kk, s_rmax[kk]);
+}
+
 // R^T of a non-leaf block row, one workgroup per unit (column range): the
 // four waves share Q_hat (in the compute precision) in LDS and take 16-column
 // groups in turn.  R^T[j][kk] = zeta sum_rho [R_t1c'; R_t2c'][rho][j]
 // conj(Q_hat[rho][kk]); the sons' values are loaded two k-steps ahead.
 template <bool MX, int KT>
 __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
-                               const UnitDev& u, double zeta, const ROp<MX>* Qs) {
+                               const UnitDev& u, double zeta, const ROp<MX>* Qs,
+                               unsigned* s_rmax) {
   using OT = ROp<MX>;
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   const int r = it.r, k = it.k, k1 = s1.k, k2 = s2.k;
@@ -1318,6 +1341,17 @@ __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemD
         int64_t jl = j0 + acc[t].row(lane, v);
         if (jl < u.ncols && kk < k) acc[t].store(it.R, (u.col_begin + jl) * k + kk, v, zeta);
       }
+      if constexpr (MX) {
+        // the stored values are the accumulators scaled by zeta in FP32
+        RAcc<MX> sc = acc[t];
+        float z = (float)zeta;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          sc.re[v] *= z;
+          sc.im[v] *= z;
+        }
+        rmax_tile<MX>(sc, j0, u.ncols, kk, k, s_rmax);
+      }
     }
   }
 }
@@ -1327,6 +1361,7 @@ template <bool MX, int KT>
 __global__ __launch_bounds__(256) void k_rprod_inner_g(const ItemDev* items, const UnitDev* units,
                                                        double zeta) {
   extern __shared__ __align__(16) char rlds[];
+  __shared__ unsigned s_rmax[kMaxR];
   using OT = ROp<MX>;
   OT* Qs = reinterpret_cast<OT*>(rlds);
   const UnitDev u = units[blockIdx.x];
@@ -1338,15 +1373,21 @@ __global__ __launch_bounds__(256) void k_rprod_inner_g(const ItemDev* items, con
     int i = e / ldq, kk = e - i * ldq;
     Qs[e] = rop<MX>((i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0));
   }
+  for (int kk = threadIdx.x; kk < kMaxR; kk += 256) s_rmax[kk] = 0u;
   __syncthreads();
-  rprod_inner_wg<MX, KT>(it, items[it.son[0]], items[it.son[1]], u, zeta, Qs);
+  rprod_inner_wg<MX, KT>(it, items[it.son[0]], items[it.son[1]], u, zeta, Qs, s_rmax);
+  if constexpr (MX) {
+    __syncthreads();
+    rmax_flush(it, s_rmax);
+  }
 }
 
 // R^T of a leaf block row: the workgroup's four waves share the item's factor
 // Q (in LDS, compute precision) and take 16-column groups in turn.
 template <int SRC, bool MX, int KT>
 __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
-                                const UnitDev& u, const ROp<MX>* Qs, const RowData* rows) {
+                                const UnitDev& u, const ROp<MX>* Qs, const RowData* rows,
+                                unsigned* s_rmax) {
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   int r = it.r, k = it.k;
   int nks = (r + 3) / 4;
@@ -1376,6 +1417,7 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
         int64_t jl = j0 + acc[t].row(lane, v);
         if (jl < u.ncols && kk < k) acc[t].store(it.R, (u.col_begin + jl) * k + kk, v);
       }
+      rmax_tile<MX>(acc[t], j0, u.ncols, kk, k, s_rmax);
     }
   }
 }
@@ -1386,6 +1428,7 @@ __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* 
                                                       int side) {
   __shared__ ROp<MX> Qs[68 * 64];   // (r + 4) x (16 KT), zero padded rows past r
   __shared__ RowData rows[64 + 8];
+  __shared__ unsigned s_rmax[64];
   const UnitDev u = units[blockIdx.x];
   const ItemDev& it = items[u.item];
   int r = it.r, k = it.k;
@@ -1397,12 +1440,17 @@ __global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* 
     Qs[e] = rop<MX>((i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0));
   }
   for (int i = threadIdx.x; i < 72; i += 256) rows[i] = row_data<SRC>(g, it, i, side);
+  for (int kk = threadIdx.x; kk < 64; kk += 256) s_rmax[kk] = 0u;
   __syncthreads();
   switch (kt) {
-    case 1: rprod_leaf_wave<SRC, MX, 1>(g, it, ents, side, u, Qs, rows); break;
-    case 2: rprod_leaf_wave<SRC, MX, 2>(g, it, ents, side, u, Qs, rows); break;
-    case 3: rprod_leaf_wave<SRC, MX, 3>(g, it, ents, side, u, Qs, rows); break;
-    default: rprod_leaf_wave<SRC, MX, 4>(g, it, ents, side, u, Qs, rows); break;
+    case 1: rprod_leaf_wave<SRC, MX, 1>(g, it, ents, side, u, Qs, rows, s_rmax); break;
+    case 2: rprod_leaf_wave<SRC, MX, 2>(g, it, ents, side, u, Qs, rows, s_rmax); break;
+    case 3: rprod_leaf_wave<SRC, MX, 3>(g, it, ents, side, u, Qs, rows, s_rmax); break;
+    default: rprod_leaf_wave<SRC, MX, 4>(g, it, ents, side, u, Qs, rows, s_rmax); break;
+  }
+  if constexpr (MX) {
+    __syncthreads();
+    rmax_flush(it, s_rmax);
   }
 }
 
@@ -1562,32 +1610,18 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
       if (mx > 0.0f) atomicMax(&rmaxb[rl], __float_as_uint(mx));
     }
   } else {
-    // non-leaf rows: largest |component| of the FP32 values over the unit.
-    // Thread t reads row t % nrow of every (512 / nrow)-th column (coalesced
-    // along the rows of one column)
-    const int nrow = ntile * 16, stride = 512 / nrow;
-    if (tid < stride * nrow) {
-      int rl = tid % nrow;
-      int64_t jphase = tid / nrow;
-      int ld;
-      const float2* src = inner_src(row0(rl >> 4) + (rl & 15), ld);
-      float mx = 0.0f;
-      if (src) {
-        const float2* base = src + (it.col_off + u.col_begin) * ld;
-        int64_t j = jphase;
-        for (; j + 7 * stride < ncols; j += 8 * stride) {
-          float2 v[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) v[q] = base[(j + q * stride) * ld];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
-        }
-        for (; j < ncols; j += stride) {
-          float2 v = base[j * ld];
-          mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
-        }
-      }
-      if (mx > 0.0f) atomicMax(&rmaxb[rl], __float_as_uint(mx));
+    // non-leaf rows: the largest |component| of every row of the sons' R
+    // (recorded by their R-products; a bound over any column range)
+    for (int e = tid; e < ntile * 16; e += 512) {
+      int rho = row0(e >> 4) + (e & 15);
+      const ItemDev& s1 = items[it.son[0]];
+      const ItemDev& s2 = items[it.son[1]];
+      float m = 0.0f;
+      if (rho < s1.k)
+        m = s1.rmax[rho];
+      else if (rho < r)
+        m = s2.rmax[rho - s1.k];
+      rmaxb[e] = __float_as_uint(m);
     }
   }
   __syncthreads();
@@ -1861,6 +1895,8 @@ void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const En
     hipLaunchKernelGGL(k_gram_i8<0>, dim3((unsigned)nunits), dim3(512), kI8Lds, st, g, items,
                        ents, units, side, 1.0, partial);
 }
+
+size_t rprod_inner_lds_max() { return kRprodLdsMax; }
 
 size_t rprod_inner_lds(bool mixed, int r, int k) {
   int kt = (k + 15) / 16;

@@ -30,6 +30,7 @@ void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const En
                     hipStream_t st);
 // LDS bytes of the non-leaf R-product workgroup for an item (r rows, rank k)
 size_t rprod_inner_lds(bool mixed, int r, int k);
+size_t rprod_inner_lds_max();
 // R-products: one workgroup per unit; non-leaf launches hold units of items
 // with ceil(k / 16) = kt only
 void launch_rprod_leaf(int src, bool mixed, const GeomDev& g, const ItemDev* items,
