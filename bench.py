@@ -94,6 +94,59 @@ def cpu_baseline(points, w, kappa, leaf, eps, budget_s):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def run_batch(args, dh2, torch, synth):
+    """Independent instances (sphere, ellipsoid, cube surface) in one call,
+    mixed form, eps 1e-4, leaf 64; also timed one instance after the other."""
+    count = int(args.workload[len("batch"):] or 48)
+    eps = 1e-4
+    inst = synth.batch_instances(count=count, seed=4)
+    forms = [f for f in args.forms.split(",") if f]
+    form = "mixed" if "mixed" in forms else forms[0]
+    o = dh2.opts(leaf_size=64, precision=dh2.MIXED if form == "mixed" else dh2.FP64)
+    t0 = time.perf_counter()
+    blocks = [dh2.blocks_build(dh2.tree_build(i.points, i.kappa, o), o) for i in inst]
+    t_plan = time.perf_counter() - t0
+    ws = [i.weights for i in inst]
+    log(f"[bench] {count} instances, n from {min(len(i.points) for i in inst)} to "
+        f"{max(len(i.points) for i in inst)}, host plans {t_plan:.2f} s")
+    times, seq, flops = [], [], 0.0
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = dh2.compress_batch(blocks, ws, eps, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = [dh2.stats(m) for m in ms]
+        flops = sum(x["flops_row"] + x["flops_col"] + x["flops_prj"] for x in st)
+        log(f"[bench] batch step {it} {'warmup' if it < args.warmup else 'timed'}: {dt:.3f} s")
+        if it >= args.warmup:
+            times.append(dt)
+        del ms
+    # the same instances one after the other (reference for the batching gain)
+    for it in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b, w in zip(blocks, ws):
+            m = dh2.compress_helmholtz(b, w, eps, o)
+            del m
+        torch.cuda.synchronize()
+        if it == 1:
+            seq.append(time.perf_counter() - t0)
+    s_b = float(np.median(times))
+    out = {
+        "metric": METRIC, "value": flops / s_b / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": s_b * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if form == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "instances": count, "eps": eps, "leaf_size": 64,
+                   "form": form, "surfaces": "sphere / rotated ellipsoid / cube surface",
+                   "kappa": "sqrt(n)/5.66"},
+        "batch_s": s_b, "sequential_s": seq[0], "batch_speedup": seq[0] / s_b,
+        "host_plan_s": t_plan,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +182,9 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
         del src, dst
+    if args.workload.startswith("batch"):
+        run_batch(args, dh2, torch, synth)
+        return
     p, w, kappa, leaf, eps = synth.workload(args.workload)
     n = len(p)
     log(f"[bench] workload {args.workload}: n={n} kappa={kappa} leaf={leaf} eps={eps}")

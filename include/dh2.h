@@ -174,9 +174,15 @@ dh2_status dh2_blocks_colsets(dh2_blocks blocks, int32_t side, int32_t* item_t,
  *        G_ij = w_j exp(i kappa r)/(4 pi r) (i != j, r = |x_i - x_j|),
  *        G_ii = sqrt(w_i/pi)/2 + i kappa w_i/(4 pi).
  *   w  : host, n float64 weights (copied); NULL means 4*pi/n for all points.
- * opts->precision selects complex FP64 throughout (DH2_FP64) or complex FP32
- * entry generation and coefficient products with FP64 Gram accumulation,
- * factorisation and truncation (DH2_MIXED).
+ * opts->precision selects complex FP64 throughout (DH2_FP64) or the mixed
+ * form (DH2_MIXED, dh2_compress_helmholtz and dh2_compress_batch only):
+ * entries with an FP64 phase reduction and FP32 polynomials, Gram matrices
+ * of the weighted block rows from exact int8 slices of their rows (int32
+ * accumulation on int8 MFMA, converted to FP64), R^T stored in complex FP32
+ * with FP32 MFMA R-products and projection; factorisation, truncation and
+ * transfer matrices stay FP64.  The slicing keeps about 2^-42 of the squared
+ * row maxima in the Gram matrices, which places the mixed form at eps >=
+ * 1e-5; smaller eps takes DH2_FP64.
  * EINVAL: eps <= 0 or non-finite, zeta <= 0 or 2 zeta^2 >= 1, ld < n,
  *         NaN/Inf in w, G or non-positive weights.
  * ENOMEM: allocation failure or max_device_bytes exceeded.
@@ -188,6 +194,17 @@ dh2_status dh2_compress_dense(dh2_blocks blocks, const void* G, int64_t ld,
 dh2_status dh2_compress_helmholtz(dh2_blocks blocks, const double* w, double eps,
                                   const dh2_opts* opts, void* stream,
                                   dh2_matrix* out);
+/* Independent Helmholtz instances in one call (same options and eps for
+ * all): blocks[i] with weights w[i] (w or w[i] NULL: 4 pi / n_i).  The
+ * instances run concurrently on a few internal streams (default priority),
+ * ordered after the work already on `stream`; all work is complete when the
+ * call returns.  outs[i] receives the matrix of instance i.
+ * Errors: as dh2_compress_helmholtz; on error no handle is returned (the
+ * matrices already built are freed) and outs is untouched.                 */
+dh2_status dh2_compress_batch(int32_t count, const dh2_blocks* blocks,
+                              const double* const* w, double eps,
+                              const dh2_opts* opts, void* stream,
+                              dh2_matrix* outs);
 void dh2_matrix_free(dh2_matrix m);
 
 /* Device memory freed by the library (matrices freed, per-level work arrays)

@@ -59,6 +59,13 @@ static void check_opts(const dh2_opts* o) {
 
 static hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// The mixed form's int8-sliced Gram matrices resolve singular values down to
+// about 1e-6 of the block-row norms; below eps = 1e-5 the FP64 form is used.
+static void check_mixed_eps(const dh2_opts* o, double eps) {
+  if (o->precision == DH2_MIXED && eps < 1e-5)
+    fail(DH2_EUNSUPPORTED, "the mixed form needs eps >= 1e-5; use DH2_FP64 below");
+}
+
 static void need_device() {
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
@@ -249,6 +256,9 @@ dh2_status dh2_compress_dense(dh2_blocks b, const void* G, int64_t ld, double ep
   })
 }
 
+// concurrent streams of dh2_compress_batch (the device's hardware queues per process)
+constexpr int kBatchStreams = 4;
+
 dh2_status dh2_compress_helmholtz(dh2_blocks b, const double* w, double eps, const dh2_opts* opts,
                                   void* stream, dh2_matrix* out) {
   DH2_TRY({
@@ -257,8 +267,33 @@ dh2_status dh2_compress_helmholtz(dh2_blocks b, const double* w, double eps, con
     if (w)
       for (int64_t i = 0; i < n; ++i)
         if (!(w[i] > 0) || !std::isfinite(w[i])) fail(DH2_EINVAL, "weights must be finite and > 0");
+    check_mixed_eps(opts, eps);
     auto m = compress(b->d, SRC_HELMHOLTZ, nullptr, 0, w, eps, *opts, stream_of(stream));
     *out = new dh2_matrix_s{std::move(m)};
+  })
+}
+
+dh2_status dh2_compress_batch(int32_t count, const dh2_blocks* blocks, const double* const* w,
+                              double eps, const dh2_opts* opts, void* stream, dh2_matrix* outs) {
+  DH2_TRY({
+    if (count < 0) fail(DH2_EINVAL, "count must be >= 0");
+    if (count > 0 && (!blocks || !outs)) fail(DH2_EINVAL, "NULL argument");
+    std::vector<std::shared_ptr<BlocksData>> blks(count);
+    std::vector<const double*> ws(count, nullptr);
+    for (int32_t i = 0; i < count; ++i) {
+      check_compress_args(blocks[i], eps, opts, outs + i);
+      if (w && w[i]) {
+        int64_t n = blocks[i]->d->tree->tr.n;
+        for (int64_t j = 0; j < n; ++j)
+          if (!(w[i][j] > 0) || !std::isfinite(w[i][j]))
+            fail(DH2_EINVAL, "weights must be finite and > 0");
+        ws[i] = w[i];
+      }
+      blks[i] = blocks[i]->d;
+    }
+    check_mixed_eps(opts, eps);
+    auto ms = compress_batch(blks, ws, eps, *opts, stream_of(stream), kBatchStreams);
+    for (int32_t i = 0; i < count; ++i) outs[i] = new dh2_matrix_s{std::move(ms[i])};
   })
 }
 

@@ -15,6 +15,8 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -1178,6 +1180,64 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   S.flops_rprod_leaf = ss_row.flops_rprod_leaf + ss_col.flops_rprod_leaf;
   trc.mark("finish", -1, -1, -1);
   return Mp;
+}
+
+// Independent Helmholtz instances: worker threads, each with its own stream
+// (default priority), take instances in turn; concurrent kernels of several
+// instances fill the device where one small instance would not.  All work
+// is ordered after the caller's stream and complete on return.
+std::vector<std::unique_ptr<MatrixData>> compress_batch(
+    const std::vector<std::shared_ptr<BlocksData>>& blks, const std::vector<const double*>& w,
+    double eps, const dh2_opts& o, hipStream_t st, int nstreams) {
+  const int n = (int)blks.size();
+  std::vector<std::unique_ptr<MatrixData>> out(n);
+  if (n == 0) return out;
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  hipEvent_t ready;
+  hip_check(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "event");
+  hip_check(hipEventRecord(ready, st), "event record");
+  std::atomic<int> next{0};
+  std::atomic<bool> failed{false};
+  std::mutex emu;
+  Error first{DH2_OK, ""};
+  auto record = [&](dh2_status c, const std::string& m) {
+    std::lock_guard<std::mutex> lk(emu);
+    if (!failed.exchange(true)) first = Error{c, m};
+  };
+  auto worker = [&]() {
+    hipStream_t s = nullptr;
+    try {
+      hip_check(hipSetDevice(dev), "hipSetDevice");
+      hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream create");
+      hip_check(hipStreamWaitEvent(s, ready, 0), "stream wait");
+      for (;;) {
+        int i = next.fetch_add(1);
+        if (i >= n || failed.load()) break;
+        out[i] = compress(blks[i], SRC_HELMHOLTZ, nullptr, 0, w[i], eps, o, s);
+      }
+    } catch (const Error& e) {
+      record(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+      record(DH2_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+      record(DH2_EDEVICE, e.what());
+    }
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  };
+  int nt = std::max(1, std::min(nstreams, n));
+  std::vector<std::thread> th;
+  for (int q = 0; q < nt; ++q) th.emplace_back(worker);
+  for (auto& t : th) t.join();
+  (void)hipEventDestroy(ready);
+  if (failed.load()) {
+    out.clear();
+    fail(first.code, first.msg);
+  }
+  return out;
 }
 
 // ---------------------------------------------------------------------------

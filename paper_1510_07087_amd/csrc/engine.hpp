@@ -139,6 +139,9 @@ std::shared_ptr<BlocksData> make_blocks(std::shared_ptr<TreeData> t, const dh2_o
 std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> b, int src, const void* G,
                                      int64_t ld, const double* w, double eps, const dh2_opts& o,
                                      hipStream_t st);
+std::vector<std::unique_ptr<MatrixData>> compress_batch(
+    const std::vector<std::shared_ptr<BlocksData>>& blks, const std::vector<const double*>& w,
+    double eps, const dh2_opts& o, hipStream_t st, int nstreams);
 void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st);
 double error_estimate(MatrixData& M, const void* G, int64_t ld, int iters, uint64_t seed,
                       hipStream_t st);

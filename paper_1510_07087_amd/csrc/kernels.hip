@@ -11,6 +11,7 @@
 // row (Section 6: the basis is formed by the first k left singular vectors).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include <cmath>
@@ -1853,12 +1854,11 @@ void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
 void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rmax, double eps,
                    int max_sweeps, int32_t* status, hipStream_t st) {
   if (nl == 0) return;
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::once_flag attr;
+  std::call_once(attr, [] {
     hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(kEigLds * sizeof(double2)));
-    attr_set = true;
-  }
+  });
   // X needs r columns plus one for the even pairing
   int cap = std::min(kEigLds, std::max(2, rmax * (rmax + 1)));
   hipLaunchKernelGGL(k_factor, dim3(nl), dim3(kFacThreads), (size_t)cap * sizeof(double2), st,
@@ -1880,14 +1880,13 @@ void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const En
                     const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
                     hipStream_t st) {
   if (nunits == 0) return;
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::once_flag attr;
+  std::call_once(attr, [] {
     hipFuncSetAttribute((const void*)k_gram_i8<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)kI8Lds);
     hipFuncSetAttribute((const void*)k_gram_i8<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)kI8Lds);
-    attr_set = true;
-  }
+  });
   if (inner)
     hipLaunchKernelGGL(k_gram_i8<1>, dim3((unsigned)nunits), dim3(512), kI8Lds, st, g, items,
                        ents, units, side, zeta * zeta, partial);
@@ -1906,12 +1905,11 @@ size_t rprod_inner_lds(bool mixed, int r, int k) {
 template <bool MX, int KT>
 static void launch_rpi(const ItemDev* items, const UnitDev* units, int64_t nunits, double zeta,
                        size_t lds, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::once_flag attr;
+  std::call_once(attr, [] {
     hipFuncSetAttribute((const void*)k_rprod_inner_g<MX, KT>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRprodLdsMax);
-    attr_set = true;
-  }
+  });
   hipLaunchKernelGGL((k_rprod_inner_g<MX, KT>), dim3((unsigned)nunits), dim3(256), lds, st, items,
                      units, zeta);
 }

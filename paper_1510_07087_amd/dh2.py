@@ -63,7 +63,8 @@ EXPORTED = [
     "dh2_opts_default", "dh2_last_error", "dh2_tree_build", "dh2_tree_free",
     "dh2_tree_get_info", "dh2_tree_export", "dh2_tree_directions", "dh2_blocks_build",
     "dh2_blocks_free", "dh2_blocks_get_info", "dh2_blocks_export", "dh2_blocks_colsets",
-    "dh2_compress_dense", "dh2_compress_helmholtz", "dh2_matrix_free", "dh2_matvec",
+    "dh2_compress_dense", "dh2_compress_helmholtz", "dh2_compress_batch", "dh2_matrix_free",
+    "dh2_matvec",
     "dh2_error_estimate", "dh2_rows_check", "dh2_get_stats", "dh2_basis_export",
     "dh2_coupling_export", "dh2_near_export", "dh2_release_cached_memory",
 ]
@@ -97,6 +98,7 @@ def lib():
         "dh2_blocks_colsets": (I32, [VP, I32, P(I32), P(I32), P(I64), P(I32), P(I32), P(I32)]),
         "dh2_compress_dense": (I32, [VP, VP, I64, D, P(Opts), VP, P(VP)]),
         "dh2_compress_helmholtz": (I32, [VP, P(D), D, P(Opts), VP, P(VP)]),
+        "dh2_compress_batch": (I32, [I32, P(VP), P(P(D)), D, P(Opts), VP, P(VP)]),
         "dh2_matrix_free": (None, [VP]),
         "dh2_matvec": (I32, [VP, C.c_char, I64, VP, VP, VP]),
         "dh2_error_estimate": (I32, [VP, VP, I64, I32, C.c_uint64, P(D), VP]),
@@ -254,6 +256,20 @@ def compress_helmholtz(b: Blocks, w, eps: float, o: Opts, stream=None) -> Matrix
     _check(lib().dh2_compress_helmholtz(b.h, _p(wa, C.c_double), float(eps), C.byref(o),
                                         _stream(stream), C.byref(h)))
     return Matrix(h, keep=b)
+
+
+def compress_batch(blocks, ws, eps: float, o: Opts, stream=None):
+    """Independent Helmholtz instances in one call: blocks[i] with weights
+    ws[i] (None: 4 pi / n_i).  Returns the list of matrices."""
+    count = len(blocks)
+    hb = (C.c_void_p * max(1, count))(*[b.h for b in blocks])
+    arrs = [None if w is None else np.ascontiguousarray(w, dtype=np.float64) for w in ws]
+    wp = (C.POINTER(C.c_double) * max(1, count))(
+        *[C.POINTER(C.c_double)() if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+          for a in arrs])
+    outs = (C.c_void_p * max(1, count))()
+    _check(lib().dh2_compress_batch(count, hb, wp, float(eps), C.byref(o), _stream(stream), outs))
+    return [Matrix(C.c_void_p(outs[i]), keep=blocks[i]) for i in range(count)]
 
 
 def compress_dense(b: Blocks, G, eps: float, o: Opts, stream=None) -> Matrix:
