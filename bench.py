@@ -24,8 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "compression s & GFLOP/s, mixed vs FP64 form at equal eps, n=131072 kappa=64"
-PEAK_FP64_MFMA = 78.6e12  # MI355X dense FP64 matrix peak (FLOP/s)
+PEAK_FP64_MFMA = 78.6e12   # MI355X dense matrix peaks (published)
 PEAK_FP32_MFMA = 157.3e12
+PEAK_INT8_MFMA = 5.0e15
 
 
 def log(*a):
@@ -153,7 +154,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere131072")
-    ap.add_argument("--forms", default="fp64")
+    ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--groups", type=int, default=0)
     ap.add_argument("--err-iters", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -219,9 +220,17 @@ def main():
     head = "mixed" if "mixed" in res else forms[0]
     r = res[head]
     st = r["stats"]
-    peak = PEAK_FP64_MFMA
-    # dominant single kernel: the leaf Gram (algorithmic flops 4 r^2 N per block row)
-    achieved = st["flops_gram_leaf"] / st["t_gram_leaf"] if st["t_gram_leaf"] > 0 else 0.0
+    nl = max(1, st["n_gram_leaf"])
+    if head == "mixed":
+        # dominant kernel: the int8-sliced leaf Gram (k_gram_i8<0>)
+        kern = "k_gram_i8<0> (leaf Gram matrices, exact int8 slices on int8 MFMA)"
+        work, peak, unit = st["ops_gram_leaf_i8"], PEAK_INT8_MFMA, "TOP/s"
+    else:
+        kern = "k_gram_leaf_w (leaf Gram matrices on FP64 MFMA)"
+        work, peak, unit = st["flops_gram_leaf"], PEAK_FP64_MFMA, "TFLOP/s"
+    achieved = work / st["t_gram_leaf"] if st["t_gram_leaf"] > 0 else 0.0
+    pk_prj = PEAK_FP32_MFMA if head == "mixed" else PEAK_FP64_MFMA
+    ach_prj = st["flops_prj"] / st["t_prj"] if st["t_prj"] > 0 else 0.0
     out = {
         "metric": METRIC,
         "value": r["gflops"],
@@ -233,18 +242,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "dtype": "f64" if head == "fp64" else "i8+f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "kappa": kappa, "leaf_size": leaf,
                    "eps": eps, "eta1": 20.0, "eta2": 5.0, "zeta": 2.0 / 3.0, "form": head,
                    "entries": "generated on the fly"},
-        "roofline": {"bound": "mfma",
-                     "kernel": "k_gram_leaf_w (FP64 MFMA Gram of leaf block rows)",
-                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma", "kernel": kern,
+                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
                      "frac": achieved / peak, "traffic": args.traffic,
                      "launches": st["n_gram_leaf"],
-                     "avg_launch_ms": st["t_gram_leaf"] / max(1, st["n_gram_leaf"]) * 1e3,
-                     "flops_per_launch": st["flops_gram_leaf"] / max(1, st["n_gram_leaf"])},
+                     "avg_launch_ms": st["t_gram_leaf"] / nl * 1e3,
+                     "work_per_launch": work / nl},
+        "roofline_projection": {"bound": "mfma",
+                                "kernel": "k_project_tiled (S_b = omega_b R|s W, "
+                                          + ("FP32" if head == "mixed" else "FP64") + " MFMA)",
+                                "achieved": ach_prj / 1e12, "peak": pk_prj / 1e12,
+                                "unit": "TFLOP/s", "frac": ach_prj / pk_prj},
         "compression_s": {f: res[f]["s"] for f in res},
         "gflops": {f: res[f]["gflops"] for f in res},
         "rel_err_2": {f: res[f]["rel_err"] for f in res},

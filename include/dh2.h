@@ -264,6 +264,8 @@ typedef struct {
   int32_t n_gram_leaf;
   int32_t pad;
   double flops_rprod_leaf;   /* R-product flops of leaf block rows */
+  double ops_gram_leaf_i8;   /* mixed form: int8 MFMA operations of the leaf Gram
+                                matrices, 60 r (r + 1) N per leaf block row      */
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_matrix m, dh2_stats* out);

@@ -70,11 +70,18 @@ struct UnitDev {
 // Projection task: S_b = omega_b * (R_tc restricted to the columns of s) * Wexp_sc.
 struct ProjDev {
   const void* R;      // R^T rows of the block (|s| x kt), complex FP64 or FP32
-  const double2* W;   // expanded column basis (|s| x ks row-major)
+  const void* W;      // expanded column basis (|s| x ks row-major), complex FP64 or FP32
   double2* S;         // output (kt x ks column-major)
   int32_t kt, ks;
   int32_t ns;         // |s|
   int32_t b;
+};
+
+// Conversion task of the mixed form: count complex values FP64 -> FP32.
+struct CvtDev {
+  const double2* src;
+  float2* dst;
+  int64_t count;
 };
 
 // Expansion task: rows of one son inside Wexp_sc = Wexp_{s_i c'} E_{s_i c}.

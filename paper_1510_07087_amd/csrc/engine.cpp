@@ -508,7 +508,7 @@ struct PhaseTimer {
 struct SweepStats {
   double flops_gram = 0, flops_rprod = 0, flops_prj = 0;
   double t_gram = 0, t_prj = 0;
-  double flops_gram_leaf = 0, t_gram_leaf = 0, flops_rprod_leaf = 0;
+  double flops_gram_leaf = 0, t_gram_leaf = 0, flops_rprod_leaf = 0, ops_gram_leaf_i8 = 0;
   int32_t n_gram_leaf = 0;
 };
 
@@ -640,6 +640,8 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
             double fl = 4.0 * rr * rr * (double)std::min(width, it.N - c0);
             ss.flops_gram += fl;
             if (it.leaf) ss.flops_gram_leaf += fl;
+            // int8 slicing: 4 real products x 15 slice pairs x 2 ops on the lower triangle
+            if (it.leaf && mixed) ss.ops_gram_leaf_i8 += 60.0 * rr * (rr + 1.0) * (double)std::min(width, it.N - c0);
           }
         }
         if (pass == 0) nleafu = (int64_t)units.size();
@@ -788,8 +790,10 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           sumS += (int64_t)S.items[q.item].k * M.side[1].items[q.witem].k;
         double2* Sarena = (double2*)mem.alloc(std::max<int64_t>(1, sumS) * sizeof(double2));
         S.keep.push_back(Sarena);
+        // launch class: (row tiles per pass, column tiles, split) or the generic kernel
+        constexpr int kGeneric = 32;
         std::vector<uint8_t> key(pl.size(), 255);
-        int64_t count[17] = {0};
+        int64_t count[kGeneric + 1] = {0};
         std::vector<ProjDev> tasks(pl.size());
         int64_t o = 0;
         for (size_t x = 0; x < pl.size(); ++x) {
@@ -798,7 +802,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           int32_t ks = M.side[1].items[q.witem].k;
           ProjDev& pd = tasks[x];
           pd.R = (const char*)it.R + q.col * it.k * esz;
-          pd.W = M.side[1].wexp[q.witem];
+          pd.W = mixed ? (const void*)M.side[1].wexp32[q.witem] : (const void*)M.side[1].wexp[q.witem];
           pd.S = Sarena + o;
           pd.kt = it.k;
           pd.ks = ks;
@@ -811,22 +815,26 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           ss.flops_prj += 8.0 * it.k * (double)ks * (double)q.ns;
           if (it.k == 0 || ks == 0) continue;
           int nj = (ks + 15) / 16, ni = (it.k + 15) / 16;
-          int kx = 16;  // generic kernel
-          if (nj <= 4) kx = (std::min(ni, project_rows_per_pass(mixed, nj)) - 1) * 4 + (nj - 1);
+          int kx = kGeneric;
+          if (nj <= 4)
+            kx = (q.ns >= 128 ? 16 : 0) +
+                 (std::min(ni, project_rows_per_pass(mixed, nj)) - 1) * 4 + (nj - 1);
           key[x] = (uint8_t)kx;
           ++count[kx];
         }
         // stable counting sort by launch class
         std::vector<ProjDev> sorted;
-        std::vector<std::array<int64_t, 3>> launches;  // ni, nj, count
+        std::vector<std::array<int64_t, 4>> launches;  // ni, nj, split, count
         {
-          int64_t start[17], run = 0;
-          for (int kx = 0; kx < 17; ++kx) {
+          int64_t start[kGeneric + 1], run = 0;
+          for (int kx = 0; kx <= kGeneric; ++kx) {
             start[kx] = run;
             run += count[kx];
             if (count[kx] == 0) continue;
-            if (kx < 16) launches.push_back({kx / 4 + 1, kx % 4 + 1, count[kx]});
-            else launches.push_back({0, 0, count[kx]});
+            if (kx < kGeneric)
+              launches.push_back({(kx % 16) / 4 + 1, kx % 4 + 1, kx / 16, count[kx]});
+            else
+              launches.push_back({0, 0, 0, count[kx]});
           }
           sorted.resize(run);
           for (size_t x = 0; x < pl.size(); ++x)
@@ -838,11 +846,12 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         int64_t off = 0;
         for (const auto& L : launches) {
           if (L[0] > 0)
-            launch_project_tiled(mixed, (int)L[0], (int)L[1], d_tasks + off, L[2], M.d_omega, st);
+            launch_project_tiled(mixed, (int)L[0], (int)L[1], L[2] != 0, d_tasks + off, L[3],
+                                 M.d_omega, st);
           else
-            launch_project(mixed, d_tasks + off, L[2], M.d_omega, st);
+            launch_project(mixed, d_tasks + off, L[3], M.d_omega, st);
           launch_check("project");
-          off += L[2];
+          off += L[3];
         }
         tp.stop();
         tr_.mark("project", s, b, lv);
@@ -915,6 +924,27 @@ static void expand_side(MatrixData& M, int s, hipStream_t st) {
     launch_expand(d_tasks, (int64_t)tasks.size(), st);
     launch_check("expand");
     hip_check(hipStreamSynchronize(st), "expand sync");
+    mem.release(d_tasks);
+  }
+  if (M.precision == DH2_MIXED) {
+    // complex FP32 copies of the expanded bases for the FP32 projection
+    int64_t total = 0;
+    for (int32_t i = 0; i < S.nitems; ++i) total += (int64_t)S.items[i].m * S.items[i].k;
+    float2* arena = (float2*)mem.alloc(std::max<int64_t>(1, total) * sizeof(float2));
+    S.keep.push_back(arena);
+    S.wexp32.assign(S.nitems, nullptr);
+    std::vector<CvtDev> tasks;
+    int64_t o = 0;
+    for (int32_t i = 0; i < S.nitems; ++i) {
+      int64_t cnt = (int64_t)S.items[i].m * S.items[i].k;
+      S.wexp32[i] = arena + o;
+      if (cnt > 0) tasks.push_back(CvtDev{S.wexp[i], arena + o, cnt});
+      o += cnt;
+    }
+    CvtDev* d_tasks = upload(mem, tasks, st);
+    launch_cvt(d_tasks, (int64_t)tasks.size(), st);
+    launch_check("basis conversion");
+    hip_check(hipStreamSynchronize(st), "conversion sync");
     mem.release(d_tasks);
   }
 }
@@ -1178,6 +1208,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   S.t_gram_leaf = ss_row.t_gram_leaf + ss_col.t_gram_leaf;
   S.n_gram_leaf = ss_row.n_gram_leaf + ss_col.n_gram_leaf;
   S.flops_rprod_leaf = ss_row.flops_rprod_leaf + ss_col.flops_rprod_leaf;
+  S.ops_gram_leaf_i8 = ss_row.ops_gram_leaf_i8 + ss_col.ops_gram_leaf_i8;
   trc.mark("finish", -1, -1, -1);
   return Mp;
 }

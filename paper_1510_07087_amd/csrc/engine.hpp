@@ -104,6 +104,7 @@ struct Side {
   std::vector<void*> keep;          // Q and sigma arenas
   // expanded basis (column side): per internal item pointer, rows x k row-major
   std::vector<double2*> wexp;
+  std::vector<float2*> wexp32;      // mixed form: FP32 copies for the projection
 };
 
 struct MatvecPlan;

@@ -537,6 +537,13 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandDev* tasks) {
   }
 }
 
+// mixed form: complex FP64 -> FP32 copies, one workgroup per task
+__global__ __launch_bounds__(256) void k_cvt(const CvtDev* tasks) {
+  const CvtDev t = tasks[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < t.count; e += 256)
+    t.dst[e] = make_float2((float)t.src[e].x, (float)t.src[e].y);
+}
+
 // copy a leaf basis (row-major rows x k) into the expanded-basis arena
 __global__ void k_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
                          int64_t count) {
@@ -587,7 +594,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
   if (kt == 0 || ks == 0) return;
   double om = omega[t.b];
   int nti = (kt + 15) / 16, ntj = (ks + 15) / 16;
-  const double2* Wb = t.W;
+  const void* Wb = t.W;
   double2* Sb = t.S;
   for (int ti16 = 0; ti16 < nti; ++ti16) {
     SAcc<MX> acc[8];
@@ -599,7 +606,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
       for (int q = 0; q < 8; ++q) {
         if (q < ntj) {
           int jj = q * 16 + row;
-          double2 b = (j < t.ns && jj < ks) ? Wb[(int64_t)j * ks + jj] : make_double2(0.0, 0.0);
+          double2 b = (j < t.ns && jj < ks) ? rload<MX>(Wb, (int64_t)j * ks + jj) : make_double2(0.0, 0.0);
           acc[q].mac(a, b);
         }
       }
@@ -670,38 +677,53 @@ struct PAcc<true> {
   __device__ __forceinline__ double2 get(int v) const { return make_double2(re[v], im[v]); }
 };
 
+// Accumulates the NI x NJ tile pairs of row tiles ti0.. over columns
+// [jb, je) of s (jb, je multiples of 4 or je = ns).
 template <bool MX, int NI, int NJ>
-__device__ void proj_wave(const ProjDev& t, int ti0, double om) {
+__device__ void proj_acc(const ProjDev& t, int ti0, int jb, int je, PAcc<MX> (&acc)[NI][NJ]) {
   int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
-  const int kt = t.kt, ks = t.ks, ns = t.ns;
-  PAcc<MX> acc[NI][NJ];
-  POp<MX> a[NI], b[NJ];
+  const int kt = t.kt, ks = t.ks;
   auto load = [&](int j, POp<MX>* aa, POp<MX>* bb) {
 #pragma unroll
     for (int I = 0; I < NI; ++I) {
       int ii = 16 * (ti0 + I) + row;
-      aa[I] = pop_make<MX>((j < ns && ii < kt) ? rload<MX>(t.R, (int64_t)j * kt + ii)
+      aa[I] = pop_make<MX>((j < je && ii < kt) ? rload<MX>(t.R, (int64_t)j * kt + ii)
                                                 : make_double2(0.0, 0.0));
     }
 #pragma unroll
     for (int J = 0; J < NJ; ++J) {
       int jj = 16 * J + row;
-      bb[J] = pop_make<MX>((j < ns && jj < ks) ? t.W[(int64_t)j * ks + jj] : make_double2(0.0, 0.0));
+      bb[J] = pop_make<MX>((j < je && jj < ks) ? rload<MX>(t.W, (int64_t)j * ks + jj)
+                                                : make_double2(0.0, 0.0));
     }
   };
-  load(kq, a, b);
-  for (int j0 = 0; j0 < ns; j0 += 4) {
-    POp<MX> an[NI], bn[NJ];
-    load(j0 + 4 + kq, an, bn);
+  // operands two k-steps ahead
+  POp<MX> a0[NI], b0[NJ], a1[NI], b1[NJ];
+  load(jb + kq, a0, b0);
+  load(jb + 4 + kq, a1, b1);
+  for (int j0 = jb; j0 < je; j0 += 4) {
+    POp<MX> a2[NI], b2[NJ];
+    load(j0 + 8 + kq, a2, b2);
 #pragma unroll
     for (int I = 0; I < NI; ++I)
 #pragma unroll
-      for (int J = 0; J < NJ; ++J) acc[I][J].mac(a[I], b[J]);
+      for (int J = 0; J < NJ; ++J) acc[I][J].mac(a0[I], b0[J]);
 #pragma unroll
-    for (int I = 0; I < NI; ++I) a[I] = an[I];
+    for (int I = 0; I < NI; ++I) {
+      a0[I] = a1[I];
+      a1[I] = a2[I];
+    }
 #pragma unroll
-    for (int J = 0; J < NJ; ++J) b[J] = bn[J];
+    for (int J = 0; J < NJ; ++J) {
+      b0[J] = b1[J];
+      b1[J] = b2[J];
+    }
   }
+}
+
+template <bool MX, int NI, int NJ>
+__device__ void proj_store(const ProjDev& t, int ti0, double om, PAcc<MX> (&acc)[NI][NJ]) {
+  int lane = threadIdx.x & 63, row = lane & 15;
   double2* Sb = t.S;
 #pragma unroll
   for (int I = 0; I < NI; ++I)
@@ -712,28 +734,72 @@ __device__ void proj_wave(const ProjDev& t, int ti0, double om) {
       for (int v = 0; v < 4; ++v) {
         int i = 16 * (ti0 + I) + acc[I][J].row(lane, v);
         double2 z = acc[I][J].get(v);
-        if (i < kt && jj < ks) Sb[i + (int64_t)jj * kt] = make_double2(om * z.x, om * z.y);
+        if (i < t.kt && jj < t.ks) Sb[i + (int64_t)jj * t.kt] = make_double2(om * z.x, om * z.y);
       }
     }
 }
 
 // Tasks of one launch share (NI, NJ): NJ = column tiles, NI = row tiles per
 // pass (the register budget allows at most 16 mixed or 8 FP64 tile pairs).
-template <bool MX, int NI, int NJ>
+// SPLIT = 1: one wave per task.  SPLIT = 4 (long column ranges): the four
+// waves of a workgroup take a quarter of the columns each and the partial
+// sums are added in a fixed order through LDS.
+template <bool MX, int NI, int NJ, int SPLIT>
 __global__ __launch_bounds__(256) void k_project_tiled(const ProjDev* tasks, int64_t ntasks,
                                                        const double* omega) {
+  using AT = typename std::conditional<MX, float, double>::type;
+  constexpr int NE = NI * NJ * 4 * 64;  // accumulator elements of one wave
+  __shared__ AT red_re[SPLIT > 1 ? 4 * NE : 1], red_im[SPLIT > 1 ? 4 * NE : 1];
   // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
   // contiguous range of workgroup slots
   unsigned nb = gridDim.x, b = blockIdx.x;
   unsigned x = b & 7u, loc = b >> 3, q = nb >> 3, rmd = nb & 7u;
   unsigned slot = x * q + (x < rmd ? x : rmd) + loc;
-  int64_t ti = (int64_t)slot * 4 + (threadIdx.x >> 6);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t ti = SPLIT > 1 ? (int64_t)slot : (int64_t)slot * 4 + w;
   if (ti >= ntasks) return;
   const ProjDev t = tasks[ti];
   if (t.kt == 0 || t.ks == 0) return;
   double om = omega[t.b];
   int nti = (t.kt + 15) / 16;
-  for (int ti0 = 0; ti0 < nti; ti0 += NI) proj_wave<MX, NI, NJ>(t, ti0, om);
+  for (int ti0 = 0; ti0 < nti; ti0 += NI) {
+    PAcc<MX> acc[NI][NJ];
+    if constexpr (SPLIT == 1) {
+      proj_acc<MX, NI, NJ>(t, ti0, 0, t.ns, acc);
+      proj_store<MX, NI, NJ>(t, ti0, om, acc);
+    } else {
+      int part = ((t.ns + 4 * SPLIT - 1) / (4 * SPLIT)) * 4;
+      int jb = w * part, je = min(t.ns, jb + part);
+      if (jb < je) proj_acc<MX, NI, NJ>(t, ti0, jb, je, acc);
+#pragma unroll
+      for (int I = 0; I < NI; ++I)
+#pragma unroll
+        for (int J = 0; J < NJ; ++J)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            int e = ((I * NJ + J) * 4 + v) * 64 + lane;
+            red_re[w * NE + e] = acc[I][J].re[v];
+            red_im[w * NE + e] = acc[I][J].im[v];
+          }
+      __syncthreads();
+      // the four partial sums in a fixed order, stored by all threads
+      for (int e = threadIdx.x; e < NE; e += 256) {
+        AT re = red_re[e], im = red_im[e];
+#pragma unroll
+        for (int src = 1; src < 4; ++src) {
+          re += red_re[src * NE + e];
+          im += red_im[src * NE + e];
+        }
+        int pr = e >> 8, v = (e >> 6) & 3, l = e & 63;
+        int I = pr / NJ, J = pr - I * NJ;
+        int i = 16 * (ti0 + I) + (MX ? f32_row(l, v) : f64_row(l, v));
+        int jj = 16 * J + (l & 15);
+        if (i < t.kt && jj < t.ks)
+          t.S[i + (int64_t)jj * t.kt] = make_double2(om * (double)re, om * (double)im);
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1479,7 +1545,6 @@ __device__ __forceinline__ ivec4 mfma_i8(ivec4 a, ivec4 b, ivec4 c) {
 constexpr int kI8Tiles = 6;                           // complex row tiles per unit
 constexpr int kI8Slab = 1024;                         // one slice of one tile: 16 rows x 64 B
 constexpr int kI8Buf = kI8Tiles * 2 * 4 * kI8Slab;    // tiles x components x slices
-constexpr int kI8Prod = 40;                           // real tile products per unit
 constexpr size_t kI8Lds = 2 * (size_t)kI8Buf + 3 * 64 * sizeof(double4) +
                           kI8Tiles * 16 * (sizeof(RowData) + 2 * sizeof(int));
 
@@ -1856,7 +1921,7 @@ void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rm
   if (nl == 0) return;
   static std::once_flag attr;
   std::call_once(attr, [] {
-    hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(kEigLds * sizeof(double2)));
   });
   // X needs r columns plus one for the even pairing
@@ -1882,9 +1947,9 @@ void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const En
   if (nunits == 0) return;
   static std::once_flag attr;
   std::call_once(attr, [] {
-    hipFuncSetAttribute((const void*)k_gram_i8<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_gram_i8<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)kI8Lds);
-    hipFuncSetAttribute((const void*)k_gram_i8<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_gram_i8<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)kI8Lds);
   });
   if (inner)
@@ -1907,7 +1972,7 @@ static void launch_rpi(const ItemDev* items, const UnitDev* units, int64_t nunit
                        size_t lds, hipStream_t st) {
   static std::once_flag attr;
   std::call_once(attr, [] {
-    hipFuncSetAttribute((const void*)k_rprod_inner_g<MX, KT>,
+    (void)hipFuncSetAttribute((const void*)k_rprod_inner_g<MX, KT>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRprodLdsMax);
   });
   hipLaunchKernelGGL((k_rprod_inner_g<MX, KT>), dim3((unsigned)nunits), dim3(256), lds, st, items,
@@ -1961,6 +2026,11 @@ void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st) {
   hipLaunchKernelGGL(k_expand, dim3((unsigned)ntasks), dim3(256), 0, st, tasks);
 }
 
+void launch_cvt(const CvtDev* tasks, int64_t ntasks, hipStream_t st) {
+  if (ntasks == 0) return;
+  hipLaunchKernelGGL(k_cvt, dim3((unsigned)ntasks), dim3(256), 0, st, tasks);
+}
+
 void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
                    int64_t count, hipStream_t st) {
   if (count == 0) return;
@@ -1981,38 +2051,46 @@ void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const doub
 
 int project_rows_per_pass(bool mixed, int ntj) { return (mixed || ntj <= 2) ? 4 : 2; }
 
-template <bool MX, int NJ>
+template <bool MX, int NJ, int SPLIT>
 static void launch_pt(int ni, const ProjDev* tasks, int64_t ntasks, const double* omega,
                       hipStream_t st) {
-  dim3 grid(blocks_for(ntasks, 4)), blk(256);
+  // row tiles per pass allowed by the register budget (project_rows_per_pass)
+  constexpr int MAXI = (MX || NJ <= 2) ? 4 : 2;
+  dim3 grid(SPLIT > 1 ? (unsigned)ntasks : blocks_for(ntasks, 4)), blk(256);
   switch (ni) {
-    case 1: hipLaunchKernelGGL((k_project_tiled<MX, 1, NJ>), grid, blk, 0, st, tasks, ntasks, omega); break;
-    case 2: hipLaunchKernelGGL((k_project_tiled<MX, 2, NJ>), grid, blk, 0, st, tasks, ntasks, omega); break;
-    case 3: hipLaunchKernelGGL((k_project_tiled<MX, 3, NJ>), grid, blk, 0, st, tasks, ntasks, omega); break;
+    case 1: hipLaunchKernelGGL((k_project_tiled<MX, 1, NJ, SPLIT>), grid, blk, 0, st, tasks, ntasks, omega); break;
+    case 2: hipLaunchKernelGGL((k_project_tiled<MX, 2, NJ, SPLIT>), grid, blk, 0, st, tasks, ntasks, omega); break;
+    case 3:
+      if constexpr (MAXI >= 3)
+        hipLaunchKernelGGL((k_project_tiled<MX, 3, NJ, SPLIT>), grid, blk, 0, st, tasks, ntasks, omega);
+      break;
     default:
-      if constexpr (MX || NJ <= 2)
-        hipLaunchKernelGGL((k_project_tiled<MX, 4, NJ>), grid, blk, 0, st, tasks, ntasks, omega);
+      if constexpr (MAXI >= 4)
+        hipLaunchKernelGGL((k_project_tiled<MX, 4, NJ, SPLIT>), grid, blk, 0, st, tasks, ntasks, omega);
       break;
   }
 }
 
-void launch_project_tiled(bool mixed, int ni, int nj, const ProjDev* tasks, int64_t ntasks,
-                          const double* omega, hipStream_t st) {
+template <bool MX, int SPLIT>
+static void launch_pt_nj(int ni, int nj, const ProjDev* tasks, int64_t ntasks,
+                         const double* omega, hipStream_t st) {
+  switch (nj) {
+    case 1: launch_pt<MX, 1, SPLIT>(ni, tasks, ntasks, omega, st); break;
+    case 2: launch_pt<MX, 2, SPLIT>(ni, tasks, ntasks, omega, st); break;
+    case 3: launch_pt<MX, 3, SPLIT>(ni, tasks, ntasks, omega, st); break;
+    default: launch_pt<MX, 4, SPLIT>(ni, tasks, ntasks, omega, st); break;
+  }
+}
+
+void launch_project_tiled(bool mixed, int ni, int nj, bool split, const ProjDev* tasks,
+                          int64_t ntasks, const double* omega, hipStream_t st) {
   if (ntasks == 0) return;
   if (mixed) {
-    switch (nj) {
-      case 1: launch_pt<true, 1>(ni, tasks, ntasks, omega, st); break;
-      case 2: launch_pt<true, 2>(ni, tasks, ntasks, omega, st); break;
-      case 3: launch_pt<true, 3>(ni, tasks, ntasks, omega, st); break;
-      default: launch_pt<true, 4>(ni, tasks, ntasks, omega, st); break;
-    }
+    if (split) launch_pt_nj<true, 4>(ni, nj, tasks, ntasks, omega, st);
+    else launch_pt_nj<true, 1>(ni, nj, tasks, ntasks, omega, st);
   } else {
-    switch (nj) {
-      case 1: launch_pt<false, 1>(ni, tasks, ntasks, omega, st); break;
-      case 2: launch_pt<false, 2>(ni, tasks, ntasks, omega, st); break;
-      case 3: launch_pt<false, 3>(ni, tasks, ntasks, omega, st); break;
-      default: launch_pt<false, 4>(ni, tasks, ntasks, omega, st); break;
-    }
+    if (split) launch_pt_nj<false, 4>(ni, nj, tasks, ntasks, omega, st);
+    else launch_pt_nj<false, 1>(ni, nj, tasks, ntasks, omega, st);
   }
 }
 

@@ -39,6 +39,7 @@ void launch_rprod_leaf(int src, bool mixed, const GeomDev& g, const ItemDev* ite
 void launch_rprod_inner(bool mixed, int kt, const ItemDev* items, const UnitDev* units,
                         int64_t nunits, double zeta, size_t lds, hipStream_t st);
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st);
+void launch_cvt(const CvtDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
                    int64_t count, hipStream_t st);
 void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const double* omega,
@@ -46,8 +47,9 @@ void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const doub
 // blocks with ks <= 64: every task of one launch has ceil(ks/16) = nj and is
 // processed in passes of ni = min(ceil(kt/16), project_rows_per_pass) row tiles
 int project_rows_per_pass(bool mixed, int nj);
-void launch_project_tiled(bool mixed, int ni, int nj, const ProjDev* tasks, int64_t ntasks,
-                          const double* omega, hipStream_t st);
+// split: one workgroup per task with the columns of s divided among its waves
+void launch_project_tiled(bool mixed, int ni, int nj, bool split, const ProjDev* tasks,
+                          int64_t ntasks, const double* omega, hipStream_t st);
 void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
                  const int64_t* s_off, const int64_t* s_len, const int64_t* out_off,
                  int64_t nblocks, double2* out, hipStream_t st);
