@@ -704,10 +704,12 @@ __device__ void proj_acc(const ProjDev& t, int ti0, int jb, int je, PAcc<MX> (&a
   for (int j0 = jb; j0 < je; j0 += 4) {
     POp<MX> a2[NI], b2[NJ];
     load(j0 + 8 + kq, a2, b2);
+    // accumulators hold S^T tiles (rows: columns of W, columns: rows of R^T),
+    // so that the column-major S is stored with coalesced writes
 #pragma unroll
     for (int I = 0; I < NI; ++I)
 #pragma unroll
-      for (int J = 0; J < NJ; ++J) acc[I][J].mac(a0[I], b0[J]);
+      for (int J = 0; J < NJ; ++J) acc[I][J].mac(b0[J], a0[I]);
 #pragma unroll
     for (int I = 0; I < NI; ++I) {
       a0[I] = a1[I];
@@ -729,10 +731,10 @@ __device__ void proj_store(const ProjDev& t, int ti0, double om, PAcc<MX> (&acc)
   for (int I = 0; I < NI; ++I)
 #pragma unroll
     for (int J = 0; J < NJ; ++J) {
-      int jj = 16 * J + row;
+      int i = 16 * (ti0 + I) + row;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int i = 16 * (ti0 + I) + acc[I][J].row(lane, v);
+        int jj = 16 * J + acc[I][J].row(lane, v);
         double2 z = acc[I][J].get(v);
         if (i < t.kt && jj < t.ks) Sb[i + (int64_t)jj * t.kt] = make_double2(om * z.x, om * z.y);
       }
@@ -792,8 +794,8 @@ __global__ __launch_bounds__(256) void k_project_tiled(const ProjDev* tasks, int
         }
         int pr = e >> 8, v = (e >> 6) & 3, l = e & 63;
         int I = pr / NJ, J = pr - I * NJ;
-        int i = 16 * (ti0 + I) + (MX ? f32_row(l, v) : f64_row(l, v));
-        int jj = 16 * J + (l & 15);
+        int i = 16 * (ti0 + I) + (l & 15);
+        int jj = 16 * J + (MX ? f32_row(l, v) : f64_row(l, v));
         if (i < t.kt && jj < t.ks)
           t.S[i + (int64_t)jj * t.kt] = make_double2(om * (double)re, om * (double)im);
       }
