@@ -27,6 +27,9 @@ METRIC = "compression s & GFLOP/s, mixed vs FP64 form at equal eps, n=131072 kap
 PEAK_FP64_MFMA = 78.6e12   # MI355X dense matrix peaks (published)
 PEAK_FP32_MFMA = 157.3e12
 PEAK_INT8_MFMA = 5.0e15
+# HBM bytes per launch of k_gram_i8<0> on the default workload: FETCH_SIZE x 2 +
+# WRITE_SIZE x 1 (1 GiB copy calibration), profiles/compress_sphere131072_mixed.md
+TRAFFIC_GRAM_I8_LEAF = (2 * 318868.4 + 79608.6) * 1024
 
 
 def log(*a):
@@ -221,10 +224,13 @@ def main():
     r = res[head]
     st = r["stats"]
     nl = max(1, st["n_gram_leaf"])
+    traffic = args.traffic
     if head == "mixed":
         # dominant kernel: the int8-sliced leaf Gram (k_gram_i8<0>)
         kern = "k_gram_i8<0> (leaf Gram matrices, exact int8 slices on int8 MFMA)"
         work, peak, unit = st["ops_gram_leaf_i8"], PEAK_INT8_MFMA, "TOP/s"
+        if traffic is None and args.workload == "sphere131072":
+            traffic = TRAFFIC_GRAM_I8_LEAF
     else:
         kern = "k_gram_leaf_w (leaf Gram matrices on FP64 MFMA)"
         work, peak, unit = st["flops_gram_leaf"], PEAK_FP64_MFMA, "TFLOP/s"
@@ -249,7 +255,7 @@ def main():
                    "entries": "generated on the fly"},
         "roofline": {"bound": "mfma", "kernel": kern,
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
-                     "frac": achieved / peak, "traffic": args.traffic,
+                     "frac": achieved / peak, "traffic": traffic,
                      "launches": st["n_gram_leaf"],
                      "avg_launch_ms": st["t_gram_leaf"] / nl * 1e3,
                      "work_per_launch": work / nl},
