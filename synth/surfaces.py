@@ -126,6 +126,7 @@ def workload(name: str):
     sphere2048   : n=2048 spiral sphere, kappa=8, leaf 32, eps 1e-4
     sphere32768  : n=32768 spiral sphere, kappa=32, leaf 64, eps 1e-6
     ellip32768   : n=32768 rotated ellipsoid (1,.5,.25), kappa=32, leaf 64, eps 1e-4
+    ellip32768e6 : the same ellipsoid at eps 1e-6
     sphere131072 : n=131072 spiral sphere, kappa=64, leaf 64, eps 1e-4
     """
     if name == "sphere2048":
@@ -137,6 +138,9 @@ def workload(name: str):
     if name == "ellip32768":
         p, w = ellipsoid(32768)
         return p, w, 32.0, 64, 1e-4
+    if name == "ellip32768e6":
+        p, w = ellipsoid(32768)
+        return p, w, 32.0, 64, 1e-6
     if name == "sphere131072":
         p, w = fibonacci_sphere(131072)
         return p, w, 64.0, 64, 1e-4
