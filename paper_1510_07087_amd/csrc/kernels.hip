@@ -1545,6 +1545,9 @@ __device__ __forceinline__ ivec4 mfma_i8(ivec4 a, ivec4 b, ivec4 c) {
 }
 
 constexpr int kI8Tiles = 6;                           // complex row tiles per unit
+constexpr int kI8Threads = 1024;                      // 16 waves per unit
+constexpr int kI8Waves = kI8Threads / 64;
+constexpr int kI8ProdPerWave = 3;                     // 40 real tile products over 16 waves
 constexpr int kI8Slab = 1024;                         // one slice of one tile: 16 rows x 64 B
 constexpr int kI8Buf = kI8Tiles * 2 * 4 * kI8Slab;    // tiles x components x slices
 constexpr size_t kI8Lds = 2 * (size_t)kI8Buf + 3 * 64 * sizeof(double4) +
@@ -1554,31 +1557,26 @@ __device__ __forceinline__ int i8_off(int T, int comp, int p, int g, int i) {
   return ((((T * 2 + comp) * 4 + p) * 4 + g) * 16 + i) * 16;
 }
 
-// Four int8 slices of 8 values, packed two dwords each.  sc = 2^(28 - E)
+// Four int8 slices of 4 values, packed one dword each.  sc = 2^(28 - E)
 // with |v| < 2^E, so Y = trunc(v sc) fits 28 bits and
 // Y = q1 2^21 + q2 2^14 + q3 2^7 + q4 exactly, with q1 = floor(Y / 2^21) in
 // [-128, 127] and q2, q3, q4 in [0, 127] (two's complement bit fields).
-__device__ __forceinline__ void i8_slice8(const float* v, float sc, uint2* out) {
-  unsigned lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+__device__ __forceinline__ void i8_slice4(const float* v, float sc, unsigned* out) {
+  unsigned w[4] = {0, 0, 0, 0};
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < 4; ++q) {
     int Y = (int)(v[q] * sc);
     unsigned u = (unsigned)Y;
     unsigned b[4] = {(unsigned)(Y >> 21) & 0xffu, (u >> 14) & 0x7fu, (u >> 7) & 0x7fu, u & 0x7fu};
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      if (q < 4)
-        lo[p] |= b[p] << (8 * q);
-      else
-        hi[p] |= b[p] << (8 * (q - 4));
-    }
+    for (int p = 0; p < 4; ++p) w[p] |= b[p] << (8 * q);
   }
 #pragma unroll
-  for (int p = 0; p < 4; ++p) out[p] = make_uint2(lo[p], hi[p]);
+  for (int p = 0; p < 4; ++p) out[p] = w[p];
 }
 
 template <int KIND>  // 0: generated leaf block rows, 1: non-leaf block rows from the sons' R
-__global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items,
+__global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev* items,
                                                  const EntDev* ents, const UnitDev* units,
                                                  int side, double zeta2, double2* partial) {
   extern __shared__ __align__(16) char lds[];
@@ -1602,7 +1600,7 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
   auto row0 = [&](int T) { return 16 * (T < na ? u.a0 + T : u.b0 + (T - na)); };
 
   // ---- row data and row bounds ----
-  for (int e = tid; e < ntile * 16; e += 512) {
+  for (int e = tid; e < ntile * 16; e += kI8Threads) {
     rmaxb[e] = 0u;
     if constexpr (KIND == 0) rowd[e] = row_data<SRC_HELMHOLTZ>(g, it, row0(e >> 4) + (e & 15), side);
   }
@@ -1654,7 +1652,7 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
     }
     __syncthreads();
     const int64_t e0 = s_e0, ne = s_e1 - s_e0;
-    const int nrow = ntile * 16, stride = 512 / nrow;
+    const int nrow = ntile * 16, stride = kI8Threads / nrow;
     if (tid < stride * nrow) {
       const int rl = tid % nrow;
       const RowData rw = rowd[rl];
@@ -1680,7 +1678,7 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
   } else {
     // non-leaf rows: the largest |component| of every row of the sons' R
     // (recorded by their R-products; a bound over any column range)
-    for (int e = tid; e < ntile * 16; e += 512) {
+    for (int e = tid; e < ntile * 16; e += kI8Threads) {
       int rho = row0(e >> 4) + (e & 15);
       const ItemDev& s1 = items[it.son[0]];
       const ItemDev& s2 = items[it.son[1]];
@@ -1693,7 +1691,7 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
     }
   }
   __syncthreads();
-  for (int e = tid; e < ntile * 16; e += 512) {
+  for (int e = tid; e < ntile * 16; e += kI8Threads) {
     float m = __uint_as_float(rmaxb[e]) * 1.01f;
     int E = m > 0.0f ? ilogbf(m) + 1 : -100000;
     rexp[e] = E > -100 ? E : -100000;   // rows below 2^-100 are taken as zero
@@ -1703,21 +1701,23 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
   // ---- produce: entries of chunk c, sliced into buffer buf ----
   // non-leaf: the raw values of a chunk are loaded into registers one
   // iteration before they are sliced
-  float2 raw[2][8];
+  // combos of 4 columns: cb = ((T * 4 + gg) * 4 + pp) * 16 + i, columns
+  // 16 gg + 4 pp .. + 3 of the chunk for row i of tile T
+  float2 raw[2][4];
   auto load_raw = [&](int c) {
 #pragma unroll
     for (int h2 = 0; h2 < 2; ++h2) {
-      int cb = tid + 512 * h2;
+      int cb = tid + kI8Threads * h2;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) raw[h2][q] = make_float2(0.0f, 0.0f);
-      if (cb < ntile * 128 && c < nch) {
-        int i = cb & 15, hh = (cb >> 4) & 1, gg = (cb >> 5) & 3, T = cb >> 7;
+      for (int q = 0; q < 4; ++q) raw[h2][q] = make_float2(0.0f, 0.0f);
+      if (cb < ntile * 256 && c < nch) {
+        int i = cb & 15, pp = (cb >> 4) & 3, gg = (cb >> 6) & 3, T = cb >> 8;
         int ld;
         const float2* src = inner_src(row0(T) + i, ld);
-        int64_t j0 = (int64_t)c * 64 + 16 * gg + 8 * hh;
+        int64_t j0 = (int64_t)c * 64 + 16 * gg + 4 * pp;
         if (src) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q)
+          for (int q = 0; q < 4; ++q)
             if (j0 + q < ncols) raw[h2][q] = src[(it.col_off + u.col_begin + j0 + q) * ld];
         }
       }
@@ -1727,43 +1727,43 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
     char* S = slices + buf * kI8Buf;
 #pragma unroll
     for (int h2 = 0; h2 < 2; ++h2) {
-      int cb = tid + 512 * h2;
-      if (cb < ntile * 128) {
-        int i = cb & 15, hh = (cb >> 4) & 1, gg = (cb >> 5) & 3, T = cb >> 7;
+      int cb = tid + kI8Threads * h2;
+      if (cb < ntile * 256) {
+        int i = cb & 15, pp = (cb >> 4) & 3, gg = (cb >> 6) & 3, T = cb >> 8;
         int E = rexp[T * 16 + i];
         float sc = E > -100000 ? ldexpf(1.0f, 28 - E) : 0.0f;
-        float vr[8], vi[8];
+        float vr[4], vi[4];
         if constexpr (KIND == 0) {
           const RowData rw = rowd[T * 16 + i];
-          const double4* cc = cold + (c % 3) * 64 + 16 * gg + 8 * hh;
+          const double4* cc = cold + (c % 3) * 64 + 16 * gg + 4 * pp;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
+          for (int q = 0; q < 4; ++q) {
             float2 v = gen_entry_mx(g, rw, cc[q], side);
             vr[q] = v.x;
             vi[q] = v.y;
           }
         } else {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
+          for (int q = 0; q < 4; ++q) {
             vr[q] = raw[h2][q].x;
             vi[q] = raw[h2][q].y;
           }
         }
-        uint2 pr[4], pi[4];
-        i8_slice8(vr, sc, pr);
-        i8_slice8(vi, sc, pi);
+        unsigned pr[4], pi[4];
+        i8_slice4(vr, sc, pr);
+        i8_slice4(vi, sc, pi);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-          *reinterpret_cast<uint2*>(S + i8_off(T, 0, p, gg, i) + 8 * hh) = pr[p];
-          *reinterpret_cast<uint2*>(S + i8_off(T, 1, p, gg, i) + 8 * hh) = pi[p];
+          *reinterpret_cast<unsigned*>(S + i8_off(T, 0, p, gg, i) + 4 * pp) = pr[p];
+          *reinterpret_cast<unsigned*>(S + i8_off(T, 1, p, gg, i) + 4 * pp) = pi[p];
         }
       }
     }
   };
 
-  ivec4 acc[5][6];
+  ivec4 acc[kI8ProdPerWave][6];
 #pragma unroll
-  for (int s = 0; s < 5; ++s)
+  for (int s = 0; s < kI8ProdPerWave; ++s)
 #pragma unroll
     for (int l = 0; l < 6; ++l) acc[s][l] = ivec4{0, 0, 0, 0};
   // product q = 4 pair + type; type 0: re re, 1: im im, 2: im re, 3: re im
@@ -1785,32 +1785,23 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
     const char* S = slices + buf * kI8Buf;
     int gg = lane >> 4, i = lane & 15;
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-      int q = w + 8 * s;
+    for (int s = 0; s < kI8ProdPerWave; ++s) {
+      int q = w + kI8Waves * s;
       if (q < nprod) {
         int TA, TB, cA, cB;
         tiles_of(q, TA, TB, cA, cB);
-        ivec4 a[4], b[4];
+        // slice pairs (p, q) with p + q <= 5 (0-based) into level p + q
+        ivec4 a[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < 4; ++p)
           a[p] = *reinterpret_cast<const ivec4*>(S + i8_off(TA, cA, p, gg, i));
-          b[p] = *reinterpret_cast<const ivec4*>(S + i8_off(TB, cB, p, gg, i));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ivec4 b = *reinterpret_cast<const ivec4*>(S + i8_off(TB, cB, q, gg, i));
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+            if (p + q <= 5) acc[s][p + q] = mfma_i8(a[p], b, acc[s][p + q]);
         }
-        acc[s][0] = mfma_i8(a[0], b[0], acc[s][0]);
-        acc[s][1] = mfma_i8(a[0], b[1], acc[s][1]);
-        acc[s][1] = mfma_i8(a[1], b[0], acc[s][1]);
-        acc[s][2] = mfma_i8(a[0], b[2], acc[s][2]);
-        acc[s][2] = mfma_i8(a[1], b[1], acc[s][2]);
-        acc[s][2] = mfma_i8(a[2], b[0], acc[s][2]);
-        acc[s][3] = mfma_i8(a[0], b[3], acc[s][3]);
-        acc[s][3] = mfma_i8(a[1], b[2], acc[s][3]);
-        acc[s][3] = mfma_i8(a[2], b[1], acc[s][3]);
-        acc[s][3] = mfma_i8(a[3], b[0], acc[s][3]);
-        acc[s][4] = mfma_i8(a[1], b[3], acc[s][4]);
-        acc[s][4] = mfma_i8(a[2], b[2], acc[s][4]);
-        acc[s][4] = mfma_i8(a[3], b[1], acc[s][4]);
-        acc[s][5] = mfma_i8(a[2], b[3], acc[s][5]);
-        acc[s][5] = mfma_i8(a[3], b[2], acc[s][5]);
       }
     }
   };
@@ -1823,19 +1814,23 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
   produce(0, 0);
   if constexpr (KIND == 1) load_raw(1);
   __syncthreads();
+  // waves w, w + 4, w + 8, w + 12 share a SIMD: half of them run the two
+  // phases in the opposite order so that VALU work overlaps MFMAs
+  const bool mfma_first = (w >> 2) & 1;
   for (int c = 0; c < nch; ++c) {
     stage_cols(c + 2, (c + 2) % 3);
+    if (mfma_first) consume(c & 1);
     if (c + 1 < nch) produce(c + 1, (c + 1) & 1);
     if constexpr (KIND == 1) load_raw(c + 2);
-    consume(c & 1);
+    if (!mfma_first) consume(c & 1);
     __syncthreads();
   }
 
   // ---- FP64 conversion: real tile products to LDS, then complex pairs ----
   double* conv = reinterpret_cast<double*>(lds);  // nprod x 256, over the slice buffers
 #pragma unroll
-  for (int s = 0; s < 5; ++s) {
-    int q = w + 8 * s;
+  for (int s = 0; s < kI8ProdPerWave; ++s) {
+    int q = w + kI8Waves * s;
     if (q < nprod) {
       int TA, TB, cA, cB;
       tiles_of(q, TA, TB, cA, cB);
@@ -1852,7 +1847,7 @@ __global__ __launch_bounds__(512) void k_gram_i8(GeomDev g, const ItemDev* items
     }
   }
   __syncthreads();
-  for (int e = tid; e < npair * 256; e += 512) {
+  for (int e = tid; e < npair * 256; e += kI8Threads) {
     int p = e >> 8, v = (e >> 6) & 3, l = e & 63;
     int row = (l >> 4) + 4 * v, col = l & 15, o = row * 16 + col;
     double re = conv[(4 * p) * 256 + o] + conv[(4 * p + 1) * 256 + o];
@@ -1955,10 +1950,10 @@ void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const En
                         (int)kI8Lds);
   });
   if (inner)
-    hipLaunchKernelGGL(k_gram_i8<1>, dim3((unsigned)nunits), dim3(512), kI8Lds, st, g, items,
+    hipLaunchKernelGGL(k_gram_i8<1>, dim3((unsigned)nunits), dim3(kI8Threads), kI8Lds, st, g, items,
                        ents, units, side, zeta * zeta, partial);
   else
-    hipLaunchKernelGGL(k_gram_i8<0>, dim3((unsigned)nunits), dim3(512), kI8Lds, st, g, items,
+    hipLaunchKernelGGL(k_gram_i8<0>, dim3((unsigned)nunits), dim3(kI8Threads), kI8Lds, st, g, items,
                        ents, units, side, 1.0, partial);
 }
 
