@@ -1464,19 +1464,36 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
     int64_t j = u.col_begin + j0 + row;
     double4 cc = j0 + row < u.ncols ? it.cols[j] : make_double4(0.0, 0.0, 0.0, 0.0);
     RAcc<MX> acc[KT];
-    auto a = rop<MX>(gen_entry<SRC, MX>(g, rows[kq], cc, side));
-    for (int ks = 0; ks < nks; ++ks) {
-      int rho = 4 * ks + kq;
-      // next k-step's entry (rows array is padded past r)
-      auto an = rop<MX>(gen_entry<SRC, MX>(g, rows[rho + 4], cc, side));
+    if constexpr (MX && SRC == SRC_HELMHOLTZ) {
+      // the lane's entries of all k-steps first (independent chains), then
+      // the MFMAs (leaf block rows have at most 64 rows: 16 k-steps)
+      float2 e[16];
 #pragma unroll
-      for (int t = 0; t < KT; ++t) acc[t].mac(a, Qs[rho * (16 * KT) + 16 * t + row]);
+      for (int ks = 0; ks < 16; ++ks)
+        if (ks < nks) e[ks] = gen_entry_mx(g, rows[4 * ks + kq], cc, side);
 #pragma unroll
-      for (int q = 0; q < 4 * KT; ++q) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+      for (int ks = 0; ks < 16; ++ks) {
+        if (ks < nks) {
+          int rho = 4 * ks + kq;
+#pragma unroll
+          for (int t = 0; t < KT; ++t) acc[t].mac(e[ks], Qs[rho * (16 * KT) + 16 * t + row]);
+        }
       }
-      a = an;
+    } else {
+      auto a = rop<MX>(gen_entry<SRC, MX>(g, rows[kq], cc, side));
+      for (int ks = 0; ks < nks; ++ks) {
+        int rho = 4 * ks + kq;
+        // next k-step's entry (rows array is padded past r)
+        auto an = rop<MX>(gen_entry<SRC, MX>(g, rows[rho + 4], cc, side));
+#pragma unroll
+        for (int t = 0; t < KT; ++t) acc[t].mac(a, Qs[rho * (16 * KT) + 16 * t + row]);
+#pragma unroll
+        for (int q = 0; q < 4 * KT; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+        }
+        a = an;
+      }
     }
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
