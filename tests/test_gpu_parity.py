@@ -234,3 +234,24 @@ def test_stats(problem, gpu):
     kref = max(list(ref.V.k.values()) + list(ref.W.k.values()))
     assert abs(st["k_max"] - kref) <= 1
     assert st["t_total"] > 0 and st["flops_row"] > 0 and st["flops_col"] > 0
+
+
+def test_mixed_at_smallest_supported_eps(problem):
+    """The mixed form at eps = 1e-5, the smallest it accepts: global error
+    within 1.1 eps and within 10 % of the oracle's at the same eps."""
+    from oracle import dh2 as OD
+    from paper_1510_07087_amd import dh2
+    from dh2_export import exported_dense
+    eps = 1e-5
+    ref = OC.compress(problem["M"], problem["plan"], eps, ZETA)
+    o = dh2.opts(leaf_size=problem["leaf"], precision=dh2.MIXED)
+    b = dh2.blocks_build(dh2.tree_build(problem["p"], problem["kappa"], o), o)
+    m = dh2.compress_helmholtz(b, problem["w"], eps, o)
+    torch.cuda.synchronize()
+    G = problem["G"]
+    Gt = exported_dense(m, problem["plan"])[0]
+    err = np.linalg.norm(G - Gt, 2) / np.linalg.norm(G, 2)
+    err_ref = np.linalg.norm(G - OD.reconstruct(ref), 2) / np.linalg.norm(G, 2)
+    print(f"[gpu parity] mixed at eps 1e-5: rel err gpu {err:.3e} oracle {err_ref:.3e}", flush=True)
+    assert err <= 1.1 * eps
+    assert 0.9 * err_ref <= err <= 1.1 * err_ref
