@@ -29,7 +29,7 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_INT8_MFMA = 5.0e15
 # HBM bytes per launch of k_gram_i8<0> on the default workload: FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 (1 GiB copy calibration), profiles/compress_sphere131072_mixed.md
-TRAFFIC_GRAM_I8_LEAF = (2 * 318868.4 + 79608.6) * 1024
+TRAFFIC_GRAM_I8_LEAF = (2 * 333405.8 + 184032.7) * 1024
 
 
 def log(*a):
