@@ -43,6 +43,10 @@ __device__ __forceinline__ fvec4 mfma_f32(float a, float b, fvec4 c) {
 // lane l holds row 4 (l / 16) + v, column l % 16; operands as for FP64.
 __device__ __forceinline__ int f32_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 
+// Index of the calling wave in its workgroup as a wave-uniform value, so that
+// loops and loads that depend only on it stay scalar.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // complex element of an R^T array stored in FP64 (MX false) or FP32 (MX true)
 template <bool MX>
 __device__ __forceinline__ double2 rload(const void* R, int64_t idx) {
@@ -196,7 +200,7 @@ __global__ __launch_bounds__(256) void k_block_norm(GeomDev g, const int64_t* t_
   if (b >= nblocks) return;
   const int64_t to = t_off[b], tl = t_len[b], so = s_off[b], sl = s_len[b];
   // four row groups x 64 column lanes
-  const int ty = threadIdx.x >> 6, tx = threadIdx.x & 63;
+  const int ty = wave_id(), tx = threadIdx.x & 63;
   double acc = 0.0;
   for (int64_t i = to + ty; i < to + tl; i += 4) {
     if constexpr (SRC == SRC_HELMHOLTZ) {
@@ -315,7 +319,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
   int32_t ii = litems[blockIdx.x];
   ItemDev& it = items[ii];
   int r = it.r;
-  int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   const double2* Mi = it.M;
   if (r == 0) {
     if (tid == 0) it.k = 0;
@@ -586,7 +590,7 @@ struct SAcc<true> {
 template <bool MX>
 __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t ntasks,
                                                  const double* omega) {
-  int64_t ti = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  int64_t ti = (int64_t)blockIdx.x * 4 + wave_id();
   if (ti >= ntasks) return;
   const ProjDev t = tasks[ti];
   int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
@@ -634,20 +638,33 @@ template <bool MX>
 struct POp;
 template <>
 struct POp<false> {
-  double re, im, nim;
+  double re, im;
 };
 template <>
 struct POp<true> {
-  float re, im, nim;
+  float re, im;
 };
 
+// Load of element idx of a complex array in device memory, through a global
+// (not flat) pointer so that only the vector memory counter tracks it.
+// Buffer resource over the first `bytes` bytes at p (raw addressing, no
+// stride).  Loads through it at byte offsets past `bytes` return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// Complex element at byte offset off of a buffer (zero past its end).
 template <bool MX>
-__device__ __forceinline__ POp<MX> pop_make(double2 v) {
-  POp<MX> o;
-  o.re = v.x;
-  o.im = v.y;
-  o.nim = -o.im;
-  return o;
+__device__ __forceinline__ POp<MX> pload(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (MX) {
+    typedef float E __attribute__((ext_vector_type(2)));
+    E v = __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return POp<MX>{v.x, v.y};
+  } else {
+    typedef double E __attribute__((ext_vector_type(2)));
+    E v = __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return POp<MX>{v.x, v.y};
+  }
 }
 
 template <bool MX>
@@ -655,9 +672,10 @@ struct PAcc;
 template <>
 struct PAcc<false> {
   dvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+  // acc += a b (complex)
   __device__ __forceinline__ void mac(const POp<false>& a, const POp<false>& b) {
     re = mfma_f64(a.re, b.re, re);
-    re = mfma_f64(a.nim, b.im, re);
+    re = mfma_f64(-a.im, b.im, re);
     im = mfma_f64(a.re, b.im, im);
     im = mfma_f64(a.im, b.re, im);
   }
@@ -669,7 +687,7 @@ struct PAcc<true> {
   fvec4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
   __device__ __forceinline__ void mac(const POp<true>& a, const POp<true>& b) {
     re = mfma_f32(a.re, b.re, re);
-    re = mfma_f32(a.nim, b.im, re);
+    re = mfma_f32(-a.im, b.im, re);
     im = mfma_f32(a.re, b.im, im);
     im = mfma_f32(a.im, b.re, im);
   }
@@ -678,49 +696,67 @@ struct PAcc<true> {
 };
 
 // Accumulates the NI x NJ tile pairs of row tiles ti0.. over columns
-// [jb, je) of s (jb, je multiples of 4 or je = ns).
+// [jb, je) of s (jb a multiple of 4, jb < je).  Every load is unconditional:
+// row and column indices past kt, ks only feed accumulator rows and columns
+// that are never stored, so they are clamped to the last valid one; columns
+// of s past je lie outside the buffer ranges and load as zero.  Operands are
+// loaded two k-steps ahead into a ring of three register sets that is
+// unrolled, so no loaded register is copied (a copy would wait for the load).
 template <bool MX, int NI, int NJ>
 __device__ void proj_acc(const ProjDev& t, int ti0, int jb, int je, PAcc<MX> (&acc)[NI][NJ]) {
   int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   const int kt = t.kt, ks = t.ks;
+  constexpr int esz = sizeof(POp<MX>);
+  // columns of s past je read as zero from both buffers
+  const __amdgpu_buffer_rsrc_t rR = buf_rsrc(t.R, (int64_t)je * kt * esz);
+  const __amdgpu_buffer_rsrc_t rW = buf_rsrc(t.W, (int64_t)je * ks * esz);
+  int ra[NI], wa[NJ];
+#pragma unroll
+  for (int I = 0; I < NI; ++I) ra[I] = min(16 * (ti0 + I) + row, kt - 1) * esz;
+#pragma unroll
+  for (int J = 0; J < NJ; ++J) wa[J] = min(16 * J + row, ks - 1) * esz;
   auto load = [&](int j, POp<MX>* aa, POp<MX>* bb) {
 #pragma unroll
-    for (int I = 0; I < NI; ++I) {
-      int ii = 16 * (ti0 + I) + row;
-      aa[I] = pop_make<MX>((j < je && ii < kt) ? rload<MX>(t.R, (int64_t)j * kt + ii)
-                                                : make_double2(0.0, 0.0));
-    }
+    for (int I = 0; I < NI; ++I) aa[I] = pload<MX>(rR, j * kt * esz + ra[I]);
 #pragma unroll
-    for (int J = 0; J < NJ; ++J) {
-      int jj = 16 * J + row;
-      bb[J] = pop_make<MX>((j < je && jj < ks) ? rload<MX>(t.W, (int64_t)j * ks + jj)
-                                                : make_double2(0.0, 0.0));
-    }
+    for (int J = 0; J < NJ; ++J) bb[J] = pload<MX>(rW, j * ks * esz + wa[J]);
   };
-  // operands two k-steps ahead
-  POp<MX> a0[NI], b0[NJ], a1[NI], b1[NJ];
-  load(jb + kq, a0, b0);
-  load(jb + 4 + kq, a1, b1);
-  for (int j0 = jb; j0 < je; j0 += 4) {
-    POp<MX> a2[NI], b2[NJ];
-    load(j0 + 8 + kq, a2, b2);
-    // accumulators hold S^T tiles (rows: columns of W, columns: rows of R^T),
-    // so that the column-major S is stored with coalesced writes
+  // accumulators hold S^T tiles (rows: columns of W, columns: rows of R^T),
+  // so that the column-major S is stored with coalesced writes
+  auto step = [&](const POp<MX>* aa, const POp<MX>* bb) {
 #pragma unroll
     for (int I = 0; I < NI; ++I)
 #pragma unroll
-      for (int J = 0; J < NJ; ++J) acc[I][J].mac(b0[J], a0[I]);
-#pragma unroll
-    for (int I = 0; I < NI; ++I) {
-      a0[I] = a1[I];
-      a1[I] = a2[I];
-    }
-#pragma unroll
-    for (int J = 0; J < NJ; ++J) {
-      b0[J] = b1[J];
-      b1[J] = b2[J];
-    }
+      for (int J = 0; J < NJ; ++J) acc[I][J].mac(bb[J], aa[I]);
+  };
+  POp<MX> a0[NI], b0[NJ], a1[NI], b1[NJ], a2[NI], b2[NJ];
+  // drain the previous pass (its stores and unused prefetches), so that the
+  // wait counts inside the loop below are exact
+  __builtin_amdgcn_s_waitcnt(0);
+  load(jb + kq, a0, b0);
+  __builtin_amdgcn_sched_barrier(0);
+  load(jb + 4 + kq, a1, b1);
+  __builtin_amdgcn_sched_barrier(0);
+  const int nst = (je - jb + 3) / 4;
+  int j0 = jb;
+  // the scheduling barriers keep every load two steps ahead of its use (the
+  // scheduler would otherwise sink the loads to the end of the loop body)
+  for (int it = nst / 3; it > 0; --it, j0 += 12) {
+    load(j0 + 8 + kq, a2, b2);
+    __builtin_amdgcn_sched_barrier(0);
+    step(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(j0 + 12 + kq, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    step(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    load(j0 + 16 + kq, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(a2, b2);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (nst % 3 >= 1) step(a0, b0);
+  if (nst % 3 == 2) step(a1, b1);
 }
 
 template <bool MX, int NI, int NJ>
@@ -757,7 +793,7 @@ __global__ __launch_bounds__(256) void k_project_tiled(const ProjDev* tasks, int
   unsigned nb = gridDim.x, b = blockIdx.x;
   unsigned x = b & 7u, loc = b >> 3, q = nb >> 3, rmd = nb & 7u;
   unsigned slot = x * q + (x < rmd ? x : rmd) + loc;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = wave_id(), lane = threadIdx.x & 63;
   int64_t ti = SPLIT > 1 ? (int64_t)slot : (int64_t)slot * 4 + w;
   if (ti >= ntasks) return;
   const ProjDev t = tasks[ti];
@@ -1180,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_gram_leaf_w(GeomDev g, const ItemDev* i
                                                      const EntDev* ents, const UnitDev* units,
                                                      int64_t nunits, int side, double2* partial) {
   __shared__ double4 cls[4][64];
-  int w = threadIdx.x >> 6;
+  int w = wave_id();
   int64_t ui = (int64_t)blockIdx.x * 4 + w;
   if (ui >= nunits) return;
   const UnitDev u = units[ui];
@@ -1266,7 +1302,7 @@ template <bool MX>
 __global__ __launch_bounds__(256) void k_gram_inner_w(const ItemDev* items, const UnitDev* units,
                                                       int64_t nunits, double zeta,
                                                       double2* partial) {
-  int w = threadIdx.x >> 6;
+  int w = wave_id();
   int64_t ui = (int64_t)blockIdx.x * 4 + w;
   if (ui >= nunits) return;
   const UnitDev u = units[ui];
@@ -1367,48 +1403,101 @@ __device__ __forceinline__ void rmax_flush(const ItemDev& it, const unsigned* s_
     if (s_rmax[kk]) atomicMax(reinterpret_cast<unsigned*>(it.rmax) + kk, s_rmax[kk]);
 }
 
+// Complex element at byte offset off of a buffer (zero past its end), as an
+// R-product operand.
+template <bool MX>
+__device__ __forceinline__ ROp<MX> rbload(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (MX)
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 // R^T of a non-leaf block row, one workgroup per unit (column range): the
-// four waves share Q_hat (in the compute precision) in LDS and take 16-column
-// groups in turn.  R^T[j][kk] = zeta sum_rho [R_t1c'; R_t2c'][rho][j]
-// conj(Q_hat[rho][kk]); the sons' values are loaded two k-steps ahead.
+// four waves share Q_hat (in the compute precision, rows padded with zeros to
+// r + 8) in LDS and take 16-column groups in turn.
+// R^T[j][kk] = zeta sum_rho [R_t1c'; R_t2c'][rho][j] conj(Q_hat[rho][kk]).
+// Row rho of the stacked sons' R is the sum of one load from each son's
+// buffer, the other being out of range (zero); columns past the unit load as
+// zero too.  The sons' values are loaded two k-steps ahead and Q_hat one
+// step ahead, in rings of three register sets that are unrolled so that no
+// loaded register is copied.
 template <bool MX, int KT>
 __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
                                const UnitDev& u, double zeta, const ROp<MX>* Qs,
                                unsigned* s_rmax) {
   using OT = ROp<MX>;
-  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  constexpr int esz = sizeof(OT);
+  int w = wave_id(), lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   const int r = it.r, k = it.k, k1 = s1.k, k2 = s2.k;
   const int nks = (r + 3) / 4;
   constexpr int ldq = 16 * KT;
-  const OT* R1 = reinterpret_cast<const OT*>(s1.R);
-  const OT* R2 = reinterpret_cast<const OT*>(s2.R);
-  for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
-    const bool valid = j0 + row < u.ncols;
-    const int64_t jc = it.col_off + u.col_begin + j0 + row;
-    auto ld = [&](int rho) -> OT {
-      OT z;
-      z.x = 0;
-      z.y = 0;
-      if (!valid || rho >= r) return z;
-      return rho < k1 ? R1[jc * k1 + rho] : R2[jc * k2 + (rho - k1)];
+  const int ncols = (int)u.ncols;
+  const int64_t c0 = it.col_off + u.col_begin;
+  const int nb1 = ncols * k1 * esz, nb2 = ncols * k2 * esz;
+  const __amdgpu_buffer_rsrc_t rs1 = buf_rsrc((const char*)s1.R + c0 * k1 * esz, nb1);
+  const __amdgpu_buffer_rsrc_t rs2 = buf_rsrc((const char*)s2.R + c0 * k2 * esz, nb2);
+  struct AP {
+    OT x, y;
+  };
+  for (int j0 = 16 * w; j0 < ncols; j0 += 64) {
+    const int jl = j0 + row;
+    auto lda = [&](int rho, AP& a) {
+      a.x = rbload<MX>(rs1, rho < k1 ? (jl * k1 + rho) * esz : nb1);
+      a.y = rbload<MX>(rs2, (rho >= k1 && rho < r) ? (jl * k2 + rho - k1) * esz : nb2);
+    };
+    auto ldqs = [&](int rho, OT* q) {
+#pragma unroll
+      for (int t = 0; t < KT; ++t) q[t] = Qs[rho * ldq + 16 * t + row];
     };
     RAcc<MX> acc[KT];
-    OT a0 = ld(kq), a1 = ld(kq + 4);
-    for (int ks = 0; ks < nks; ++ks) {
-      int rho = 4 * ks + kq;
-      OT a2 = ld(rho + 8);
+    auto mac = [&](const AP& a, const OT* q) {
+      OT v;
+      v.x = a.x.x + a.y.x;
+      v.y = a.x.y + a.y.y;
 #pragma unroll
-      for (int t = 0; t < KT; ++t) acc[t].mac(a0, Qs[rho * ldq + 16 * t + row]);
-      a0 = a1;
-      a1 = a2;
+      for (int t = 0; t < KT; ++t) acc[t].mac(v, q[t]);
+    };
+    AP a0, a1, a2;
+    OT q0[KT], q1[KT], q2[KT];
+    // drain the previous column group (stores, unused prefetches) so that the
+    // wait counts inside the loop are exact
+    __builtin_amdgcn_s_waitcnt(0);
+    lda(kq, a0);
+    __builtin_amdgcn_sched_barrier(0);
+    lda(4 + kq, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    ldqs(kq, q0);
+    int rho0 = 0;
+    for (int n3 = nks / 3; n3 > 0; --n3, rho0 += 12) {
+      lda(rho0 + 8 + kq, a2);
+      ldqs(rho0 + 4 + kq, q1);
+      __builtin_amdgcn_sched_barrier(0);
+      mac(a0, q0);
+      __builtin_amdgcn_sched_barrier(0);
+      lda(rho0 + 12 + kq, a0);
+      ldqs(rho0 + 8 + kq, q2);
+      __builtin_amdgcn_sched_barrier(0);
+      mac(a1, q1);
+      __builtin_amdgcn_sched_barrier(0);
+      lda(rho0 + 16 + kq, a1);
+      ldqs(rho0 + 12 + kq, q0);
+      __builtin_amdgcn_sched_barrier(0);
+      mac(a2, q2);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (nks % 3 >= 1) {
+      ldqs(rho0 + 4 + kq, q1);
+      mac(a0, q0);
+    }
+    if (nks % 3 == 2) mac(a1, q1);
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
       int kk = 16 * t + row;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int64_t jl = j0 + acc[t].row(lane, v);
-        if (jl < u.ncols && kk < k) acc[t].store(it.R, (u.col_begin + jl) * k + kk, v, zeta);
+        int64_t jv = j0 + acc[t].row(lane, v);
+        if (jv < ncols && kk < k) acc[t].store(it.R, (u.col_begin + jv) * k + kk, v, zeta);
       }
       if constexpr (MX) {
         // the stored values are the accumulators scaled by zeta in FP32
@@ -1419,7 +1508,7 @@ __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemD
           sc.re[v] *= z;
           sc.im[v] *= z;
         }
-        rmax_tile<MX>(sc, j0, u.ncols, kk, k, s_rmax);
+        rmax_tile<MX>(sc, j0, ncols, kk, k, s_rmax);
       }
     }
   }
@@ -1438,7 +1527,7 @@ __global__ __launch_bounds__(256) void k_rprod_inner_g(const ItemDev* items, con
   const int r = it.r, k = it.k;
   if (k == 0 || (k + 15) / 16 != KT) return;
   constexpr int ldq = 16 * KT;
-  for (int e = threadIdx.x; e < (r + 4) * ldq; e += 256) {
+  for (int e = threadIdx.x; e < (r + 8) * ldq; e += 256) {
     int i = e / ldq, kk = e - i * ldq;
     Qs[e] = rop<MX>((i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0));
   }
@@ -1457,7 +1546,7 @@ template <int SRC, bool MX, int KT>
 __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
                                 const UnitDev& u, const ROp<MX>* Qs, const RowData* rows,
                                 unsigned* s_rmax) {
-  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+  int w = wave_id(), lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   int r = it.r, k = it.k;
   int nks = (r + 3) / 4;
   for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
@@ -1605,7 +1694,7 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
 
   const UnitDev u = units[blockIdx.x];
   const ItemDev& it = items[u.item];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, w = wave_id(), lane = tid & 63;
   const bool diag = u.a0 == u.b0;
   const int na = u.na, nb = u.nb;
   const int ntile = diag ? na : na + nb;
@@ -1978,7 +2067,7 @@ size_t rprod_inner_lds_max() { return kRprodLdsMax; }
 
 size_t rprod_inner_lds(bool mixed, int r, int k) {
   int kt = (k + 15) / 16;
-  return (size_t)(r + 4) * 16 * kt * (mixed ? sizeof(float2) : sizeof(double2));
+  return (size_t)(r + 8) * 16 * kt * (mixed ? sizeof(float2) : sizeof(double2));
 }
 
 template <bool MX, int KT>
