@@ -77,6 +77,23 @@ struct ProjDev {
   int32_t b;
 };
 
+// Stacked projection of the mixed form: the blocks of one level that share
+// the expanded column basis W_sc are stacked row-wise (their R rows one after
+// the other); a tile is up to 64 consecutive stacked rows.
+struct PBlkDev {
+  const float2* R;  // R^T rows of the block: column j of s at R[j * kt + i]
+  double2* S;       // output (kt x ks column-major)
+  int32_t kt, b;
+};
+struct PTileDev {
+  const float2* W;  // expanded column basis (|s| x ks row-major), complex FP32
+  int32_t blk0;     // block holding the tile's first row (index into the PBlkDev array)
+  int32_t i0;       // that row inside blk0
+  int32_t rows;     // stacked rows of the tile (1..64)
+  int32_t nblk;     // blocks the tile intersects (1..64)
+  int32_t ns, ks;   // |s| and the rank of W (1..64)
+};
+
 // Conversion task of the mixed form: count complex values FP64 -> FP32.
 struct CvtDev {
   const double2* src;

@@ -104,6 +104,12 @@ size_t cache_limit() {
   return lim;
 }
 
+size_t g_cache_largest_locked() {
+  size_t big = 0;
+  for (const auto& c : g_cache) big = std::max(big, c.bytes);
+  return big;
+}
+
 void trim_cache_locked(size_t keep) {
   while (g_cached > keep && !g_cache.empty()) {
     size_t big = 0;
@@ -157,18 +163,52 @@ void* DevMem::alloc(size_t bytes) {
     }
   }
   if (!p) {
+    // keep cached blocks from pushing the device past its memory: the driver
+    // would evict allocations to host memory instead of failing
+    {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        const size_t margin = size_t(2) << 30;
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        while (fr < bytes + margin && !g_cache.empty()) {
+          size_t big = g_cache_largest_locked();
+          trim_cache_locked(g_cached - std::min(g_cached, big));
+          fr += big;
+        }
+      } else {
+        (void)hipGetLastError();
+      }
+    }
     hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
+    while (e != hipSuccess) {
       (void)hipGetLastError();
+      // no room: take the smallest cached block that is large enough, however
+      // large, else return the largest cached block to the driver and retry
+      // (freeing the whole cache would make every later level allocate from
+      // scratch)
+      bool freed = false;
       {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        trim_cache_locked(0);
+        size_t best = g_cache.size();
+        for (size_t i = 0; i < g_cache.size(); ++i)
+          if (g_cache[i].bytes >= bytes && (cap_ <= 0 || used_ + (int64_t)g_cache[i].bytes <= cap_) &&
+              (best == g_cache.size() || g_cache[i].bytes < g_cache[best].bytes))
+            best = i;
+        if (best < g_cache.size()) {
+          p = g_cache[best].p;
+          bytes = g_cache[best].bytes;
+          g_cached -= bytes;
+          g_cache[best] = g_cache.back();
+          g_cache.pop_back();
+          break;
+        }
+        if (!g_cache.empty()) {
+          trim_cache_locked(g_cached - std::min(g_cached, g_cache_largest_locked()));
+          freed = true;
+        }
       }
+      if (!freed) fail(DH2_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
       e = hipMalloc(&p, bytes);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(DH2_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-      }
     }
   }
   live_.push_back({p, bytes});
@@ -814,6 +854,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           o += (int64_t)it.k * ks;
           ss.flops_prj += 8.0 * it.k * (double)ks * (double)q.ns;
           if (it.k == 0 || ks == 0) continue;
+          if (mixed && ks <= 64) continue;  // stacked kernel below
           int nj = (ks + 15) / 16, ni = (it.k + 15) / 16;
           int kx = kGeneric;
           if (nj <= 4)
@@ -840,9 +881,78 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           for (size_t x = 0; x < pl.size(); ++x)
             if (key[x] != 255) sorted[start[key[x]]++] = tasks[x];
         }
+        // mixed form, ks <= 64: the blocks of each run of equal column item
+        // (the plan is sorted by it) stacked row-wise, cut into tiles of up
+        // to 64 rows, tiles sorted by ceil(ks / 4)
+        std::vector<PBlkDev> pblk;
+        std::vector<PTileDev> ptile;
+        int64_t ncount[17] = {0};
+        if (mixed) {
+          std::vector<uint8_t> tnc;
+          for (size_t g0 = 0; g0 < pl.size();) {
+            size_t g1 = g0;
+            while (g1 < pl.size() && pl[g1].witem == pl[g0].witem) ++g1;
+            const int32_t ks = M.side[1].items[pl[g0].witem].k;
+            if (ks == 0 || ks > 64) {
+              g0 = g1;
+              continue;
+            }
+            const int32_t b0 = (int32_t)pblk.size();
+            for (size_t x = g0; x < g1; ++x)
+              if (tasks[x].kt > 0)
+                pblk.push_back(PBlkDev{(const float2*)tasks[x].R, tasks[x].S, tasks[x].kt, tasks[x].b});
+            const int32_t b1 = (int32_t)pblk.size();
+            int32_t bi = b0, i0 = 0;
+            while (bi < b1) {
+              PTileDev t;
+              t.W = M.side[1].wexp32[pl[g0].witem];
+              t.blk0 = bi;
+              t.i0 = i0;
+              t.ns = pl[g0].ns;
+              t.ks = ks;
+              int32_t rows = 0, nblk = 0;
+              while (rows < 64 && bi < b1) {
+                int32_t take = std::min(64 - rows, pblk[bi].kt - i0);
+                rows += take;
+                i0 += take;
+                ++nblk;
+                if (i0 == pblk[bi].kt) {
+                  ++bi;
+                  i0 = 0;
+                }
+              }
+              t.rows = rows;
+              t.nblk = nblk;
+              ptile.push_back(t);
+              tnc.push_back((uint8_t)((ks + 3) / 4));
+              ++ncount[(ks + 3) / 4];
+            }
+            g0 = g1;
+          }
+          std::vector<PTileDev> tsorted(ptile.size());
+          int64_t start[17], run = 0;
+          for (int c = 0; c <= 16; ++c) {
+            start[c] = run;
+            run += ncount[c];
+          }
+          for (size_t x = 0; x < ptile.size(); ++x) tsorted[start[tnc[x]]++] = ptile[x];
+          ptile.swap(tsorted);
+        }
         ProjDev* d_tasks = upload(mem, sorted, st);
+        PBlkDev* d_pblk = upload(mem, pblk, st);
+        PTileDev* d_ptile = upload(mem, ptile, st);
         tr_.mark("proj tasks", s, b, lv);
         tp.start();
+        {
+          int64_t toff = 0;
+          for (int cls = 0, c = 1; cls < 3; ++cls) {
+            int64_t cnt = 0;
+            for (; c <= kPstLast[cls]; ++c) cnt += ncount[c];
+            launch_project_stacked(cls, d_ptile + toff, cnt, d_pblk, M.d_omega, st);
+            toff += cnt;
+          }
+          launch_check("project (stacked)");
+        }
         int64_t off = 0;
         for (const auto& L : launches) {
           if (L[0] > 0)
@@ -856,6 +966,8 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         tp.stop();
         tr_.mark("project", s, b, lv);
         mem.release(d_tasks);
+        mem.release(d_pblk);
+        mem.release(d_ptile);
       }
       hip_check(hipStreamSynchronize(st), "level sync");
       mem.release(d_units);
@@ -1019,7 +1131,8 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     if (tr.level[t] == lg) group[t] = ngroups++;
     else if (tr.level[t] > lg) group[t] = group[tr.father[t]];
   }
-  // estimated R memory per level (16 bytes per coefficient, rank estimate)
+  // estimated R memory per level (rank estimate, 16 bytes per coefficient in
+  // the FP64 form, 8 in the mixed form)
   std::vector<double> lvlN(tr.depth + 2, 0.0), grpN(std::max(1, ngroups), 0.0);
   for (int s = 0; s < 2; ++s) {
     const ColumnSets& cs = blk->cs[s];
@@ -1033,7 +1146,8 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   }
   double kest = std::min(48.0, (double)o.leaf_size);
   double peak = 0;
-  for (int32_t l = 0; l <= tr.depth; ++l) peak = std::max(peak, (lvlN[l] + lvlN[l + 1]) * kest * 16.0);
+  const double csz = o.precision == DH2_MIXED ? 8.0 : 16.0;
+  for (int32_t l = 0; l <= tr.depth; ++l) peak = std::max(peak, (lvlN[l] + lvlN[l + 1]) * kest * csz);
   size_t freeb = 0, totalb = 0;
   hip_check(hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo");
   {

@@ -13,6 +13,7 @@
 
 #include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include <cmath>
 #include <cstdint>
@@ -700,7 +701,7 @@ struct PAcc<true> {
 // row and column indices past kt, ks only feed accumulator rows and columns
 // that are never stored, so they are clamped to the last valid one; columns
 // of s past je lie outside the buffer ranges and load as zero.  Operands are
-// loaded two k-steps ahead into a ring of three register sets that is
+// loaded three k-steps ahead into a ring of four register sets that is
 // unrolled, so no loaded register is copied (a copy would wait for the load).
 template <bool MX, int NI, int NJ>
 __device__ void proj_acc(const ProjDev& t, int ti0, int jb, int je, PAcc<MX> (&acc)[NI][NJ]) {
@@ -729,34 +730,158 @@ __device__ void proj_acc(const ProjDev& t, int ti0, int jb, int je, PAcc<MX> (&a
 #pragma unroll
       for (int J = 0; J < NJ; ++J) acc[I][J].mac(bb[J], aa[I]);
   };
-  POp<MX> a0[NI], b0[NJ], a1[NI], b1[NJ], a2[NI], b2[NJ];
+  constexpr int kRing = 4;
+  POp<MX> a[kRing][NI], b[kRing][NJ];
   // drain the previous pass (its stores and unused prefetches), so that the
   // wait counts inside the loop below are exact
   __builtin_amdgcn_s_waitcnt(0);
-  load(jb + kq, a0, b0);
-  __builtin_amdgcn_sched_barrier(0);
-  load(jb + 4 + kq, a1, b1);
-  __builtin_amdgcn_sched_barrier(0);
-  const int nst = (je - jb + 3) / 4;
-  int j0 = jb;
-  // the scheduling barriers keep every load two steps ahead of its use (the
-  // scheduler would otherwise sink the loads to the end of the loop body)
-  for (int it = nst / 3; it > 0; --it, j0 += 12) {
-    load(j0 + 8 + kq, a2, b2);
-    __builtin_amdgcn_sched_barrier(0);
-    step(a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
-    load(j0 + 12 + kq, a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
-    step(a1, b1);
-    __builtin_amdgcn_sched_barrier(0);
-    load(j0 + 16 + kq, a1, b1);
-    __builtin_amdgcn_sched_barrier(0);
-    step(a2, b2);
+#pragma unroll
+  for (int st = 0; st < kRing - 1; ++st) {
+    load(jb + 4 * st + kq, a[st], b[st]);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (nst % 3 >= 1) step(a0, b0);
-  if (nst % 3 == 2) step(a1, b1);
+  const int nst = (je - jb + 3) / 4;
+  int j0 = jb;
+  // the scheduling barriers keep every load kRing - 1 steps ahead of its use
+  // (the scheduler would otherwise sink the loads to the end of the body)
+  for (int n = nst / kRing; n > 0; --n, j0 += 4 * kRing) {
+#pragma unroll
+    for (int st = 0; st < kRing; ++st) {
+      load(j0 + 4 * (st + kRing - 1) + kq, a[(st + kRing - 1) % kRing], b[(st + kRing - 1) % kRing]);
+      __builtin_amdgcn_sched_barrier(0);
+      step(a[st], b[st]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int st = 0; st < kRing - 1; ++st)
+    if (st < nst % kRing) step(a[st], b[st]);
+}
+
+// Stacked projection (mixed form), one wave per tile of up to 64 stacked rows
+// of blocks sharing W: lane l owns stacked row l, and the 4x4x1 MFMA (16
+// blocks of 4 x 4) runs with its A operand broadcast from block c (CBSZ 4,
+// ABID c), so that lane 4 c + v supplies W[j][4 c + v] to every block and
+// the product lands in lane l, register v as S(row l, column 4 c + v).  One
+// load of R and one of W per column j of s feed 4 NC MFMAs; no dimension is
+// padded beyond the column groups of 4 and the tile's last rows.
+template <int C>
+__device__ __forceinline__ void pst_mac(float wr, float wi, float rr, float ri, float nri,
+                                        fvec4& re, fvec4& im) {
+  re = __builtin_amdgcn_mfma_f32_4x4x1f32(wr, rr, re, 4, C, 0);
+  re = __builtin_amdgcn_mfma_f32_4x4x1f32(wi, nri, re, 4, C, 0);
+  im = __builtin_amdgcn_mfma_f32_4x4x1f32(wr, ri, im, 4, C, 0);
+  im = __builtin_amdgcn_mfma_f32_4x4x1f32(wi, rr, im, 4, C, 0);
+}
+
+template <int... C>
+__device__ __forceinline__ void pst_macs(std::integer_sequence<int, C...>, float2 w, float2 r,
+                                         fvec4* re, fvec4* im) {
+  const float nri = -r.y;
+  (pst_mac<C>(w.x, w.y, r.x, r.y, nri, re[C], im[C]), ...);
+}
+
+template <int NC>
+__device__ __forceinline__ void pst_tile(const PTileDev& t, const PBlkDev* blks,
+                                         const double* omega) {
+  typedef float fv2 __attribute__((ext_vector_type(2)));
+  using GP = const __attribute__((address_space(1))) fv2*;
+  constexpr int kRing = 8;
+  const int lane = threadIdx.x & 63;
+  // ranks of the tile's blocks in lanes q < nblk, their first stacked rows
+  // (relative to the tile) by an exclusive prefix sum, then this lane's block
+  const int ktq = lane < t.nblk ? blks[t.blk0 + lane].kt : 0;
+  int incl = ktq;
+  for (int o = 1; o < 64; o <<= 1) {
+    int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  const int start = incl - ktq - t.i0;
+  const int m = min(lane, t.rows - 1);
+  int myq = 0, i = m + t.i0;
+  for (int q = 1; q < t.nblk; ++q) {
+    int sq = __builtin_amdgcn_readlane(start, q);
+    if (m >= sq) {
+      myq = q;
+      i = m - sq;
+    }
+  }
+  const PBlkDev B = blks[t.blk0 + myq];
+  const int kt = B.kt, ns = t.ns, ks = t.ks;
+  const GP Rp = (GP)(B.R + i);                    // column j at Rp[j * kt]
+  const GP Wp = (GP)(t.W + min(lane, ks - 1));    // row j at Wp[j * ks]
+  fvec4 re[NC], im[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) re[c] = im[c] = fvec4{0.0f, 0.0f, 0.0f, 0.0f};
+  fv2 rv[kRing], wv[kRing];
+  auto load = [&](int j, int st) {
+    const int jc = min(j, ns - 1);
+    rv[st] = Rp[(int64_t)jc * kt];
+    wv[st] = Wp[(int64_t)jc * ks];
+  };
+  auto mac = [&](int st) {
+    pst_macs(std::make_integer_sequence<int, NC>{}, make_float2(wv[st].x, wv[st].y),
+             make_float2(rv[st].x, rv[st].y), re, im);
+  };
+  // columns of s kRing - 1 ahead of their use, in an unrolled ring
+#pragma unroll
+  for (int st = 0; st < kRing - 1; ++st) {
+    load(st, st);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  int j0 = 0;
+  for (int n = ns / kRing; n > 0; --n, j0 += kRing) {
+#pragma unroll
+    for (int st = 0; st < kRing; ++st) {
+      load(j0 + st + kRing - 1, (st + kRing - 1) % kRing);
+      __builtin_amdgcn_sched_barrier(0);
+      mac(st);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int st = 0; st < kRing - 1; ++st)
+    if (st < ns % kRing) mac(st);
+  if (lane < t.rows) {
+    const double om = omega[B.b];
+    double2* Sr = B.S + i;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int col = 4 * c + v;
+        if (col < ks) Sr[(int64_t)col * kt] = make_double2(om * re[c][v], om * im[c][v]);
+      }
+  }
+}
+
+// Tiles of one launch have ceil(ks / 4) in [NC0, NC1]; each wave dispatches
+// on its own tile's column-group count.
+template <int NC0, int NC1>
+__global__ __launch_bounds__(256) void k_project_stacked(const PTileDev* tiles, int64_t ntiles,
+                                                         const PBlkDev* blks,
+                                                         const double* omega) {
+  // XCD-aware order, as in k_project_tiled
+  unsigned nb = gridDim.x, bx = blockIdx.x;
+  unsigned x = bx & 7u, loc = bx >> 3, qx = nb >> 3, rmd = nb & 7u;
+  unsigned slot = x * qx + (x < rmd ? x : rmd) + loc;
+  int64_t ti = (int64_t)slot * 4 + wave_id();
+  if (ti >= ntiles) return;
+  const PTileDev t = tiles[ti];
+  const int nc = (t.ks + 3) / 4;
+  static_assert(NC0 >= 1 && NC1 <= 16 && NC0 <= NC1, "column groups");
+#define DH2_PST_CASE(C) \
+  case C:               \
+    if constexpr (C >= NC0 && C <= NC1) pst_tile<C>(t, blks, omega); \
+    break;
+  switch (nc) {
+    DH2_PST_CASE(1) DH2_PST_CASE(2) DH2_PST_CASE(3) DH2_PST_CASE(4)
+    DH2_PST_CASE(5) DH2_PST_CASE(6) DH2_PST_CASE(7) DH2_PST_CASE(8)
+    DH2_PST_CASE(9) DH2_PST_CASE(10) DH2_PST_CASE(11) DH2_PST_CASE(12)
+    DH2_PST_CASE(13) DH2_PST_CASE(14) DH2_PST_CASE(15) DH2_PST_CASE(16)
+    default: break;
+  }
+#undef DH2_PST_CASE
 }
 
 template <bool MX, int NI, int NJ>
@@ -1419,15 +1544,16 @@ __device__ __forceinline__ ROp<MX> rbload(__amdgpu_buffer_rsrc_t r, int off) {
 // R^T[j][kk] = zeta sum_rho [R_t1c'; R_t2c'][rho][j] conj(Q_hat[rho][kk]).
 // Row rho of the stacked sons' R is the sum of one load from each son's
 // buffer, the other being out of range (zero); columns past the unit load as
-// zero too.  The sons' values are loaded two k-steps ahead and Q_hat one
-// step ahead, in rings of three register sets that are unrolled so that no
-// loaded register is copied.
+// zero too.  The sons' values are loaded kRing - 1 k-steps ahead and Q_hat
+// one step ahead, in rings of kRing register sets that are unrolled so that
+// no loaded register is copied.
 template <bool MX, int KT>
 __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
                                const UnitDev& u, double zeta, const ROp<MX>* Qs,
                                unsigned* s_rmax) {
   using OT = ROp<MX>;
   constexpr int esz = sizeof(OT);
+  constexpr int kRing = 5;
   int w = wave_id(), lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   const int r = it.r, k = it.k, k1 = s1.k, k2 = s2.k;
   const int nks = (r + 3) / 4;
@@ -1458,39 +1584,37 @@ __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemD
 #pragma unroll
       for (int t = 0; t < KT; ++t) acc[t].mac(v, q[t]);
     };
-    AP a0, a1, a2;
-    OT q0[KT], q1[KT], q2[KT];
+    // ring of kRing register sets: son values kRing - 1 steps ahead, Q_hat
+    // one step ahead
+    AP a[kRing];
+    OT q[kRing][KT];
     // drain the previous column group (stores, unused prefetches) so that the
     // wait counts inside the loop are exact
     __builtin_amdgcn_s_waitcnt(0);
-    lda(kq, a0);
-    __builtin_amdgcn_sched_barrier(0);
-    lda(4 + kq, a1);
-    __builtin_amdgcn_sched_barrier(0);
-    ldqs(kq, q0);
+#pragma unroll
+    for (int st = 0; st < kRing - 1; ++st) {
+      lda(4 * st + kq, a[st]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    ldqs(kq, q[0]);
     int rho0 = 0;
-    for (int n3 = nks / 3; n3 > 0; --n3, rho0 += 12) {
-      lda(rho0 + 8 + kq, a2);
-      ldqs(rho0 + 4 + kq, q1);
-      __builtin_amdgcn_sched_barrier(0);
-      mac(a0, q0);
-      __builtin_amdgcn_sched_barrier(0);
-      lda(rho0 + 12 + kq, a0);
-      ldqs(rho0 + 8 + kq, q2);
-      __builtin_amdgcn_sched_barrier(0);
-      mac(a1, q1);
-      __builtin_amdgcn_sched_barrier(0);
-      lda(rho0 + 16 + kq, a1);
-      ldqs(rho0 + 12 + kq, q0);
-      __builtin_amdgcn_sched_barrier(0);
-      mac(a2, q2);
-      __builtin_amdgcn_sched_barrier(0);
+    for (int n = nks / kRing; n > 0; --n, rho0 += 4 * kRing) {
+#pragma unroll
+      for (int st = 0; st < kRing; ++st) {
+        lda(rho0 + 4 * (st + kRing - 1) + kq, a[(st + kRing - 1) % kRing]);
+        ldqs(rho0 + 4 * (st + 1) + kq, q[(st + 1) % kRing]);
+        __builtin_amdgcn_sched_barrier(0);
+        mac(a[st], q[st]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
-    if (nks % 3 >= 1) {
-      ldqs(rho0 + 4 + kq, q1);
-      mac(a0, q0);
+#pragma unroll
+    for (int st = 0; st < kRing - 1; ++st) {
+      if (st < nks % kRing) {
+        ldqs(rho0 + 4 * (st + 1) + kq, q[(st + 1) % kRing]);
+        mac(a[st], q[st]);
+      }
     }
-    if (nks % 3 == 2) mac(a1, q1);
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
       int kk = 16 * t + row;
@@ -2139,6 +2263,26 @@ void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t ds
   if (count == 0) return;
   hipLaunchKernelGGL(k_copy_c, dim3(blocks_for(count, 256)), dim3(256), 0, st, src, src_off, dst,
                      dst_off, count);
+}
+
+void launch_project_stacked(int cls, const PTileDev* tiles, int64_t ntiles, const PBlkDev* blks,
+                            const double* omega, hipStream_t st) {
+  if (ntiles == 0) return;
+  dim3 grid((unsigned)((ntiles + 3) / 4));
+  switch (cls) {
+    case 0:
+      hipLaunchKernelGGL((k_project_stacked<1, kPstLast[0]>), grid, dim3(256), 0, st, tiles, ntiles,
+                         blks, omega);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_project_stacked<kPstLast[0] + 1, kPstLast[1]>), grid, dim3(256), 0, st,
+                         tiles, ntiles, blks, omega);
+      break;
+    default:
+      hipLaunchKernelGGL((k_project_stacked<kPstLast[1] + 1, 16>), grid, dim3(256), 0, st, tiles,
+                         ntiles, blks, omega);
+      break;
+  }
 }
 
 void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const double* omega,
