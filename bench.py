@@ -29,7 +29,7 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_INT8_MFMA = 5.0e15
 # HBM bytes per launch of k_gram_i8<0> on the default workload: FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 (1 GiB copy calibration), profiles/compress_sphere131072_mixed.md
-TRAFFIC_GRAM_I8_LEAF = (2 * 333405.8 + 184032.7) * 1024
+TRAFFIC_GRAM_I8_LEAF = (2 * 637277.3 + 154566.0) * 1024
 
 
 def log(*a):
@@ -141,7 +141,7 @@ def run_batch(args, dh2, torch, synth):
         "metric": METRIC, "value": flops / s_b / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": s_b * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if form == "mixed" else "f64", "data": "synthetic",
+        "dtype": "i8+f32+f64" if form == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "instances": count, "eps": eps, "leaf_size": 64,
                    "form": form, "surfaces": "sphere / rotated ellipsoid / cube surface",
                    "kappa": "sqrt(n)/5.66"},
@@ -260,8 +260,9 @@ def main():
                      "avg_launch_ms": st["t_gram_leaf"] / nl * 1e3,
                      "work_per_launch": work / nl},
         "roofline_projection": {"bound": "mfma",
-                                "kernel": "k_project_tiled (S_b = omega_b R|s W, "
-                                          + ("FP32" if head == "mixed" else "FP64") + " MFMA)",
+                                "kernel": ("k_project_stacked (S_b = omega_b R|s W, stacked "
+                                           "by W, FP32 4x4x1 MFMA)" if head == "mixed" else
+                                           "k_project_tiled (S_b = omega_b R|s W, FP64 MFMA)"),
                                 "achieved": ach_prj / 1e12, "peak": pk_prj / 1e12,
                                 "unit": "TFLOP/s", "frac": ach_prj / pk_prj},
         "compression_s": {f: res[f]["s"] for f in res},
