@@ -99,7 +99,7 @@ size_t cache_limit() {
       (void)hipGetLastError();
       tot = size_t(64) << 30;
     }
-    lim = tot / 2;
+    lim = tot / 10 * 8;
   }
   return lim;
 }
@@ -1154,8 +1154,8 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     std::lock_guard<std::mutex> lk(g_cache_mu);
     freeb += g_cached;  // blocks held in the cache are available to this call
   }
-  double budget = 0.4 * (double)freeb;
-  if (o.max_device_bytes > 0) budget = std::min(budget, 0.4 * (double)o.max_device_bytes);
+  double budget = 0.75 * (double)freeb;
+  if (o.max_device_bytes > 0) budget = std::min(budget, 0.75 * (double)o.max_device_bytes);
   int32_t nb = o.groups > 0 ? o.groups : (int32_t)std::ceil(peak / std::max(1.0, budget));
   nb = std::max(1, std::min(nb, std::max(1, ngroups)));
   M.nbatch = nb;
