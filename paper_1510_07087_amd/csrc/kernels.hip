@@ -134,7 +134,7 @@ __device__ __forceinline__ void sincos_mixed(double x, float& s, float& c) {
   pc = fmaf(pc, y2, 4.1666667e-02f);          // 1/4!
   pc = fmaf(pc, y2, -0.5f);                   // -1/2!
   float cy = fmaf(pc, y2, 1.0f);
-  int q = (int)((long long)n & 3);
+  int q = (int)n & 3;  // |n| < 2^31 for the phases that occur
   float ss = (q & 1) ? cy : sy, cc = (q & 1) ? sy : cy;
   s = (q & 2) ? -ss : ss;
   c = ((q + 1) & 2) ? -cc : cc;
@@ -1259,13 +1259,17 @@ __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw
 // Mixed form, Helmholtz: the same entry as complex FP32.
 __device__ __forceinline__ float2 gen_entry_mx(const GeomDev& g, const RowData& rw, double4 cc,
                                                int side) {
-  double f = rw.f * cc.w;
   double dx = rw.x - cc.x, dy = rw.y - cc.y, dz = rw.z - cc.z;
   double r2 = fmax(dx * dx + dy * dy + dz * dz, 1e-300);
-  double ri = rsqrt_nr(r2);
+  // 1/r: the hardware estimate (r2 is positive and finite, so no special
+  // cases) refined by one Newton step; r = r2 / r to full FP64 accuracy
+  double r0 = __builtin_amdgcn_rsq(r2);
+  double e = fma(-r2 * r0, r0, 1.0);
+  double ri = fma(0.5 * r0, e, r0);
   float sn, cs;
   sincos_mixed(g.kappa * (r2 * ri), sn, cs);
-  float a = (float)(f * ri);
+  // the amplitude only needs FP32
+  float a = (float)rw.f * (float)cc.w * (float)ri;
   return make_float2(a * cs, side == 0 ? a * sn : -a * sn);
 }
 
