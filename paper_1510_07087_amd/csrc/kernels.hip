@@ -203,22 +203,31 @@ __global__ __launch_bounds__(256) void k_block_norm(GeomDev g, const int64_t* t_
   // four row groups x 64 column lanes
   const int ty = wave_id(), tx = threadIdx.x & 63;
   double acc = 0.0;
-  for (int64_t i = to + ty; i < to + tl; i += 4) {
-    if constexpr (SRC == SRC_HELMHOLTZ) {
-      const double* xi = g.pts + 4 * i;
-      const double x0 = xi[0], x1 = xi[1], x2 = xi[2];
-      for (int64_t j = so + tx; j < so + sl; j += 64) {
-        const double* xj = g.pts + 4 * j;
-        double dx = x0 - xj[0], dy = x1 - xj[1], dz = x2 - xj[2];
-        double a = xj[3] * kInv4Pi;
-        acc += a * a / (dx * dx + dy * dy + dz * dz);
+  if constexpr (SRC == SRC_HELMHOLTZ) {
+    // the lane keeps its column point in registers; the wave's rows are
+    // wave-uniform (scalar loads); 1/r^2 is the hardware reciprocal refined
+    // by two Newton steps
+    for (int64_t j = so + tx; j < so + sl; j += 64) {
+      const double* xj = g.pts + 4 * j;
+      const double y0 = xj[0], y1 = xj[1], y2 = xj[2];
+      const double a = xj[3] * kInv4Pi, a2 = a * a;
+#pragma unroll 4
+      for (int64_t i = to + ty; i < to + tl; i += 4) {
+        const double* xi = g.pts + 4 * i;
+        double dx = xi[0] - y0, dy = xi[1] - y1, dz = xi[2] - y2;
+        double r2 = dx * dx + dy * dy + dz * dz;
+        double q = __builtin_amdgcn_rcp(r2);
+        q = fma(q, fma(-r2, q, 1.0), q);
+        q = fma(q, fma(-r2, q, 1.0), q);
+        acc = fma(a2, q, acc);
       }
-    } else {
+    }
+  } else {
+    for (int64_t i = to + ty; i < to + tl; i += 4)
       for (int64_t j = so + tx; j < so + sl; j += 64) {
         double2 z = dense_entry(g, i, j, 0);
         acc += z.x * z.x + z.y * z.y;
       }
-    }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
