@@ -720,21 +720,28 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       tr_.mark("gram", s, b, lv);
       launch_gram_reduce(S.d_items, d_litems, n, d_ubegin, d_units, partial, st);
       launch_check("gram reduce");
-      // factor launches by size class (LDS per workgroup follows the largest r)
+      // factor launches by size class: the LDS of a workgroup follows the
+      // largest r of its class, so small factors run more workgroups per CU
       {
-        std::vector<int32_t> fl[2];
-        int32_t rm[2] = {0, 0};
+        constexpr int kFacClasses = 4;
+        constexpr int32_t kFacLimit[kFacClasses - 1] = {32, 48, 64};
+        std::vector<int32_t> fl[kFacClasses];
+        int32_t rm[kFacClasses] = {0, 0, 0, 0};
         for (int32_t i = lo; i < hi; ++i) {
-          int c = S.items[i].r > 64 ? 1 : 0;
+          int c = 0;
+          while (c < kFacClasses - 1 && S.items[i].r > kFacLimit[c]) ++c;
           fl[c].push_back(i);
           rm[c] = std::max(rm[c], S.items[i].r);
         }
-        std::vector<int32_t> all(fl[0]);
-        all.insert(all.end(), fl[1].begin(), fl[1].end());
+        std::vector<int32_t> all;
+        for (int c = 0; c < kFacClasses; ++c) all.insert(all.end(), fl[c].begin(), fl[c].end());
         int32_t* d_fl = upload(mem, all, st);
-        launch_factor(S.d_items, d_fl, (int32_t)fl[0].size(), rm[0], M.eps, 60, d_status, st);
-        launch_factor(S.d_items, d_fl + fl[0].size(), (int32_t)fl[1].size(), rm[1], M.eps, 60,
-                      d_status, st);
+        int64_t off = 0;
+        for (int c = 0; c < kFacClasses; ++c) {
+          launch_factor(S.d_items, d_fl + off, (int32_t)fl[c].size(), rm[c], M.eps, 60, d_status,
+                        st);
+          off += (int64_t)fl[c].size();
+        }
         launch_check("factor");
         hip_check(hipStreamSynchronize(st), "factor sync");
         mem.release(d_fl);

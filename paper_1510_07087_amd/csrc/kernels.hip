@@ -1541,65 +1541,56 @@ __device__ __forceinline__ void rmax_flush(const ItemDev& it, const unsigned* s_
     if (s_rmax[kk]) atomicMax(reinterpret_cast<unsigned*>(it.rmax) + kk, s_rmax[kk]);
 }
 
-// Complex element at byte offset off of a buffer (zero past its end), as an
-// R-product operand.
-template <bool MX>
-__device__ __forceinline__ ROp<MX> rbload(__amdgpu_buffer_rsrc_t r, int off) {
-  if constexpr (MX)
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-  else
-    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-}
-
 // R^T of a non-leaf block row, one workgroup per unit (column range): the
 // four waves share Q_hat (in the compute precision, rows padded with zeros to
 // r + 8) in LDS and take 16-column groups in turn.
 // R^T[j][kk] = zeta sum_rho [R_t1c'; R_t2c'][rho][j] conj(Q_hat[rho][kk]).
-// Row rho of the stacked sons' R is the sum of one load from each son's
-// buffer, the other being out of range (zero); columns past the unit load as
-// zero too.  The sons' values are loaded kRing - 1 k-steps ahead and Q_hat
-// one step ahead, in rings of kRing register sets that are unrolled so that
-// no loaded register is copied.
+// Row rho of the stacked sons' R is one load from the son that holds it.
+// The sons' values are loaded kRing - 1 k-steps ahead and Q_hat one step
+// ahead, in rings of kRing register sets that are unrolled so that no loaded
+// register is copied.
 template <bool MX, int KT>
 __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
                                const UnitDev& u, double zeta, const ROp<MX>* Qs,
                                unsigned* s_rmax) {
   using OT = ROp<MX>;
-  constexpr int esz = sizeof(OT);
+  using S = typename std::conditional<MX, float, double>::type;
+  typedef S E2 __attribute__((ext_vector_type(2)));
+  using GP = const __attribute__((address_space(1))) E2*;
   constexpr int kRing = 5;
   int w = wave_id(), lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
-  const int r = it.r, k = it.k, k1 = s1.k, k2 = s2.k;
+  const int r = it.r, k = it.k, k1 = s1.k;
   const int nks = (r + 3) / 4;
   constexpr int ldq = 16 * KT;
   const int ncols = (int)u.ncols;
   const int64_t c0 = it.col_off + u.col_begin;
-  const int nb1 = ncols * k1 * esz, nb2 = ncols * k2 * esz;
-  const __amdgpu_buffer_rsrc_t rs1 = buf_rsrc((const char*)s1.R + c0 * k1 * esz, nb1);
-  const __amdgpu_buffer_rsrc_t rs2 = buf_rsrc((const char*)s2.R + c0 * k2 * esz, nb2);
-  struct AP {
-    OT x, y;
-  };
+  const OT* R1 = reinterpret_cast<const OT*>(s1.R) + c0 * k1;  // column j at R1[j * k1]
+  const OT* R2 = reinterpret_cast<const OT*>(s2.R) + c0 * s2.k;
   for (int j0 = 16 * w; j0 < ncols; j0 += 64) {
-    const int jl = j0 + row;
-    auto lda = [&](int rho, AP& a) {
-      a.x = rbload<MX>(rs1, rho < k1 ? (jl * k1 + rho) * esz : nb1);
-      a.y = rbload<MX>(rs2, (rho >= k1 && rho < r) ? (jl * k2 + rho - k1) * esz : nb2);
+    // one load per element: row rho of [R1; R2] in column j; columns past
+    // the unit and rows past r read a valid element instead (their products
+    // land in columns that are not stored, or meet zero rows of Q_hat)
+    const int jc = min(j0 + row, ncols - 1);
+    const OT* c1 = R1 + (int64_t)jc * k1;
+    const OT* c2 = R2 + (int64_t)jc * s2.k - k1;
+    auto lda = [&](int rho, OT& a) {
+      const int rc = min(rho, r - 1);
+      E2 v = ((GP)(rc < k1 ? c1 + rc : c2 + rc))[0];
+      a.x = v.x;
+      a.y = v.y;
     };
     auto ldqs = [&](int rho, OT* q) {
 #pragma unroll
       for (int t = 0; t < KT; ++t) q[t] = Qs[rho * ldq + 16 * t + row];
     };
     RAcc<MX> acc[KT];
-    auto mac = [&](const AP& a, const OT* q) {
-      OT v;
-      v.x = a.x.x + a.y.x;
-      v.y = a.x.y + a.y.y;
+    auto mac = [&](const OT& v, const OT* q) {
 #pragma unroll
       for (int t = 0; t < KT; ++t) acc[t].mac(v, q[t]);
     };
     // ring of kRing register sets: son values kRing - 1 steps ahead, Q_hat
     // one step ahead
-    AP a[kRing];
+    OT a[kRing];
     OT q[kRing][KT];
     // drain the previous column group (stores, unused prefetches) so that the
     // wait counts inside the loop are exact
