@@ -1040,8 +1040,10 @@ __global__ __launch_bounds__(128) void k_fwd_inner(const ItemDev* items, const i
 }
 
 // coupling: yh_i = sum over the item's blocks of S_b xh_partner (or S_b^* for
-// the adjoint, where S_b is kr x kc with the item on the column side)
-__global__ __launch_bounds__(128) void k_coupling(const ItemDev* items, int32_t nitems,
+// the adjoint, where S_b is kr x kc with the item on the column side).  One
+// wave per item, lane kk one coefficient; the terms of a block are loaded
+// four at a time so that several loads are in flight.
+__global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t nitems,
                                                   const int64_t* cbegin, const int32_t* cblock,
                                                   const int32_t* cpartner,
                                                   const double2* const* S_ptr,
@@ -1049,31 +1051,40 @@ __global__ __launch_bounds__(128) void k_coupling(const ItemDev* items, int32_t 
                                                   const int64_t* xh_off, const double2* xh,
                                                   const int64_t* yh_off, double2* yh,
                                                   int adjoint) {
-  int32_t i = blockIdx.x;
+  int32_t i = (int32_t)blockIdx.x * 4 + wave_id();
   if (i >= nitems) return;
-  int k = items[i].k;
-  for (int kk = threadIdx.x; kk < k; kk += blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int k = items[i].k;
+  for (int kk0 = 0; kk0 < k; kk0 += 64) {
+    const int kk = min(kk0 + lane, k - 1);
     double2 s = make_double2(0.0, 0.0);
+    auto add = [&](double2 a, double2 x, bool conj_a) {
+      double2 v = conj_a ? cmulc(a, x) : cmul(a, x);
+      s.x += v.x;
+      s.y += v.y;
+    };
     for (int64_t q = cbegin[i]; q < cbegin[i + 1]; ++q) {
-      int32_t b = cblock[q];
+      const int32_t b = cblock[q];
       const double2* Sb = S_ptr[b];
-      int kr = S_rows[b], kc = S_cols[b];
+      const int kr = S_rows[b], kc = S_cols[b];
       const double2* x = xh + xh_off[cpartner[q]];
-      if (!adjoint) {
-        for (int jj = 0; jj < kc; ++jj) {
-          double2 v = cmul(Sb[kk + (int64_t)jj * kr], x[jj]);
-          s.x += v.x;
-          s.y += v.y;
-        }
-      } else {
-        for (int jj = 0; jj < kr; ++jj) {
-          double2 v = cmulc(Sb[jj + (int64_t)kk * kr], x[jj]);
-          s.x += v.x;
-          s.y += v.y;
-        }
+      // op N: sum_jj S[kk, jj] x[jj]; adjoint: sum_jj conj(S[jj, kk]) x[jj]
+      const int n = adjoint ? kr : kc;
+      const int64_t st = adjoint ? 1 : kr;
+      const double2* a0 = adjoint ? Sb + (int64_t)kk * kr : Sb + kk;
+      int jj = 0;
+      for (; jj + 3 < n; jj += 4) {
+        double2 a_0 = a0[jj * st], a_1 = a0[(jj + 1) * st], a_2 = a0[(jj + 2) * st],
+                a_3 = a0[(jj + 3) * st];
+        double2 x0 = x[jj], x1 = x[jj + 1], x2 = x[jj + 2], x3 = x[jj + 3];
+        add(a_0, x0, adjoint);
+        add(a_1, x1, adjoint);
+        add(a_2, x2, adjoint);
+        add(a_3, x3, adjoint);
       }
+      for (; jj < n; ++jj) add(a0[jj * st], x[jj], adjoint);
     }
-    yh[yh_off[i] + kk] = s;
+    if (kk0 + lane < k) yh[yh_off[i] + kk0 + lane] = s;
   }
 }
 
@@ -1102,43 +1113,67 @@ __global__ __launch_bounds__(128) void k_bwd_inner(const ItemDev* items, const i
   }
 }
 
-// leaf rows: y|L = sum_c Q_Lc yh_Lc + near-field rows of L
-__global__ __launch_bounds__(128) void k_bwd_leaf(const ItemDev* items, const LeafDev* leaves,
+// leaf rows: y|L = sum_c Q_Lc yh_Lc + near-field rows of L.  One workgroup
+// of four waves per leaf, lane j one row of the leaf (leaves have at most 64
+// rows): the waves take the leaf's basis terms and near-field blocks in
+// turn, with four columns' loads in flight, and the partial sums are added
+// through LDS in wave order.
+__global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const LeafDev* leaves,
                                                   const NearRefDev* nref, const NearDev* nears,
                                                   const double2* nearv, const int64_t* yh_off,
                                                   const double2* yh, const double2* xp,
                                                   double2* yp, int adjoint) {
+  __shared__ double2 part[4][64];
   const LeafDev L = leaves[blockIdx.x];
-  for (int j = threadIdx.x; j < L.len; j += blockDim.x) {
+  const int w = wave_id(), lane = threadIdx.x & 63;
+  for (int j0 = 0; j0 < L.len; j0 += 64) {
+    const int j = min(j0 + lane, L.len - 1);
     double2 s = make_double2(0.0, 0.0);
-    for (int q = L.item_first; q < L.item_first + L.item_count; ++q) {
+    auto add = [&](double2 a, double2 x, bool conj_a) {
+      double2 v = conj_a ? cmulc(a, x) : cmul(a, x);
+      s.x += v.x;
+      s.y += v.y;
+    };
+    for (int q = L.item_first + w; q < L.item_first + L.item_count; q += 4) {
       const ItemDev& it = items[q];
-      for (int kk = 0; kk < it.k; ++kk) {
-        double2 v = cmul(it.Q[(int64_t)j * it.k + kk], yh[yh_off[q] + kk]);
-        s.x += v.x;
-        s.y += v.y;
-      }
+      const double2* Qr = it.Q + (int64_t)j * it.k;
+      const double2* y = yh + yh_off[q];
+      for (int kk = 0; kk < it.k; ++kk) add(Qr[kk], y[kk], false);
     }
-    for (int64_t q = L.near_begin; q < L.near_end; ++q) {
+    for (int64_t q = L.near_begin + w; q < L.near_end; q += 4) {
       const NearRefDev ref = nref[q];
       const NearDev nb = nears[ref.b];
-      int64_t row = ref.row0 + j;  // row of the block (column for the adjoint)
+      const int64_t row = ref.row0 + j;  // row of the block (column for the adjoint)
       const double2* B = nearv + nb.off;
-      if (!adjoint) {
-        for (int64_t c = 0; c < nb.s_len; ++c) {
-          double2 v = cmul(B[row + c * nb.t_len], xp[nb.s_off + c]);
-          s.x += v.x;
-          s.y += v.y;
-        }
-      } else {
-        for (int64_t c = 0; c < nb.t_len; ++c) {
-          double2 v = cmulc(B[c + row * nb.t_len], xp[nb.t_off + c]);
-          s.x += v.x;
-          s.y += v.y;
-        }
+      // op N: sum_c B[row, c] x[s_off + c]; adjoint: sum_c conj(B[c, row]) x[t_off + c]
+      const int64_t n = adjoint ? nb.t_len : nb.s_len;
+      const int64_t st = adjoint ? 1 : nb.t_len;
+      const double2* a0 = adjoint ? B + row * nb.t_len : B + row;
+      const double2* x = xp + (adjoint ? nb.t_off : nb.s_off);
+      int64_t c = 0;
+      for (; c + 3 < n; c += 4) {
+        double2 a_0 = a0[c * st], a_1 = a0[(c + 1) * st], a_2 = a0[(c + 2) * st],
+                a_3 = a0[(c + 3) * st];
+        double2 x0 = x[c], x1 = x[c + 1], x2 = x[c + 2], x3 = x[c + 3];
+        add(a_0, x0, adjoint);
+        add(a_1, x1, adjoint);
+        add(a_2, x2, adjoint);
+        add(a_3, x3, adjoint);
       }
+      for (; c < n; ++c) add(a0[c * st], x[c], adjoint);
     }
-    yp[L.row_off + j] = s;
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j0 + lane < L.len) {
+      double2 t = part[0][lane];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        t.x += part[q][lane].x;
+        t.y += part[q][lane].y;
+      }
+      yp[L.row_off + j0 + lane] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -2381,7 +2416,7 @@ void launch_coupling(const ItemDev* items, int32_t nitems, const int64_t* cbegin
                      const double2* xh, const int64_t* yh_off, double2* yh, int adjoint,
                      hipStream_t st) {
   if (nitems == 0) return;
-  hipLaunchKernelGGL(k_coupling, dim3(nitems), dim3(128), 0, st, items, nitems, cbegin, cblock,
+  hipLaunchKernelGGL(k_coupling, dim3((nitems + 3) / 4), dim3(256), 0, st, items, nitems, cbegin, cblock,
                      cpartner, S_ptr, S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint);
 }
 void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
@@ -2396,7 +2431,7 @@ void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleave
                      const int64_t* yh_off, const double2* yh, const double2* xp, double2* yp,
                      int adjoint, hipStream_t st) {
   if (nleaves == 0) return;
-  hipLaunchKernelGGL(k_bwd_leaf, dim3(nleaves), dim3(128), 0, st, items, leaves, nref, nears,
+  hipLaunchKernelGGL(k_bwd_leaf, dim3(nleaves), dim3(256), 0, st, items, leaves, nref, nears,
                      nearv, yh_off, yh, xp, yp, adjoint);
 }
 void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
