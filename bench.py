@@ -151,6 +151,52 @@ def run_batch(args, dh2, torch, synth):
     print(json.dumps(out), flush=True)
 
 
+def run_matvec(args, dh2, torch, synth, blocks, w, eps, leaf, kappa, n, form):
+    """Matvec timing: one compression (untimed), then y = G~x and y = G~^*x on
+    one right-hand side, each timed over `steps` products after `warmup`.  The
+    representation (bases, transfer matrices, coupling matrices, near field)
+    is read once per product: its size over the product time is the HBM rate."""
+    prec = dh2.FP64 if form == "fp64" else dh2.MIXED
+    o = dh2.opts(leaf_size=leaf, precision=prec, groups=args.groups)
+    m = dh2.compress_helmholtz(blocks, w, eps, o)
+    torch.cuda.synchronize()
+    st = dh2.stats(m)
+    rep_bytes = st["mem_bytes"]
+    x = torch.from_numpy(synth.complex_gaussian(n, 6)).to("cuda")
+    y = torch.empty_like(x)
+    ms = {}
+    for op in ("N", "C"):
+        for _ in range(args.warmup):
+            dh2.matvec(m, op, x, y)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(args.steps):
+            dh2.matvec(m, op, x, y)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps * 1e3
+        ms[op] = ev0.elapsed_time(ev1) / args.steps
+        log(f"[bench] matvec {op}: {ms[op]:.3f} ms per product (wall {wall:.3f} ms), "
+            f"representation {rep_bytes / 1e9:.2f} GB")
+    ach = rep_bytes / (ms["N"] * 1e-3) / 1e9
+    out = {
+        "metric": "matvec ms, y = G~x with the compressed representation, n=%d kappa=%g" % (n, kappa),
+        "value": ms["N"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms["N"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "kappa": kappa, "leaf_size": leaf,
+                   "eps": eps, "form": form, "nrhs": 1},
+        "roofline": {"bound": "hbm", "kernel": "matvec (representation read once per product)",
+                     "achieved": ach, "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
+                     "traffic": None},
+        "adjoint_ms": ms["C"],
+        "representation_bytes": rep_bytes,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +212,9 @@ def main():
                     help="HBM bytes per launch of the roofline kernel from the counter runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter scale calibration)")
+    ap.add_argument("--mode", choices=("compress", "matvec"), default="compress",
+                    help="compress (default): the compression step; matvec: y = G~x and "
+                         "y = G~^*x with the compressed representation of the first form")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path; "
@@ -201,6 +250,9 @@ def main():
     log(f"[bench] host plan {t_plan:.2f} s: {binfo}")
 
     forms = [f for f in args.forms.split(",") if f]
+    if args.mode == "matvec":
+        run_matvec(args, dh2, torch, synth, blocks, w, eps, leaf, kappa, n, forms[0])
+        return
     res = {}
     for form in forms:
         m, st, times = run_form(dh2, torch, blocks, w, eps, leaf, form, args.steps, args.warmup,
