@@ -1405,70 +1405,101 @@ __global__ __launch_bounds__(256) void k_gram_leaf_w(GeomDev g, const ItemDev* i
 }
 
 // Row rho of G_hat_tc = zeta [R_t1c' ; R_t2c'] at column j (0 outside).
-template <bool MX>
-__device__ __forceinline__ double2 ghat(const ItemDev& s1, const ItemDev& s2, int64_t j, int rho,
-                                        int r, double zeta) {
-  if (rho >= r) return make_double2(0.0, 0.0);
-  double2 z = rho < s1.k ? rload<MX>(s1.R, j * s1.k + rho) : rload<MX>(s2.R, j * s2.k + (rho - s1.k));
-  return make_double2(z.x * zeta, z.y * zeta);
-}
-
 // Gram of a non-leaf block row, one unit (column range x tile block) per wave.
-// The wave loads the rows of its tiles for 4 columns per k-step (software
-// pipelined one k-step ahead) and accumulates the tile pairs of its block.
+// Each lane's row of every tile comes from one son, so its source pointer
+// and stride are fixed for the unit; loads are unconditional (rows past r
+// read row r - 1 and only feed Gram rows and columns that are not kept;
+// columns past the unit are clamped and masked to zero at use), four columns
+// per k-step, two k-steps ahead in an unrolled ring of three register sets.
+// zeta^2 is applied to the finished tiles.
 template <bool MX, int NA, int NB, bool DIAG>
 __device__ void gram_inner_wave(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
                                 const UnitDev& u, double zeta, double2* out) {
   constexpr int NP = DIAG ? NA * (NA + 1) / 2 : NA * NB;
   constexpr int NL = DIAG ? 0 : NB;
+  constexpr int NT = NA + NL;
+  using Sc = typename std::conditional<MX, float, double>::type;
+  typedef Sc E2 __attribute__((ext_vector_type(2)));
+  using GP = const __attribute__((address_space(1))) E2*;
+  using OT = typename std::conditional<MX, float2, double2>::type;
   int lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
-  int r = it.r;
+  const int r = it.r, k1 = s1.k;
+  const int ncols = (int)u.ncols;
+  const int64_t c0 = it.col_off + u.col_begin;
+  GP src[NT];
+  int ld[NT];
+#pragma unroll
+  for (int T = 0; T < NT; ++T) {
+    int rho = 16 * (T < NA ? u.a0 + T : u.b0 + (T - NA)) + row;
+    int rc = min(rho, r - 1);
+    if (rc < k1) {
+      src[T] = (GP)(reinterpret_cast<const OT*>(s1.R) + c0 * k1 + rc);
+      ld[T] = k1;
+    } else {
+      src[T] = (GP)(reinterpret_cast<const OT*>(s2.R) + c0 * s2.k + (rc - k1));
+      ld[T] = s2.k;
+    }
+  }
   dvec4 acr[NP], aci[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     acr[p] = dvec4{0, 0, 0, 0};
     aci[p] = dvec4{0, 0, 0, 0};
   }
-  int64_t jb = it.col_off + u.col_begin;
-  int64_t nc4 = (u.ncols + 3) & ~int64_t(3);
-  double2 ca[NA], cb[NL > 0 ? NL : 1];
-  auto load = [&](int64_t c, double2* a, double2* b) {
-    bool cv = c < u.ncols;
-    int64_t j = jb + c;
+  auto load = [&](int c, E2* v) {
+    const int cc = min(c, ncols - 1);
 #pragma unroll
-    for (int I = 0; I < NA; ++I)
-      a[I] = cv ? ghat<MX>(s1, s2, j, 16 * (u.a0 + I) + row, r, zeta) : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int J = 0; J < NL; ++J)
-      b[J] = cv ? ghat<MX>(s1, s2, j, 16 * (u.b0 + J) + row, r, zeta) : make_double2(0.0, 0.0);
+    for (int T = 0; T < NT; ++T) v[T] = src[T][(int64_t)cc * ld[T]];
   };
-  load(kq, ca, cb);
-  for (int64_t c = kq; c < nc4; c += 4) {
-    double2 na_[NA], nb_[NL > 0 ? NL : 1];
-    load(c + 4, na_, nb_);
+  auto step = [&](int c, const E2* v) {
+    const bool ok = c < ncols;
+    double2 x[NT];
+#pragma unroll
+    for (int T = 0; T < NT; ++T) x[T] = ok ? make_double2(v[T].x, v[T].y) : make_double2(0.0, 0.0);
     int p = 0;
 #pragma unroll
     for (int I = 0; I < NA; ++I) {
 #pragma unroll
       for (int J = 0; J < (DIAG ? I + 1 : NB); ++J) {
-        double2 x = ca[I];
-        double2 y = DIAG ? ca[J] : cb[J];
-        acr[p] = mfma_f64(x.x, y.x, acr[p]);
-        acr[p] = mfma_f64(x.y, y.y, acr[p]);
-        aci[p] = mfma_f64(x.y, y.x, aci[p]);
-        aci[p] = mfma_f64(-x.x, y.y, aci[p]);
+        double2 xa = x[I];
+        double2 yb = DIAG ? x[J] : x[NA + J];
+        acr[p] = mfma_f64(xa.x, yb.x, acr[p]);
+        acr[p] = mfma_f64(xa.y, yb.y, acr[p]);
+        aci[p] = mfma_f64(xa.y, yb.x, aci[p]);
+        aci[p] = mfma_f64(-xa.x, yb.y, aci[p]);
         ++p;
       }
     }
-#pragma unroll
-    for (int I = 0; I < NA; ++I) ca[I] = na_[I];
-#pragma unroll
-    for (int J = 0; J < NL; ++J) cb[J] = nb_[J];
+  };
+  E2 v0[NT], v1[NT], v2[NT];
+  load(kq, v0);
+  __builtin_amdgcn_sched_barrier(0);
+  load(4 + kq, v1);
+  __builtin_amdgcn_sched_barrier(0);
+  const int nst = (ncols + 3) / 4;
+  int c = kq;
+  for (int n = nst / 3; n > 0; --n, c += 12) {
+    load(c + 8, v2);
+    __builtin_amdgcn_sched_barrier(0);
+    step(c, v0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(c + 12, v0);
+    __builtin_amdgcn_sched_barrier(0);
+    step(c + 4, v1);
+    __builtin_amdgcn_sched_barrier(0);
+    load(c + 16, v1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(c + 8, v2);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (nst % 3 >= 1) step(c, v0);
+  if (nst % 3 == 2) step(c + 4, v1);
+  const double z2 = zeta * zeta;
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[(p * 4 + v) * 64 + lane] = make_double2(acr[p][v], aci[p][v]);
+    for (int v = 0; v < 4; ++v)
+      out[(p * 4 + v) * 64 + lane] = make_double2(acr[p][v] * z2, aci[p][v] * z2);
 }
 
 template <bool MX>
