@@ -29,7 +29,7 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_INT8_MFMA = 5.0e15
 # HBM bytes per launch of k_gram_i8<0> on the default workload: FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 (1 GiB copy calibration), profiles/compress_sphere131072_mixed.md
-TRAFFIC_GRAM_I8_LEAF = (2 * 637277.3 + 154566.0) * 1024
+TRAFFIC_GRAM_I8_LEAF = (2 * 1274170.2 + 305164.0) * 1024
 
 
 def log(*a):
