@@ -721,7 +721,9 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       launch_gram_reduce(S.d_items, d_litems, n, d_ubegin, d_units, partial, st);
       launch_check("gram reduce");
       // factor launches by size class: the LDS of a workgroup follows the
-      // largest r of its class, so small factors run more workgroups per CU
+      // largest r of its class, so small factors run more workgroups per CU.
+      // A launch lasts at least as long as its slowest item, so a class too
+      // small to fill the device joins the next larger one.
       {
         constexpr int kFacClasses = 4;
         constexpr int32_t kFacLimit[kFacClasses - 1] = {32, 48, 64};
@@ -733,6 +735,12 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           fl[c].push_back(i);
           rm[c] = std::max(rm[c], S.items[i].r);
         }
+        for (int c = 0; c + 1 < kFacClasses; ++c)
+          if (!fl[c].empty() && fl[c].size() < 2048) {
+            fl[c + 1].insert(fl[c + 1].end(), fl[c].begin(), fl[c].end());
+            rm[c + 1] = std::max(rm[c + 1], rm[c]);
+            fl[c].clear();
+          }
         std::vector<int32_t> all;
         for (int c = 0; c < kFacClasses; ++c) all.insert(all.end(), fl[c].begin(), fl[c].end());
         int32_t* d_fl = upload(mem, all, st);

@@ -1312,8 +1312,9 @@ __device__ __forceinline__ float2 gen_entry_mx(const GeomDev& g, const RowData& 
   double ri = fma(0.5 * r0, e, r0);
   float sn, cs;
   sincos_mixed(g.kappa * (r2 * ri), sn, cs);
-  // the amplitude only needs FP32
-  float a = (float)rw.f * (float)cc.w * (float)ri;
+  // the amplitude only needs FP32 (1/r is capped so that a padding factor 0
+  // meets a finite value even where the distance was clamped)
+  float a = (float)rw.f * (float)cc.w * fminf((float)ri, 3.0e38f);
   return make_float2(a * cs, side == 0 ? a * sn : -a * sn);
 }
 
