@@ -359,14 +359,20 @@ static std::shared_ptr<SidePlan> build_side_plan(const BlocksData& B, int s, int
   S.items0.assign(ni, ItemDev{});
   S.t.resize(ni);
   S.c.resize(ni);
+  S.ninh.resize(ni);
   S.ent_col.assign(cs.ent.size(), 0);
   // per external item: N and entry column starts
-  std::vector<int64_t> Next(ni, 0);
+  std::vector<int64_t> Next(ni, 0), Ninh(ni, 0);
   for (int32_t e = 0; e < ni; ++e) {
     int64_t col = 0;
+    bool own = false;
     for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) {
       S.ent_col[q] = col;
       col += tr.size[cs.ent[q].s];
+      // inherited entries come first, the item's own blocks last
+      if (cs.ent[q].d == 0) own = true;
+      else if (own) fail(DH2_EDEVICE, "internal: column set out of order");
+      else Ninh[e] = col;
     }
     Next[e] = col;
   }
@@ -397,6 +403,7 @@ static std::shared_ptr<SidePlan> build_side_plan(const BlocksData& B, int s, int
     ItemDev& it = S.items0[i];
     S.t[i] = t;
     S.c[i] = c;
+    S.ninh[i] = Ninh[e];
     it.row_off = tr.off[t];
     it.N = Next[e];
     it.m = (int32_t)tr.size[t];
@@ -441,8 +448,9 @@ static std::shared_ptr<SidePlan> build_side_plan(const BlocksData& B, int s, int
       for (int q = 0; q < 2; ++q) {
         int32_t so = S.ext2int[son_ext[2 * (size_t)i + q]];
         S.items0[i].son[q] = so;
-        // the kernels read columns col_off .. col_off+N of the son's R
-        if (S.items0[i].col_off + S.items0[i].N > S.items0[so].N ||
+        // the kernels read columns col_off .. col_off+N of the son's R, all
+        // of them inherited ones
+        if (S.items0[i].col_off + S.items0[i].N > S.ninh[so] ||
             S.items0[so].level != S.items0[i].level + 1)
           fail(DH2_EDEVICE, "internal: inconsistent column sets");
       }
@@ -786,7 +794,9 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       if (mbytes) hip_check(hipMemsetAsync(Rarena + rbytes, 0, mbytes, st), "row maxima clear");
       copy_to(S.d_items + lo, S.items.data() + lo, n, st);
       // R-product units: one workgroup per 1024 columns; leaf units first,
-      // then non-leaf units grouped by ceil(k / 16)
+      // then non-leaf units grouped by ceil(k / 16).  The father reads only
+      // the inherited columns of R; the own-block columns are kept for the
+      // projection of the row sweep and not formed in the column sweep.
       std::vector<UnitDev> ru;
       int64_t nleafr = 0;
       std::vector<std::array<int64_t, 3>> rlaunch;  // kt, count, lds bytes
@@ -799,15 +809,16 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           if (it.k == 0) continue;
           int kt = (it.k + 15) / 16;
           if (!it.leaf) lds_kt[kt] = std::max(lds_kt[kt], rprod_inner_lds(mixed, it.r, it.k));
-          for (int64_t c0 = 0; c0 < it.N; c0 += rwidth) {
+          const int64_t nr = s == 0 ? it.N : S.P->ninh[i];
+          for (int64_t c0 = 0; c0 < nr; c0 += rwidth) {
             UnitDev u{};
             u.item = i;
             u.col_begin = c0;
-            u.ncols = std::min(rwidth, it.N - c0);
+            u.ncols = std::min(rwidth, nr - c0);
             (it.leaf ? ru : inner_by_kt[kt]).push_back(u);
           }
-          ss.flops_rprod += 8.0 * it.k * (double)it.r * (double)it.N;
-          if (it.leaf) ss.flops_rprod_leaf += 8.0 * it.k * (double)it.r * (double)it.N;
+          ss.flops_rprod += 8.0 * it.k * (double)it.r * (double)nr;
+          if (it.leaf) ss.flops_rprod_leaf += 8.0 * it.k * (double)it.r * (double)nr;
         }
         nleafr = (int64_t)ru.size();
         for (int kt = 1; kt <= 8; ++kt) {

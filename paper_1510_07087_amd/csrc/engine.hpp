@@ -73,6 +73,9 @@ struct SidePlan {
   std::vector<int32_t> t, c;        // per internal item
   std::vector<EntDev> ents;         // leaf column-set entries (scale filled per matrix)
   std::vector<int64_t> ent_col;     // per column-set entry: column start inside its item
+  // per internal item: columns inherited from the father's sets (the first
+  // ninh columns; the item's own blocks follow them)
+  std::vector<int64_t> ninh;
   // (batch, level) ranges of internal items
   std::vector<std::vector<std::pair<int32_t, int32_t>>> range;  // [batch][level] -> [lo,hi)
 };
