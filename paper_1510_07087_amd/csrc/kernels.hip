@@ -866,8 +866,8 @@ __device__ __forceinline__ void pst_tile(const PTileDev& t, const PBlkDev* blks,
 
 // Tiles of one launch have ceil(ks / 4) in [NC0, NC1]; each wave dispatches
 // on its own tile's column-group count.
-template <int NC0, int NC1>
-__global__ __launch_bounds__(256) void k_project_stacked(const PTileDev* tiles, int64_t ntiles,
+template <int NC0, int NC1, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_project_stacked(const PTileDev* tiles, int64_t ntiles,
                                                          const PBlkDev* blks,
                                                          const double* omega) {
   // XCD-aware order, as in k_project_tiled
@@ -1711,7 +1711,7 @@ __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemD
 
 // every unit of one launch has ceil(k / 16) = KT
 template <bool MX, int KT>
-__global__ __launch_bounds__(256) void k_rprod_inner_g(const ItemDev* items, const UnitDev* units,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX && KT <= 3 ? 8 - 2 * KT + 2 : 1))) void k_rprod_inner_g(const ItemDev* items, const UnitDev* units,
                                                        double zeta) {
   extern __shared__ __align__(16) char rlds[];
   __shared__ unsigned s_rmax[kMaxR];
@@ -1793,7 +1793,7 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
 }
 
 template <int SRC, bool MX>
-__global__ __launch_bounds__(256) void k_rprod_leaf_w(GeomDev g, const ItemDev* items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX ? 4 : 1))) void k_rprod_leaf_w(GeomDev g, const ItemDev* items,
                                                       const EntDev* ents, const UnitDev* units,
                                                       int side) {
   __shared__ ROp<MX> Qs[68 * 64];   // (r + 4) x (16 KT), zero padded rows past r
@@ -2342,15 +2342,15 @@ void launch_project_stacked(int cls, const PTileDev* tiles, int64_t ntiles, cons
   dim3 grid((unsigned)((ntiles + 3) / 4));
   switch (cls) {
     case 0:
-      hipLaunchKernelGGL((k_project_stacked<1, kPstLast[0]>), grid, dim3(256), 0, st, tiles, ntiles,
+      hipLaunchKernelGGL((k_project_stacked<1, kPstLast[0], 4>), grid, dim3(256), 0, st, tiles, ntiles,
                          blks, omega);
       break;
     case 1:
-      hipLaunchKernelGGL((k_project_stacked<kPstLast[0] + 1, kPstLast[1]>), grid, dim3(256), 0, st,
+      hipLaunchKernelGGL((k_project_stacked<kPstLast[0] + 1, kPstLast[1], 3>), grid, dim3(256), 0, st,
                          tiles, ntiles, blks, omega);
       break;
     default:
-      hipLaunchKernelGGL((k_project_stacked<kPstLast[1] + 1, 16>), grid, dim3(256), 0, st, tiles,
+      hipLaunchKernelGGL((k_project_stacked<kPstLast[1] + 1, 16, 2>), grid, dim3(256), 0, st, tiles,
                          ntiles, blks, omega);
       break;
   }
