@@ -126,3 +126,43 @@ def test_invalid_arguments():
     with pytest.raises(dh2.DH2Error) as e:
         dh2.tree_build(dup, 1.0, o)
     assert e.value.code == -1 and "coincident" in str(e.value)
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_inherited_columns_form_a_prefix(side):
+    """The father's sets F_tc, taken in the father's direction order, are the
+    leading columns of the son's set for sd(c), and the son's own blocks come
+    last (the R recursion of the paper's transfer step reads only inherited
+    columns, so the column sweep forms R over that prefix alone)."""
+    pts, _ = synth.fibonacci_sphere(8192)
+    o = dh2.opts(leaf_size=64)
+    t = dh2.tree_build(pts, 16.0, o)
+    te = dh2.tree_export(t)
+    b = dh2.blocks_build(t, o)
+    cs = dh2.blocks_colsets(b, side)
+    beg = cs["item_begin"]
+    ent = list(zip(cs["ent_b"], cs["ent_s"], cs["ent_d"]))
+    item = {(int(t_), int(c)): i for i, (t_, c) in enumerate(zip(cs["item_t"], cs["item_c"]))}
+    father = {}
+    for f, (s1, s2) in enumerate(zip(te["son1"], te["son2"])):
+        if s1 >= 0:
+            father[int(s1)] = f
+            father[int(s2)] = f
+    checked = 0
+    for (t_, c), i in item.items():
+        es = ent[beg[i]:beg[i + 1]]
+        d = [e[2] for e in es]
+        nown = sum(1 for x in d if x == 0)
+        assert all(x > 0 for x in d[:len(d) - nown]) and all(x == 0 for x in d[len(d) - nown:])
+        if t_ not in father:
+            continue
+        f = father[t_]
+        _, sd = dh2.tree_directions(t, int(te["level"][f]))
+        expect = []
+        for cf in sorted(c2 for (t2, c2) in item if t2 == f):
+            if sd[cf] == c:
+                j = item[(f, cf)]
+                expect += [(e[0], e[1], e[2] + 1) for e in ent[beg[j]:beg[j + 1]]]
+        assert es[:len(es) - nown] == expect
+        checked += 1
+    assert checked > 0
