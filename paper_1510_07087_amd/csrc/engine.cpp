@@ -128,14 +128,84 @@ void release_cached_memory() {
   trim_cache_locked(0);
 }
 
+// pinned staging buffers, reused across compressions
+constexpr size_t kPinBytes = size_t(32) << 20;
+static std::mutex g_pin_mu;
+static std::vector<char*> g_pin_pool;
+
 DevMem::~DevMem() {
+  // an error may have left work queued that still uses released blocks or
+  // the staging buffer
+  if (pin_ || !released_.empty()) (void)hipDeviceSynchronize();
+  if (pin_) {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_pool.push_back(pin_);
+    pin_ = nullptr;
+  }
   std::lock_guard<std::mutex> lk(g_cache_mu);
   for (auto& pr : live_) {
     g_cache.push_back({pr.first, pr.second});
     g_cached += pr.second;
   }
   live_.clear();
+  for (auto& pr : released_) {
+    g_cache.push_back({pr.first, pr.second});
+    g_cached += pr.second;
+  }
+  released_.clear();
   trim_cache_locked(cache_limit());
+}
+
+void DevMem::flush_released() {
+  if (released_.empty()) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& pr : released_) {
+    g_cache.push_back({pr.first, pr.second});
+    g_cached += pr.second;
+  }
+  released_.clear();
+  trim_cache_locked(cache_limit());
+}
+
+void DevMem::sync(hipStream_t st, const char* what) {
+  hip_check(hipStreamSynchronize(st), what);
+  pin_off_ = 0;
+  flush_released();
+}
+
+void DevMem::upload(void* d, const void* h, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return;
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (!pin_ || need > kPinBytes) {
+    hip_check(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st), "upload");
+    sync(st, "upload sync");
+    return;
+  }
+  if (pin_off_ + need > kPinBytes) sync(st, "staging sync");  // earlier transfers done
+  std::memcpy(pin_ + pin_off_, h, bytes);
+  hip_check(hipMemcpyAsync(d, pin_ + pin_off_, bytes, hipMemcpyHostToDevice, st), "upload");
+  pin_off_ += need;
+}
+
+void DevMem::begin_staging() {
+  if (pin_) return;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (!g_pin_pool.empty()) {
+      pin_ = g_pin_pool.back();
+      g_pin_pool.pop_back();
+    }
+  }
+  if (!pin_) hip_check(hipHostMalloc((void**)&pin_, kPinBytes, hipHostMallocDefault), "hipHostMalloc");
+  pin_off_ = 0;
+}
+
+void DevMem::end_staging(hipStream_t st) {
+  sync(st, "staging end");
+  if (!pin_) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_pool.push_back(pin_);
+  pin_ = nullptr;
 }
 
 void* DevMem::alloc(size_t bytes) {
@@ -169,6 +239,11 @@ void* DevMem::alloc(size_t bytes) {
       size_t fr = 0, tot = 0;
       if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
         const size_t margin = size_t(2) << 30;
+        if (fr < bytes + margin && !released_.empty()) {
+          hip_check(hipDeviceSynchronize(), "release sync");
+          pin_off_ = 0;
+          flush_released();
+        }
         std::lock_guard<std::mutex> lk(g_cache_mu);
         while (fr < bytes + margin && !g_cache.empty()) {
           size_t big = g_cache_largest_locked();
@@ -182,6 +257,13 @@ void* DevMem::alloc(size_t bytes) {
     hipError_t e = hipMalloc(&p, bytes);
     while (e != hipSuccess) {
       (void)hipGetLastError();
+      // blocks released since the last sync: wait for the device, then they
+      // are free for anyone
+      if (!released_.empty()) {
+        hip_check(hipDeviceSynchronize(), "release sync");
+        pin_off_ = 0;
+        flush_released();
+      }
       // no room: take the smallest cached block that is large enough, however
       // large, else return the largest cached block to the driver and retry
       // (freeing the whole cache would make every later level allocate from
@@ -221,13 +303,10 @@ void DevMem::release(void* p) {
   if (!p) return;
   for (size_t i = live_.size(); i-- > 0;) {
     if (live_[i].first == p) {
-      std::lock_guard<std::mutex> lk(g_cache_mu);
-      g_cache.push_back({p, live_[i].second});
-      g_cached += live_[i].second;
+      released_.push_back(live_[i]);
       used_ -= (int64_t)live_[i].second;
       live_[i] = live_.back();
       live_.pop_back();
-      trim_cache_locked(cache_limit());
       return;
     }
   }
@@ -236,19 +315,13 @@ void DevMem::release(void* p) {
 template <class T>
 static T* upload(DevMem& mem, const std::vector<T>& v, hipStream_t st) {
   T* d = (T*)mem.alloc(v.size() * sizeof(T));
-  if (!v.empty()) {
-    hip_check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st),
-              "upload");
-    hip_check(hipStreamSynchronize(st), "upload sync");
-  }
+  mem.upload(d, v.data(), v.size() * sizeof(T), st);
   return d;
 }
 
 template <class T>
-static void copy_to(T* d, const T* h, size_t n, hipStream_t st) {
-  if (n == 0) return;
-  hip_check(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, st), "copy_to");
-  hip_check(hipStreamSynchronize(st), "copy_to sync");
+static void copy_to(DevMem& mem, T* d, const T* h, size_t n, hipStream_t st) {
+  mem.upload(d, h, n * sizeof(T), st);
 }
 
 template <class T>
@@ -531,25 +604,34 @@ static std::shared_ptr<PlanCache> plan_cache(const BlocksData& B, int32_t nb,
 // ---------------------------------------------------------------------------
 // compression
 // ---------------------------------------------------------------------------
+// Event-timed phases: each start/stop records an event on the stream; the
+// times are read once, after the last stop has completed, so that timing
+// adds no wait to the sweep.
 struct PhaseTimer {
-  hipEvent_t a, b;
   hipStream_t st;
-  double acc = 0;
-  explicit PhaseTimer(hipStream_t s) : st(s) {
-    hip_check(hipEventCreate(&a), "event");
-    hip_check(hipEventCreate(&b), "event");
-  }
+  std::vector<hipEvent_t> ev;  // start, stop, start, stop, ...
+  explicit PhaseTimer(hipStream_t s) : st(s) {}
   ~PhaseTimer() {
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
-  void start() { hip_check(hipEventRecord(a, st), "event record"); }
-  void stop() {
-    hip_check(hipEventRecord(b, st), "event record");
-    hip_check(hipEventSynchronize(b), "event sync");
-    float ms = 0;
-    hip_check(hipEventElapsedTime(&ms, a, b), "event time");
-    acc += ms * 1e-3;
+  void record() {
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "event");
+    ev.push_back(e);
+    hip_check(hipEventRecord(e, st), "event record");
+  }
+  void start() { record(); }
+  void stop() { record(); }
+  double total() {
+    double acc = 0;
+    if (ev.empty()) return acc;
+    hip_check(hipEventSynchronize(ev.back()), "event sync");
+    for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+      float ms = 0;
+      hip_check(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "event time");
+      acc += ms * 1e-3;
+    }
+    return acc;
   }
 };
 
@@ -632,7 +714,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           o1 += it.r;
         }
       }
-      copy_to(S.d_items + lo, S.items.data() + lo, n, st);
+      copy_to(mem, S.d_items + lo, S.items.data() + lo, n, st);
       int32_t* d_leaf_ids = upload(mem, leaf_ids, st);
       launch_leaf_cols(M.src, g, S.d_items, d_leaf_ids, (int32_t)leaf_ids.size(), S.d_ents, s, st);
       launch_check("leaf columns");
@@ -759,7 +841,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           off += (int64_t)fl[c].size();
         }
         launch_check("factor");
-        hip_check(hipStreamSynchronize(st), "factor sync");
+        mem.sync(st, "factor sync");
         mem.release(d_fl);
       }
       copy_from(S.items.data() + lo, S.d_items + lo, n, st);
@@ -792,7 +874,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         }
       }
       if (mbytes) hip_check(hipMemsetAsync(Rarena + rbytes, 0, mbytes, st), "row maxima clear");
-      copy_to(S.d_items + lo, S.items.data() + lo, n, st);
+      copy_to(mem, S.d_items + lo, S.items.data() + lo, n, st);
       // R-product units: one workgroup per 1024 columns; leaf units first,
       // then non-leaf units grouped by ceil(k / 16).  The father reads only
       // the inherited columns of R; the own-block columns are kept for the
@@ -995,7 +1077,8 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         mem.release(d_pblk);
         mem.release(d_ptile);
       }
-      hip_check(hipStreamSynchronize(st), "level sync");
+      // no wait here: the next level's host work overlaps this level's
+      // kernels, and the released blocks are reused only after a sync
       mem.release(d_units);
       mem.release(d_litems);
       mem.release(d_ubegin);
@@ -1011,9 +1094,9 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
     for (int32_t i = 0; i < S.nitems; ++i) S.items[i].R = nullptr;
   }
   mem.release(partial);
-  ss.t_gram += tg.acc;
-  ss.t_prj += tp.acc;
-  ss.t_gram_leaf += tgl.acc;
+  ss.t_gram += tg.total();
+  ss.t_prj += tp.total();
+  ss.t_gram_leaf += tgl.total();
 }
 
 // expanded column bases, level by level from the leaves
@@ -1061,7 +1144,7 @@ static void expand_side(MatrixData& M, int s, hipStream_t st) {
     ExpandDev* d_tasks = upload(mem, tasks, st);
     launch_expand(d_tasks, (int64_t)tasks.size(), st);
     launch_check("expand");
-    hip_check(hipStreamSynchronize(st), "expand sync");
+    mem.sync(st, "expand sync");
     mem.release(d_tasks);
   }
   if (M.precision == DH2_MIXED) {
@@ -1082,7 +1165,7 @@ static void expand_side(MatrixData& M, int s, hipStream_t st) {
     CvtDev* d_tasks = upload(mem, tasks, st);
     launch_cvt(d_tasks, (int64_t)tasks.size(), st);
     launch_check("basis conversion");
-    hip_check(hipStreamSynchronize(st), "conversion sync");
+    mem.sync(st, "conversion sync");
     mem.release(d_tasks);
   }
 }
@@ -1103,6 +1186,8 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   int64_t n = tr.n;
   int64_t nadm = (int64_t)bt.adm_t.size();
   DevMem& mem = *M.mem;
+  // uploads of the compression go through pinned staging, without waits
+  mem.begin_staging();
 
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "event");
@@ -1239,7 +1324,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
       launch_entry_scale(S.d_ents, (int64_t)nent, M.d_omega, M.zeta, st);
       launch_check("entry scales");
     }
-    hip_check(hipStreamSynchronize(st), "weights sync");
+    mem.sync(st, "weights sync");
   }
   hip_check(hipEventRecord(e1, st), "event");
   hip_check(hipEventSynchronize(e1), "event");
@@ -1287,7 +1372,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     int64_t* d_oo = upload(mem, oo, st);
     launch_near(src, g, d_to, d_tl, d_so, d_sl, d_oo, nnear, M.d_near, st);
     launch_check("near field");
-    hip_check(hipStreamSynchronize(st), "near sync");
+    mem.sync(st, "near sync");
     mem.release(d_to);
     mem.release(d_tl);
     mem.release(d_so);
@@ -1349,6 +1434,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   S.n_gram_leaf = ss_row.n_gram_leaf + ss_col.n_gram_leaf;
   S.flops_rprod_leaf = ss_row.flops_rprod_leaf + ss_col.flops_rprod_leaf;
   S.ops_gram_leaf_i8 = ss_row.ops_gram_leaf_i8 + ss_col.ops_gram_leaf_i8;
+  mem.end_staging(st);
   trc.mark("finish", -1, -1, -1);
   return Mp;
 }
@@ -1621,14 +1707,14 @@ double error_estimate(MatrixData& M, const void* G, int64_t ld, int iters, uint6
     for (auto& v : hx) v = make_double2(v.x / nrm, v.y / nrm);
     double lam = 0, lam_old = 0;
     for (int it = 0; it < iters; ++it) {
-      copy_to(x, hx.data(), n, st);
+      copy_to(mem, x, hx.data(), n, st);
       direct_apply(M, src, g, x, y1, 0, tp, to, st);
       if (diff) {
         matvec(M, 'N', x, y2, st);
         copy_from(hy.data(), y1, n, st);
         copy_from(hz.data(), y2, n, st);
         for (int64_t i = 0; i < n; ++i) hy[i] = make_double2(hy[i].x - hz[i].x, hy[i].y - hz[i].y);
-        copy_to(y1, hy.data(), n, st);
+        copy_to(mem, y1, hy.data(), n, st);
       }
       direct_apply(M, src, g, y1, z, 1, tp, to, st);
       if (diff) {

@@ -25,21 +25,40 @@ void hip_check(hipError_t e, const char* what);
 // Return the cached (freed but kept) device blocks to the driver.
 void release_cached_memory();
 
-// Device allocations with an optional cap (max_device_bytes).
+// Device allocations with an optional cap (max_device_bytes), owned by one
+// host thread that queues its work on one stream at a time.
 class DevMem {
  public:
   explicit DevMem(int64_t cap = 0) : cap_(cap) {}
   ~DevMem();
   void* alloc(size_t bytes);
+  // The block stops counting against the cap at once; it joins the
+  // process-wide cache, where work on other streams may take it, only at the
+  // next sync(), when no queued work of this owner can still use it.
   void release(void* p);
+  // Wait for the stream, then hand the released blocks to the cache and
+  // recycle the staging buffer.
+  void sync(hipStream_t st, const char* what);
+  // Host-to-device copy.  While staging is on, the bytes are copied into a
+  // pinned buffer at once and the transfer is queued without waiting (the
+  // host data may change on return); otherwise the call waits for the stream.
+  void upload(void* d, const void* h, size_t bytes, hipStream_t st);
+  // Staging on: a pinned buffer from a process-wide pool.  Off: sync(st),
+  // buffer back to the pool.
+  void begin_staging();
+  void end_staging(hipStream_t st);
   int64_t used() const { return used_; }
   int64_t peak() const { return peak_; }
 
  private:
+  void flush_released();
   int64_t cap_;
   int64_t used_ = 0;
   int64_t peak_ = 0;
   std::vector<std::pair<void*, size_t>> live_;
+  std::vector<std::pair<void*, size_t>> released_;
+  char* pin_ = nullptr;
+  size_t pin_off_ = 0;
 };
 
 struct TreeData {
