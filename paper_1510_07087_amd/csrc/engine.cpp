@@ -841,10 +841,17 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           off += (int64_t)fl[c].size();
         }
         launch_check("factor");
+        // only the ranks come back to the host (4 bytes per item)
+        int32_t* d_k = (int32_t*)mem.alloc((size_t)n * sizeof(int32_t));
+        launch_ranks(S.d_items + lo, n, d_k, st);
+        launch_check("ranks");
         mem.sync(st, "factor sync");
+        std::vector<int32_t> hk(n);
+        copy_from(hk.data(), d_k, n, st);
+        for (int32_t i = 0; i < n; ++i) S.items[lo + i].k = hk[i];
         mem.release(d_fl);
+        mem.release(d_k);
       }
-      copy_from(S.items.data() + lo, S.d_items + lo, n, st);
       int32_t status = 0;
       copy_from(&status, d_status, 1, st);
       if (status & 1)

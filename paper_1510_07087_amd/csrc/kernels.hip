@@ -531,6 +531,11 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
   if (tid == 0) it.k = k;
 }
 
+__global__ __launch_bounds__(256) void k_ranks(const ItemDev* items, int32_t n, int32_t* out) {
+  int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = items[i].k;
+}
+
 // ---------------------------------------------------------------------------
 // Expansion of the column basis: dst rows = src (rows x ks) * E (ks x k).
 // ---------------------------------------------------------------------------
@@ -2212,6 +2217,11 @@ void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
   if (nl == 0) return;
   hipLaunchKernelGGL(k_gram_reduce, dim3(nl), dim3(256), 0, st, items, litems, ubegin, units,
                      partial);
+}
+
+void launch_ranks(const ItemDev* items, int32_t n, int32_t* out, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_ranks, dim3(blocks_for(n, 256)), dim3(256), 0, st, items, n, out);
 }
 
 void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rmax, double eps,

@@ -18,6 +18,9 @@ void launch_gram(int src, bool inner, bool mixed, const GeomDev& g, const ItemDe
 void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
                         const int32_t* ubegin, const UnitDev* units, const double2* partial,
                         hipStream_t st);
+// ranks k of items [0, n) into out (the host reads them back after a level's
+// factorisations)
+void launch_ranks(const ItemDev* items, int32_t n, int32_t* out, hipStream_t st);
 void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rmax, double eps,
                    int max_sweeps, int32_t* status, hipStream_t st);
 // Column data (x, y, z, factor) of the listed leaf items into their it.cols.
