@@ -800,7 +800,7 @@ __device__ __forceinline__ void pst_tile(const PTileDev& t, const PBlkDev* blks,
                                          const double* omega) {
   typedef float fv2 __attribute__((ext_vector_type(2)));
   using GP = const __attribute__((address_space(1))) fv2*;
-  constexpr int kRing = 8;
+  constexpr int kRing = 12;
   const int lane = threadIdx.x & 63;
   // ranks of the tile's blocks in lanes q < nblk, their first stacked rows
   // (relative to the tile) by an exclusive prefix sum, then this lane's block
