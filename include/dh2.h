@@ -208,10 +208,12 @@ dh2_status dh2_compress_batch(int32_t count, const dh2_blocks* blocks,
 void dh2_matrix_free(dh2_matrix m);
 
 /* Device memory freed by the library (matrices freed, per-level work arrays)
- * is kept in a process-wide cache, up to half of the device memory, and reused
- * by later calls: handing touched memory back to the driver costs about
- * 10-20 ms per gigabyte.  This call returns the whole cache to the driver.
- * Do not call it while another thread is inside a dh2 call.                */
+ * is kept in a process-wide cache, up to 80 % of the device memory, and
+ * reused by later calls: handing touched memory back to the driver costs
+ * about 10-20 ms per gigabyte.  The pinned host buffers that stage uploads
+ * (32 MiB each, one per compression running at a time) are pooled the same
+ * way.  This call returns both caches to the driver.  Do not call it while
+ * another thread is inside a dh2 call.                                      */
 void dh2_release_cached_memory(void);
 
 /* ---------------------------------------------------------------------------

@@ -123,15 +123,21 @@ void trim_cache_locked(size_t keep) {
 }
 }  // namespace
 
-void release_cached_memory() {
-  std::lock_guard<std::mutex> lk(g_cache_mu);
-  trim_cache_locked(0);
-}
-
-// pinned staging buffers, reused across compressions
+// pinned staging buffers, reused across compressions (a buffer in the pool
+// has no transfer in flight)
 constexpr size_t kPinBytes = size_t(32) << 20;
 static std::mutex g_pin_mu;
 static std::vector<char*> g_pin_pool;
+
+void release_cached_memory() {
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    trim_cache_locked(0);
+  }
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  for (char* p : g_pin_pool) (void)hipHostFree(p);
+  g_pin_pool.clear();
+}
 
 DevMem::~DevMem() {
   // an error may have left work queued that still uses released blocks or
