@@ -1066,11 +1066,9 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         tp.start();
         {
           int64_t toff = 0;
-          for (int cls = 0, c = 1; cls < 3; ++cls) {
-            int64_t cnt = 0;
-            for (; c <= kPstLast[cls]; ++c) cnt += ncount[c];
-            launch_project_stacked(cls, d_ptile + toff, cnt, d_pblk, M.d_omega, st);
-            toff += cnt;
+          for (int c = 1; c <= 16; ++c) {
+            launch_project_stacked(c, d_ptile + toff, ncount[c], d_pblk, M.d_omega, st);
+            toff += ncount[c];
           }
           launch_check("project (stacked)");
         }

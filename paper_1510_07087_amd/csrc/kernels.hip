@@ -869,33 +869,20 @@ __device__ __forceinline__ void pst_tile(const PTileDev& t, const PBlkDev* blks,
   }
 }
 
-// Tiles of one launch have ceil(ks / 4) in [NC0, NC1]; each wave dispatches
-// on its own tile's column-group count.
-template <int NC0, int NC1, int WPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_project_stacked(const PTileDev* tiles, int64_t ntiles,
-                                                         const PBlkDev* blks,
-                                                         const double* omega) {
+// Every tile of one launch has ceil(ks / 4) = NC column groups (one
+// instance per NC: a launch runs one loop body; WPE bounds the registers so
+// that WPE or more waves share a SIMD).
+template <int NC, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_project_stacked(
+    const PTileDev* tiles, int64_t ntiles, const PBlkDev* blks, const double* omega) {
   // XCD-aware order, as in k_project_tiled
   unsigned nb = gridDim.x, bx = blockIdx.x;
   unsigned x = bx & 7u, loc = bx >> 3, qx = nb >> 3, rmd = nb & 7u;
   unsigned slot = x * qx + (x < rmd ? x : rmd) + loc;
   int64_t ti = (int64_t)slot * 4 + wave_id();
   if (ti >= ntiles) return;
-  const PTileDev t = tiles[ti];
-  const int nc = (t.ks + 3) / 4;
-  static_assert(NC0 >= 1 && NC1 <= 16 && NC0 <= NC1, "column groups");
-#define DH2_PST_CASE(C) \
-  case C:               \
-    if constexpr (C >= NC0 && C <= NC1) pst_tile<C>(t, blks, omega); \
-    break;
-  switch (nc) {
-    DH2_PST_CASE(1) DH2_PST_CASE(2) DH2_PST_CASE(3) DH2_PST_CASE(4)
-    DH2_PST_CASE(5) DH2_PST_CASE(6) DH2_PST_CASE(7) DH2_PST_CASE(8)
-    DH2_PST_CASE(9) DH2_PST_CASE(10) DH2_PST_CASE(11) DH2_PST_CASE(12)
-    DH2_PST_CASE(13) DH2_PST_CASE(14) DH2_PST_CASE(15) DH2_PST_CASE(16)
-    default: break;
-  }
-#undef DH2_PST_CASE
+  static_assert(NC >= 1 && NC <= 16, "column groups");
+  pst_tile<NC>(tiles[ti], blks, omega);
 }
 
 template <bool MX, int NI, int NJ>
@@ -2346,24 +2333,23 @@ void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t ds
                      dst_off, count);
 }
 
-void launch_project_stacked(int cls, const PTileDev* tiles, int64_t ntiles, const PBlkDev* blks,
+void launch_project_stacked(int nc, const PTileDev* tiles, int64_t ntiles, const PBlkDev* blks,
                             const double* omega, hipStream_t st) {
   if (ntiles == 0) return;
   dim3 grid((unsigned)((ntiles + 3) / 4));
-  switch (cls) {
-    case 0:
-      hipLaunchKernelGGL((k_project_stacked<1, kPstLast[0], 4>), grid, dim3(256), 0, st, tiles, ntiles,
-                         blks, omega);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_project_stacked<kPstLast[0] + 1, kPstLast[1], 3>), grid, dim3(256), 0, st,
-                         tiles, ntiles, blks, omega);
-      break;
-    default:
-      hipLaunchKernelGGL((k_project_stacked<kPstLast[1] + 1, 16, 2>), grid, dim3(256), 0, st, tiles,
-                         ntiles, blks, omega);
-      break;
+#define DH2_PST_NC(C)                                                                      \
+  case C:                                                                                  \
+    hipLaunchKernelGGL((k_project_stacked<C, (C <= 6 ? 4 : C <= 9 ? 3 : 2)>), grid,       \
+                       dim3(256), 0, st, tiles, ntiles, blks, omega);                      \
+    break;
+  switch (nc) {
+    DH2_PST_NC(1) DH2_PST_NC(2) DH2_PST_NC(3) DH2_PST_NC(4)
+    DH2_PST_NC(5) DH2_PST_NC(6) DH2_PST_NC(7) DH2_PST_NC(8)
+    DH2_PST_NC(9) DH2_PST_NC(10) DH2_PST_NC(11) DH2_PST_NC(12)
+    DH2_PST_NC(13) DH2_PST_NC(14) DH2_PST_NC(15) DH2_PST_NC(16)
+    default: break;
   }
+#undef DH2_PST_NC
 }
 
 void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const double* omega,

@@ -47,11 +47,9 @@ void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t ds
                    int64_t count, hipStream_t st);
 void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const double* omega,
                     hipStream_t st);
-// mixed form, blocks stacked by shared W (ks <= 64): launch class cls takes
-// the tiles with ceil(ks / 4) in (kPstLast[cls - 1], kPstLast[cls]] (classes
-// by register footprint)
-constexpr int kPstLast[3] = {6, 9, 16};
-void launch_project_stacked(int cls, const PTileDev* tiles, int64_t ntiles, const PBlkDev* blks,
+// mixed form, blocks stacked by shared W (ks <= 64): one launch per column
+// group count nc = ceil(ks / 4) in 1..16
+void launch_project_stacked(int nc, const PTileDev* tiles, int64_t ntiles, const PBlkDev* blks,
                             const double* omega, hipStream_t st);
 // blocks with ks <= 64: every task of one launch has ceil(ks/16) = nj and is
 // processed in passes of ni = min(ceil(kt/16), project_rows_per_pass) row tiles
