@@ -6,7 +6,11 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 Steps, in the paper's order and notation:
 
 * block weights omega_b = ||G|_b|| for b in L+ (remark "Error control", with
-  the Frobenius norm; ``weight_norm='2'`` selects the spectral norm);
+  the Frobenius norm; ``weight_norm='2'`` selects the spectral norm;
+  ``weight_norm='global'`` gives every block the same weight, the Frobenius
+  norm of G restricted to the admissible blocks, for a global-relative
+  tolerance; ``weight_norm='one'`` the unit weights of the unweighted
+  algorithm);
 * weighted block rows G^w_tc: the columns of F_tc coming from the admissible
   block b=(t+,s) of an ancestor-or-self t+ are divided by
   omega_b * zeta^(level(t)-level(t+)) (remark "Error control": local accuracy
@@ -53,12 +57,21 @@ class Basis:
 
 
 def block_weights(M, plan: Plan, norm: str = "fro") -> np.ndarray:
-    """omega_b = ||G|_{t x s}|| for every admissible block."""
+    """omega_b = ||G|_{t x s}|| for every admissible block (norm 'fro' or '2'),
+    the same (sum_b ||G|_b||_F^2)^(1/2) for all blocks ('global'), or 1
+    ('one')."""
     tr, bt = plan.tree, plan.blocks
-    om = np.empty(len(bt.adm_t))
-    for b in range(len(bt.adm_t)):
+    nb = len(bt.adm_t)
+    if norm == "one":
+        return np.ones(nb)
+    if norm not in ("fro", "2", "global"):
+        raise ValueError(f"unknown weight norm {norm!r}")
+    om = np.empty(nb)
+    for b in range(nb):
         blk = M.block(tr.rows(bt.adm_t[b]), tr.rows(bt.adm_s[b]))
-        om[b] = np.linalg.norm(blk, "fro" if norm == "fro" else 2)
+        om[b] = np.linalg.norm(blk, 2 if norm == "2" else "fro")
+    if norm == "global":
+        om = np.full(nb, np.sqrt(np.sum(om ** 2)))
     return om
 
 

@@ -294,3 +294,70 @@ def test_kappa_zero_ranks_bounded():
             Gt = D.reconstruct(cp)[np.ix_(pl.tree.perm, pl.tree.perm)]
             assert np.linalg.norm(G - Gt, 2) / np.linalg.norm(G, 2) <= EPS
     assert kmax[1] <= kmax[0] + 4
+
+
+@pytest.fixture(scope="module")
+def small_sphere():
+    p, w = synth.fibonacci_sphere(1024)
+    pl = P.build_plan(p, 8.0, 32)
+    M = Mx.HelmholtzMatrix(p, w, 8.0, pl.tree.perm)
+    G = Mx.helmholtz_dense_original(p, w, 8.0)
+    return p, w, pl, M, G
+
+
+def test_global_weight_is_admissible_frobenius_norm(small_sphere):
+    """The global weight is ||G restricted to the admissible blocks||_F, here
+    computed from the dense matrix through a mask of the block list."""
+    p, w, pl, M, G = small_sphere
+    tr, bt = pl.tree, pl.blocks
+    mask = np.zeros(G.shape, dtype=bool)
+    for t, s in zip(bt.adm_t, bt.adm_s):
+        rows = tr.perm[tr.rows(int(t))]
+        cols = tr.perm[tr.rows(int(s))]
+        mask[np.ix_(rows, cols)] = True
+    om = C.block_weights(M, pl, "global")
+    ref = np.linalg.norm(G[mask])
+    assert np.allclose(om, ref, rtol=1e-13, atol=0)
+
+
+def test_global_weights_equal_unit_weights_at_scaled_eps(small_sphere):
+    """Constant weights omega only rescale the weighted block rows, so the
+    global-relative compression at eps equals the unweighted one at
+    eps * omega: same ranks, same subspaces (remark "Error control")."""
+    p, w, pl, M, G = small_sphere
+    cg = C.compress(M, pl, EPS, ZETA, weight_norm="global")
+    og = float(cg.omega[0])
+    c1 = C.compress(M, pl, EPS * og, ZETA, weight_norm="one")
+    for bg, b1 in ((cg.V, c1.V), (cg.W, c1.W)):
+        assert bg.k.keys() == b1.k.keys()
+        for key in bg.k:
+            s1 = b1.sigma[key]
+            if np.any(np.abs(s1 - EPS * og) <= 1e-10 * EPS * og):
+                continue
+            assert bg.k[key] == b1.k[key], key
+            assert np.allclose(bg.sigma[key] * og, s1, rtol=1e-12, atol=1e-14 * og)
+            Qg, Q1 = bg.Qexp[key], b1.Qexp[key]
+            if Qg.shape[1]:
+                assert np.linalg.norm(Qg @ Qg.conj().T - Q1 @ Q1.conj().T, 2) <= 1e-9
+
+
+def test_global_weights_block_bound(small_sphere):
+    """With one weight for all blocks every admissible block obeys the
+    bound of the error-control remark with that weight, and the global
+    relative error stays below eps * omega / ||G||_2 times the same factor."""
+    p, w, pl, M, G = small_sphere
+    cp = C.compress(M, pl, EPS, ZETA, weight_norm="global")
+    tr, bt = pl.tree, pl.blocks
+    om = float(cp.omega[0])
+    bound = math.sqrt(2.0) * EPS * om / math.sqrt(1.0 - 2.0 * ZETA ** 2)
+    worst = 0.0
+    for b in range(len(bt.adm_t)):
+        t, s, c = int(bt.adm_t[b]), int(bt.adm_s[b]), int(bt.adm_c[b])
+        Gb = M.block(tr.rows(t), tr.rows(s))
+        err = np.linalg.norm(Gb - cp.V.Qexp[(t, c)] @ cp.S[b] @ cp.W.Qexp[(s, c)].conj().T, 2)
+        worst = max(worst, err / bound)
+    assert worst <= 1.0
+    # the weights are larger than the block norms, so the compression is
+    # coarser than the block-relative one
+    cb = C.compress(M, pl, EPS, ZETA)
+    assert sum(cp.V.k.values()) <= sum(cb.V.k.values())
