@@ -73,7 +73,12 @@ typedef struct dh2_matrix_s* dh2_matrix; /* compressed DH2 representation    */
  *          comparison with cross approximation).
  *   max_device_bytes : cap on the library's device allocations (0 = none).
  *   groups : number of subtree groups swept one after another to bound the
- *          memory of the coefficient matrices R (0 = automatic).  */
+ *          memory of the coefficient matrices R (0 = automatic).
+ *   weights : block weights omega_b of the remark on error control.
+ *          DH2_WEIGHTS_BLOCK (0): omega_b = ||G|_b||_F, block-relative error
+ *          bounds (the paper's experiments).  DH2_WEIGHTS_GLOBAL (1): every
+ *          block gets (sum over admissible b' of ||G|_b'||_F^2)^(1/2), a
+ *          global-relative tolerance.  */
 typedef struct {
   int32_t leaf_size;
   double eta1;
@@ -84,7 +89,10 @@ typedef struct {
   int32_t standard_only;
   int32_t groups;
   int64_t max_device_bytes;
+  int32_t weights;
 } dh2_opts;
+
+typedef enum { DH2_WEIGHTS_BLOCK = 0, DH2_WEIGHTS_GLOBAL = 1 } dh2_weights;
 
 void dh2_opts_default(dh2_opts* opts);
 

@@ -55,6 +55,8 @@ static void check_opts(const dh2_opts* o) {
     fail(DH2_EINVAL, "unknown precision mode");
   if (o->max_device_bytes < 0) fail(DH2_EINVAL, "max_device_bytes must be >= 0");
   if (o->groups < 0) fail(DH2_EINVAL, "groups must be >= 0");
+  if (o->weights != DH2_WEIGHTS_BLOCK && o->weights != DH2_WEIGHTS_GLOBAL)
+    fail(DH2_EINVAL, "unknown block weights");
 }
 
 static hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -89,6 +91,7 @@ void dh2_opts_default(dh2_opts* o) {
   o->standard_only = 0;
   o->groups = 0;
   o->max_device_bytes = 0;
+  o->weights = DH2_WEIGHTS_BLOCK;
 }
 
 const char* dh2_last_error(void) { return g_err.c_str(); }

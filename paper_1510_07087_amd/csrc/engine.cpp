@@ -1322,6 +1322,16 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     M.d_omega = (double*)mem.alloc(std::max<int64_t>(1, nadm) * sizeof(double));
     launch_block_norm(src, g, d_to, d_tl, d_so, d_sl, nadm, M.d_omega, st);
     launch_check("block norms");
+    if (o.weights == DH2_WEIGHTS_GLOBAL && nadm > 0) {
+      // one weight for every block: the Frobenius norm of G on the
+      // admissible blocks (global-relative tolerance)
+      std::vector<double> om(nadm);
+      copy_from(om.data(), M.d_omega, nadm, st);
+      double s2 = 0.0;
+      for (double v : om) s2 += v * v;
+      std::fill(om.begin(), om.end(), std::sqrt(s2));
+      mem.upload(M.d_omega, om.data(), (size_t)nadm * sizeof(double), st);
+    }
     for (int s = 0; s < 2; ++s) {
       Side& S = M.side[s];
       S.d_items = upload(mem, S.items, st);

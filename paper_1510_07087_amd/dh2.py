@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdh2.so")
 
 FP64, MIXED = 0, 1
+WEIGHTS_BLOCK, WEIGHTS_GLOBAL = 0, 1
 _STATUS = {0: "DH2_OK", -1: "DH2_EINVAL", -2: "DH2_ENOMEM", -3: "DH2_EDEVICE",
            -4: "DH2_ENOTCONV", -5: "DH2_EUNSUPPORTED"}
 
@@ -32,7 +33,8 @@ class Opts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("eta1", C.c_double), ("eta2", C.c_double),
                 ("zeta", C.c_double), ("precision", C.c_int32),
                 ("lowfreq_zero_dir", C.c_int32), ("standard_only", C.c_int32),
-                ("groups", C.c_int32), ("max_device_bytes", C.c_int64)]
+                ("groups", C.c_int32), ("max_device_bytes", C.c_int64),
+                ("weights", C.c_int32)]
 
 
 class TreeInfo(C.Structure):
