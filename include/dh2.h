@@ -78,7 +78,9 @@ typedef struct dh2_matrix_s* dh2_matrix; /* compressed DH2 representation    */
  *          DH2_WEIGHTS_BLOCK (0): omega_b = ||G|_b||_F, block-relative error
  *          bounds (the paper's experiments).  DH2_WEIGHTS_GLOBAL (1): every
  *          block gets (sum over admissible b' of ||G|_b'||_F^2)^(1/2), a
- *          global-relative tolerance.  */
+ *          global-relative tolerance.  DH2_WEIGHTS_SPECTRAL (2):
+ *          omega_b = ||G|_b||_2 (power method on the device, clusters of at
+ *          most 1024 points, else DH2_EUNSUPPORTED).  */
 typedef struct {
   int32_t leaf_size;
   double eta1;
@@ -92,7 +94,7 @@ typedef struct {
   int32_t weights;
 } dh2_opts;
 
-typedef enum { DH2_WEIGHTS_BLOCK = 0, DH2_WEIGHTS_GLOBAL = 1 } dh2_weights;
+typedef enum { DH2_WEIGHTS_BLOCK = 0, DH2_WEIGHTS_GLOBAL = 1, DH2_WEIGHTS_SPECTRAL = 2 } dh2_weights;
 
 void dh2_opts_default(dh2_opts* opts);
 

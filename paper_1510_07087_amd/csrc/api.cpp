@@ -55,7 +55,8 @@ static void check_opts(const dh2_opts* o) {
     fail(DH2_EINVAL, "unknown precision mode");
   if (o->max_device_bytes < 0) fail(DH2_EINVAL, "max_device_bytes must be >= 0");
   if (o->groups < 0) fail(DH2_EINVAL, "groups must be >= 0");
-  if (o->weights != DH2_WEIGHTS_BLOCK && o->weights != DH2_WEIGHTS_GLOBAL)
+  if (o->weights != DH2_WEIGHTS_BLOCK && o->weights != DH2_WEIGHTS_GLOBAL &&
+      o->weights != DH2_WEIGHTS_SPECTRAL)
     fail(DH2_EINVAL, "unknown block weights");
 }
 

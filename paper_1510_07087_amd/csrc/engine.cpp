@@ -1320,7 +1320,15 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     const int64_t* d_so = d_to + 2 * nadm;
     const int64_t* d_sl = d_to + 3 * nadm;
     M.d_omega = (double*)mem.alloc(std::max<int64_t>(1, nadm) * sizeof(double));
-    launch_block_norm(src, g, d_to, d_tl, d_so, d_sl, nadm, M.d_omega, st);
+    if (o.weights == DH2_WEIGHTS_SPECTRAL) {
+      for (int64_t b = 0; b < nadm; ++b)
+        if (std::max(tr.size[bt.adm_t[b]], tr.size[bt.adm_s[b]]) > block_norm2_max_size())
+          fail(DH2_EUNSUPPORTED, "spectral block weights need clusters of at most " +
+                                     std::to_string(block_norm2_max_size()) + " points");
+      launch_block_norm2(src, g, d_to, d_tl, d_so, d_sl, nadm, 1000, 1e-13, M.d_omega, st);
+    } else {
+      launch_block_norm(src, g, d_to, d_tl, d_so, d_sl, nadm, M.d_omega, st);
+    }
     launch_check("block norms");
     if (o.weights == DH2_WEIGHTS_GLOBAL && nadm > 0) {
       // one weight for every block: the Frobenius norm of G on the

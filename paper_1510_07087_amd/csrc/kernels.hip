@@ -238,6 +238,79 @@ __global__ __launch_bounds__(256) void k_block_norm(GeomDev g, const int64_t* t_
   if (threadIdx.x == 0) omega[b] = sqrt(red[0]);
 }
 
+// Spectral block norms: omega_b = ||G|_b||_2 by the power method on
+// (G|_b)^* G|_b, one workgroup per block, entries generated in every pass.
+// With x normalised, ||G|_b x||^2 increases to sigma_1^2; the iteration
+// stops when it changes by less than tol (relative) or after max_iter steps.
+constexpr int kNorm2Max = 1024;  // largest cluster of an admissible block
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+template <int SRC>
+__global__ __launch_bounds__(256) void k_block_norm2(GeomDev g, const int64_t* t_off,
+                                                     const int64_t* t_len, const int64_t* s_off,
+                                                     const int64_t* s_len, int64_t nblocks,
+                                                     int max_iter, double tol, double* omega) {
+  __shared__ double2 xs[kNorm2Max];
+  __shared__ double2 ys[kNorm2Max];
+  __shared__ double red[4];
+  const int64_t b = blockIdx.x;
+  if (b >= nblocks) return;
+  const int64_t to = t_off[b], so = s_off[b];
+  const int tl = (int)t_len[b], sl = (int)s_len[b];
+  const int tid = threadIdx.x;
+  // start vector with no special structure (fixed, so runs repeat exactly)
+  double p = 0.0;
+  for (int j = tid; j < sl; j += 256) {
+    double2 v = make_double2(1.0 + 0.5 * sin(0.7 * j), 0.3 * cos(1.3 * j));
+    xs[j] = v;
+    p += v.x * v.x + v.y * v.y;
+  }
+  double nx = sqrt(block_sum(p, red));
+  for (int j = tid; j < sl; j += 256) xs[j] = make_double2(xs[j].x / nx, xs[j].y / nx);
+  __syncthreads();
+  double lam = 0.0;
+  for (int it = 0; it < max_iter; ++it) {
+    // y = G|_b x
+    p = 0.0;
+    for (int i = tid; i < tl; i += 256) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int j = 0; j < sl; ++j) {
+        double2 a = entry<SRC>(g, to + i, so + j, 0), x = xs[j];
+        acc.x += a.x * x.x - a.y * x.y;
+        acc.y += a.x * x.y + a.y * x.x;
+      }
+      ys[i] = acc;
+      p += acc.x * acc.x + acc.y * acc.y;
+    }
+    const double lam_new = block_sum(p, red);  // ||G|_b x||^2, x normalised
+    // x = (G|_b)^* y, normalised
+    p = 0.0;
+    for (int j = tid; j < sl; j += 256) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int i = 0; i < tl; ++i) {
+        double2 a = entry<SRC>(g, to + i, so + j, 0), y = ys[i];
+        acc.x += a.x * y.x + a.y * y.y;  // conj(a) y
+        acc.y += a.x * y.y - a.y * y.x;
+      }
+      xs[j] = acc;
+      p += acc.x * acc.x + acc.y * acc.y;
+    }
+    nx = sqrt(block_sum(p, red));
+    const bool done = !(nx > 0.0) || fabs(lam_new - lam) <= tol * lam_new;
+    lam = lam_new;
+    if (done) break;
+    for (int j = tid; j < sl; j += 256) xs[j] = make_double2(xs[j].x / nx, xs[j].y / nx);
+    __syncthreads();
+  }
+  if (tid == 0) omega[b] = sqrt(lam);
+}
+
 // scale of each column-set entry: 1 / (omega_b zeta^d)
 __global__ void k_entry_scale(EntDev* ent, int64_t nent, const double* omega, double zeta) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2165,6 +2238,20 @@ void launch_block_norm(int src, const GeomDev& g, const int64_t* t_off, const in
     hipLaunchKernelGGL(k_block_norm<SRC_DENSE>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
                        t_off, t_len, s_off, s_len, nblocks, omega);
 }
+
+void launch_block_norm2(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
+                        const int64_t* s_off, const int64_t* s_len, int64_t nblocks,
+                        int max_iter, double tol, double* omega, hipStream_t st) {
+  if (nblocks == 0) return;
+  if (src == SRC_HELMHOLTZ)
+    hipLaunchKernelGGL(k_block_norm2<SRC_HELMHOLTZ>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
+                       t_off, t_len, s_off, s_len, nblocks, max_iter, tol, omega);
+  else
+    hipLaunchKernelGGL(k_block_norm2<SRC_DENSE>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
+                       t_off, t_len, s_off, s_len, nblocks, max_iter, tol, omega);
+}
+
+int block_norm2_max_size() { return kNorm2Max; }
 
 void launch_entry_scale(EntDev* ent, int64_t nent, const double* omega, double zeta,
                         hipStream_t st) {

@@ -7,6 +7,12 @@
 
 namespace dh2 {
 
+// spectral norms of the admissible blocks (power method, clusters of at most
+// block_norm2_max_size() points)
+void launch_block_norm2(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
+                        const int64_t* s_off, const int64_t* s_len, int64_t nblocks,
+                        int max_iter, double tol, double* omega, hipStream_t st);
+int block_norm2_max_size();
 void launch_block_norm(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
                        const int64_t* s_off, const int64_t* s_len, int64_t nblocks, double* omega,
                        hipStream_t st);

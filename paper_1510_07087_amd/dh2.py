@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdh2.so")
 
 FP64, MIXED = 0, 1
-WEIGHTS_BLOCK, WEIGHTS_GLOBAL = 0, 1
+WEIGHTS_BLOCK, WEIGHTS_GLOBAL, WEIGHTS_SPECTRAL = 0, 1, 2
 _STATUS = {0: "DH2_OK", -1: "DH2_EINVAL", -2: "DH2_ENOMEM", -3: "DH2_EDEVICE",
            -4: "DH2_ENOTCONV", -5: "DH2_EUNSUPPORTED"}
 

@@ -10,7 +10,9 @@ switches, on the 2048-point sphere (leaf 32, eps 1e-4), FP64 and mixed form:
 * global block weights at kappa = 8: every block weighted by the Frobenius
   norm of G on the admissible blocks (remark on error control), a
   global-relative tolerance; its error is compared with the oracle's only,
-  since the bound eps holds relative to the weights, not to ||G||_2.
+  since the bound eps holds relative to the weights, not to ||G||_2;
+* spectral block weights at kappa = 8: omega_b = ||G|_b||_2 (power method on
+  the device against the oracle's dense 2-norm).
 
 Checks, with the tolerances derived in test_gpu_parity: singular values and
 ranks of every block row, global relative spectral error <= 1.1 eps (block
@@ -40,6 +42,7 @@ VARIANTS = {
     "lowfreq": (8.0, dict(lowfreq_zero=True)),
     "standard": (8.0, dict(standard_only=True)),
     "global": (8.0, dict(weights="global")),
+    "spectral": (8.0, dict(weights="2")),
 }
 
 
@@ -64,8 +67,8 @@ def gpu(request, problem):
     o = dh2.opts(leaf_size=32, precision=dh2.MIXED if request.param == "mixed" else dh2.FP64,
                  lowfreq_zero_dir=int(kw.get("lowfreq_zero", False)),
                  standard_only=int(kw.get("standard_only", False)),
-                 weights=dh2.WEIGHTS_GLOBAL if kw.get("weights") == "global" else
-                 dh2.WEIGHTS_BLOCK)
+                 weights={"global": dh2.WEIGHTS_GLOBAL, "2": dh2.WEIGHTS_SPECTRAL}.get(
+                     kw.get("weights"), dh2.WEIGHTS_BLOCK))
     t = dh2.tree_build(problem["p"], problem["kappa"], o)
     b = dh2.blocks_build(t, o)
     m = dh2.compress_helmholtz(b, problem["w"], EPS, o)

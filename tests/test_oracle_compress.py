@@ -361,3 +361,23 @@ def test_global_weights_block_bound(small_sphere):
     # coarser than the block-relative one
     cb = C.compress(M, pl, EPS, ZETA)
     assert sum(cp.V.k.values()) <= sum(cb.V.k.values())
+
+
+def test_spectral_weights_block_bound(small_sphere):
+    """Spectral weights omega_b = ||G|_b||_2 <= ||G|_b||_F: every block obeys
+    the bound of the error-control remark with its spectral weight, and the
+    bases are at least as large as with Frobenius weights."""
+    p, w, pl, M, G = small_sphere
+    tr, bt = pl.tree, pl.blocks
+    cs = C.compress(M, pl, EPS, ZETA, weight_norm="2")
+    cf = C.compress(M, pl, EPS, ZETA)
+    assert np.all(cs.omega <= cf.omega * (1 + 1e-14))
+    bound = math.sqrt(2.0) * EPS / math.sqrt(1.0 - 2.0 * ZETA ** 2)
+    for b in range(len(bt.adm_t)):
+        t, s, c = int(bt.adm_t[b]), int(bt.adm_s[b]), int(bt.adm_c[b])
+        Gb = M.block(tr.rows(t), tr.rows(s))
+        err = np.linalg.norm(Gb - cs.V.Qexp[(t, c)] @ cs.S[b] @ cs.W.Qexp[(s, c)].conj().T, 2)
+        assert err <= bound * cs.omega[b]
+        # the weight is the block's largest singular value
+        assert abs(np.linalg.svd(Gb, compute_uv=False)[0] - cs.omega[b]) <= 1e-13 * cs.omega[b]
+    assert sum(cs.V.k.values()) >= sum(cf.V.k.values())
