@@ -1295,9 +1295,12 @@ __global__ __launch_bounds__(256) void k_leaf_cols(GeomDev g, const ItemDev* ite
                                                    int side) {
   const ItemDev& it = items[litems[blockIdx.x]];
   double4* out = it.cols;
-  for (int64_t e = it.ent_begin; e < it.ent_end; ++e) {
+  // the four waves take the column-set entries in turn, so that the loads
+  // of several entries are in flight at once
+  const int lane = threadIdx.x & 63;
+  for (int64_t e = it.ent_begin + wave_id(); e < it.ent_end; e += 4) {
     const EntDev en = ents[e];
-    for (int64_t q = threadIdx.x; q < en.len; q += 256) {
+    for (int64_t q = lane; q < en.len; q += 64) {
       int64_t pos = en.pos + q;
       double4 v;
       if constexpr (SRC == SRC_HELMHOLTZ) {
