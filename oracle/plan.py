@@ -224,6 +224,11 @@ def admissible(tree: ClusterTree, t: int, s: int, kappa: float, eta2: float,
                standard_only: bool = False) -> bool:
     dmax = max(tree.diam[t], tree.diam[s])
     dist = box_dist(tree.lo[t], tree.hi[t], tree.lo[s], tree.hi[s])
+    # the far field needs separated boxes: (b) and (c) hold trivially for a
+    # one-point cluster with itself (diam = dist = 0), whose block holds the
+    # singular diagonal entry
+    if not dist > 0.0:
+        return False
     cond_c = dmax <= eta2 * dist
     if standard_only:
         return cond_c

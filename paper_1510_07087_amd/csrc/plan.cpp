@@ -209,7 +209,10 @@ BlockTree build_block_tree(const ClusterTree& tr, const Directions& dr, double k
     const double* hs = &tr.hi[3 * s];
     double dmax = std::max(tr.diam[t], tr.diam[s]);
     double dist = box_dist(lt, ht, ls, hs);
-    bool cond_c = dmax <= eta2 * dist;
+    // separated boxes only: (b) and (c) hold trivially for a one-point
+    // cluster with itself (diam = dist = 0), a block with the singular
+    // diagonal entry
+    bool cond_c = dist > 0.0 && dmax <= eta2 * dist;
     bool adm = cond_c;
     if (!standard_only) adm = (kappa * (dmax * dmax) <= eta2 * dist) && cond_c;
     if (adm) {

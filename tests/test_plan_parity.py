@@ -26,6 +26,12 @@ def _lib_available():
 
 pytestmark = pytest.mark.skipif(not _lib_available(), reason="libdh2.so not built")
 
+def _sphere_with_outlier(n=2048):
+    """The sphere plus one far point: bisection puts it in a one-point leaf."""
+    p, w = synth.fibonacci_sphere(n)
+    return np.vstack([p, [[5.0, 0.0, 0.0]]]), np.append(w, w[0])
+
+
 CASES = [
     ("sphere2048", lambda: synth.fibonacci_sphere(2048), 8.0, 32, {}),
     ("sphere8192_k16", lambda: synth.fibonacci_sphere(8192), 16.0, 64, {}),
@@ -35,6 +41,7 @@ CASES = [
     ("lowfreq", lambda: synth.fibonacci_sphere(4096), 11.0, 32, dict(lowfreq_zero=True)),
     ("standard", lambda: synth.fibonacci_sphere(4096), 11.0, 32, dict(standard_only=True)),
     ("eta2_1", lambda: synth.fibonacci_sphere(4096), 11.0, 32, dict(eta2=1.0)),
+    ("outlier", _sphere_with_outlier, 8.0, 32, {}),
 ]
 
 
@@ -166,3 +173,23 @@ def test_inherited_columns_form_a_prefix(side):
         assert es[:len(es) - nown] == expect
         checked += 1
     assert checked > 0
+
+
+def test_admissible_blocks_are_separated():
+    """A one-point cluster meets (b) and (c) with itself (diam = dist = 0); its
+    block holds the singular diagonal entry and must stay in the near field:
+    every admissible block has boxes at positive distance, also with a
+    one-point leaf, and a single point is one near-field block."""
+    pts, _ = _sphere_with_outlier()
+    o = dh2.opts(leaf_size=32)
+    t = dh2.tree_build(pts, 8.0, o)
+    te = dh2.tree_export(t)
+    assert 1 in set(int(x) for x in te["size"])
+    b = dh2.blocks_build(t, o)
+    be = dh2.blocks_export(b)
+    lo, hi = te["lo"].reshape(-1, 3), te["hi"].reshape(-1, 3)
+    for t_, s_ in zip(be["adm_t"], be["adm_s"]):
+        gap = np.maximum(0.0, np.maximum(lo[s_] - hi[t_], lo[t_] - hi[s_]))
+        assert np.sqrt(np.sum(gap ** 2)) > 0.0
+    one = dh2.blocks_info(dh2.blocks_build(dh2.tree_build(pts[:1], 8.0, o), o))
+    assert one["nadm"] == 0 and one["nnear"] == 1
