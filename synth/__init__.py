@@ -6,7 +6,9 @@ generator is deterministic in its arguments (numpy ``default_rng`` seeds).
 """
 from .surfaces import (
     fibonacci_sphere,
+    sphere_normals,
     ellipsoid,
+    ellipsoid_normals,
     cube_surface,
     random_rotation,
     batch_instances,
@@ -16,7 +18,9 @@ from .surfaces import (
 
 __all__ = [
     "fibonacci_sphere",
+    "sphere_normals",
     "ellipsoid",
+    "ellipsoid_normals",
     "cube_surface",
     "random_rotation",
     "batch_instances",

@@ -60,6 +60,25 @@ def ellipsoid(n: int, axes=(1.0, 0.5, 0.25), seed: int = 3):
     return np.ascontiguousarray(x), w0 * stretch
 
 
+def sphere_normals(points) -> np.ndarray:
+    """Outward unit normals of the unit sphere at the given points."""
+    p = np.asarray(points, dtype=np.float64)
+    return np.ascontiguousarray(p / np.linalg.norm(p, axis=1)[:, None])
+
+
+def ellipsoid_normals(n: int, axes=(1.0, 0.5, 0.25), seed: int = 3) -> np.ndarray:
+    """Outward unit normals at the points of ``ellipsoid(n, axes, seed)``.
+
+    The surface is {Rot diag(a,b,c) u : |u| = 1}; its normal at the image of
+    u is Rot diag(1/a,1/b,1/c) u, normalised.
+    """
+    u, _ = fibonacci_sphere(n)
+    a, b, c = (float(v) for v in axes)
+    rot = random_rotation(seed)
+    g = (u / np.array([a, b, c])) @ rot.T
+    return np.ascontiguousarray(g / np.linalg.norm(g, axis=1)[:, None])
+
+
 def cube_surface(n: int, seed: int):
     """Uniform random points on the surface of [-1,1]^3, weight 24/n each."""
     rng = np.random.default_rng(seed)
