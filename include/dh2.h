@@ -204,6 +204,20 @@ dh2_status dh2_compress_dense(dh2_blocks blocks, const void* G, int64_t ld,
 dh2_status dh2_compress_helmholtz(dh2_blocks blocks, const double* w, double eps,
                                   const dh2_opts* opts, void* stream,
                                   dh2_matrix* out);
+
+/* Double-layer operator of the Helmholtz kernel (Section 7, the DLP matrix
+ * G = M/2 + G_dlp), entries generated on the device in collocation form:
+ *   G_ij = w_j (1 - i kappa r) exp(i kappa r) <x_i - x_j, n_j> / (4 pi r^3)
+ *   (i != j), G_ii = 1/2.
+ *   w       : host, n float64 weights (copied); NULL means 4*pi/n.
+ *   normals : host, n x 3 row-major float64 unit normals in the ORIGINAL
+ *             point order (copied).
+ * FP64 form only (DH2_MIXED gives DH2_EUNSUPPORTED); errors otherwise as
+ * for dh2_compress_helmholtz, EINVAL also for NULL or non-finite normals.  */
+dh2_status dh2_compress_helmholtz_dlp(dh2_blocks blocks, const double* w,
+                                      const double* normals, double eps,
+                                      const dh2_opts* opts, void* stream,
+                                      dh2_matrix* out);
 /* Independent Helmholtz instances in one call (same options and eps for
  * all): blocks[i] with weights w[i] (w or w[i] NULL: 4 pi / n_i).  The
  * instances run concurrently on a few internal streams (default priority),

@@ -277,6 +277,25 @@ dh2_status dh2_compress_helmholtz(dh2_blocks b, const double* w, double eps, con
   })
 }
 
+dh2_status dh2_compress_helmholtz_dlp(dh2_blocks b, const double* w, const double* normals,
+                                      double eps, const dh2_opts* opts, void* stream,
+                                      dh2_matrix* out) {
+  DH2_TRY({
+    check_compress_args(b, eps, opts, out);
+    if (opts->precision != DH2_FP64)
+      fail(DH2_EUNSUPPORTED, "the double layer is compressed in FP64 only");
+    if (!normals) fail(DH2_EINVAL, "normals are NULL");
+    int64_t n = b->d->tree->tr.n;
+    for (int64_t i = 0; i < 3 * n; ++i)
+      if (!std::isfinite(normals[i])) fail(DH2_EINVAL, "non-finite normal");
+    if (w)
+      for (int64_t i = 0; i < n; ++i)
+        if (!(w[i] > 0) || !std::isfinite(w[i])) fail(DH2_EINVAL, "weights must be finite and > 0");
+    auto m = compress(b->d, SRC_DLP, nullptr, 0, w, eps, *opts, stream_of(stream), normals);
+    *out = new dh2_matrix_s{std::move(m)};
+  })
+}
+
 dh2_status dh2_compress_batch(int32_t count, const dh2_blocks* blocks, const double* const* w,
                               double eps, const dh2_opts* opts, void* stream, dh2_matrix* outs) {
   DH2_TRY({

@@ -8,7 +8,10 @@
 namespace dh2 {
 
 // Source of matrix entries.
-enum EntrySource : int32_t { SRC_HELMHOLTZ = 0, SRC_DENSE = 1 };
+// SRC_DLP: the double-layer entries of the Helmholtz kernel generated from
+// the points and their normals (FP64 form; row and column data hold
+// positions, as for the dense source)
+enum EntrySource : int32_t { SRC_HELMHOLTZ = 0, SRC_DENSE = 1, SRC_DLP = 2 };
 
 // Geometry and matrix access, all in the permuted (cluster-tree) order.
 struct GeomDev {
@@ -18,6 +21,7 @@ struct GeomDev {
   const int64_t* perm;    // position -> original index
   int64_t ldg;            // leading dimension of G in complex elements
   const double* cbox;     // per cluster: lo[3], hi[3], largest weight, 0 (bounds of entries)
+  const double* nrm;      // SRC_DLP: n x 4 unit normals (nx, ny, nz, 0), permuted order
   int64_t n;
   double kappa;
 };

@@ -1183,7 +1183,7 @@ static void expand_side(MatrixData& M, int s, hipStream_t st) {
 
 std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, const void* G,
                                      int64_t ld, const double* w, double eps, const dh2_opts& o,
-                                     hipStream_t st) {
+                                     hipStream_t st, const double* nrm) {
   auto Mp = std::make_unique<MatrixData>();
   MatrixData& M = *Mp;
   M.blk = blk;
@@ -1215,6 +1215,13 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   }
   M.d_pts = upload(mem, pp, st);
   M.d_perm = upload(mem, tr.perm, st);
+  if (src == SRC_DLP) {
+    if (!nrm) fail(DH2_EINVAL, "normals are NULL");
+    std::vector<double> pn(4 * n, 0.0);
+    for (int64_t p = 0; p < n; ++p)
+      for (int a = 0; a < 3; ++a) pn[4 * p + a] = nrm[3 * tr.perm[p] + a];
+    M.d_nrm = upload(mem, pn, st);
+  }
   {
     // cluster boxes and largest weights (bounds of the entry magnitudes)
     std::vector<double> cb(8 * (size_t)tr.nc(), 0.0);
@@ -1237,7 +1244,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   GeomDev g{};
   g.pts = M.d_pts;
   g.cbox = M.d_cbox;
-  g.cbox = M.d_cbox;
+  g.nrm = M.d_nrm;
   g.G = (const double*)G;
   g.perm = M.d_perm;
   g.ldg = ld;
@@ -1694,6 +1701,7 @@ static GeomDev geom(MatrixData& M, const void* G, int64_t ld) {
   GeomDev g{};
   g.pts = M.d_pts;
   g.cbox = M.d_cbox;
+  g.nrm = M.d_nrm;
   g.G = (const double*)G;
   g.perm = M.d_perm;
   g.ldg = ld;
@@ -1715,7 +1723,7 @@ static void direct_apply(MatrixData& M, int src, const GeomDev& g, const double2
 double error_estimate(MatrixData& M, const void* G, int64_t ld, int iters, uint64_t seed,
                       hipStream_t st) {
   int64_t n = M.blk->tree->tr.n;
-  int src = G ? SRC_DENSE : SRC_HELMHOLTZ;
+  int src = G ? SRC_DENSE : (M.src == SRC_DLP ? SRC_DLP : SRC_HELMHOLTZ);
   if (src == SRC_HELMHOLTZ && M.src == SRC_DENSE)
     fail(DH2_EINVAL, "the matrix was compressed from a dense input: pass G");
   GeomDev g = geom(M, G, ld);
@@ -1792,7 +1800,7 @@ void rows_check(MatrixData& M, const int64_t* rows, int32_t nrows, const double2
   double2* bufs = (double2*)mem.alloc((2 * n + nrows) * sizeof(double2));
   double2 *xp = bufs, *y = bufs + n, *out = bufs + 2 * n;
   launch_gather_perm(x, M.d_perm, n, xp, st);
-  launch_direct(SRC_HELMHOLTZ, g, d_pos, nrows, xp, 0, out, st);
+  launch_direct(M.src, g, d_pos, nrows, xp, 0, out, st);
   launch_check("rows direct");
   matvec(M, 'N', x, y, st);
   std::vector<double2> hd(nrows), hy(n);

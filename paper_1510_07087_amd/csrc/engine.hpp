@@ -144,6 +144,7 @@ struct MatrixData {
   double* d_pts = nullptr;     // permuted n x 4
   double* d_cbox = nullptr;    // per cluster: box and largest weight
   int64_t* d_perm = nullptr;
+  double* d_nrm = nullptr;     // double layer: permuted n x 4 normals
   std::vector<double> w;       // original-order weights
   Side side[2];
   double* d_omega = nullptr;
@@ -159,9 +160,10 @@ struct MatrixData {
 
 std::shared_ptr<TreeData> make_tree(const double* pts, int64_t n, double kappa, const dh2_opts& o);
 std::shared_ptr<BlocksData> make_blocks(std::shared_ptr<TreeData> t, const dh2_opts& o);
+// nrm: host n x 3 unit normals in the original order (SRC_DLP only)
 std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> b, int src, const void* G,
                                      int64_t ld, const double* w, double eps, const dh2_opts& o,
-                                     hipStream_t st);
+                                     hipStream_t st, const double* nrm = nullptr);
 std::vector<std::unique_ptr<MatrixData>> compress_batch(
     const std::vector<std::shared_ptr<BlocksData>>& blks, const std::vector<const double*>& w,
     double eps, const dh2_opts& o, hipStream_t st, int nstreams);

@@ -180,10 +180,35 @@ __device__ __forceinline__ double2 dense_entry(const GeomDev& g, int64_t pi, int
   return make_double2(v.x, -v.y);
 }
 
+// Double layer (Section 7, DLP matrix, collocation form): the entry of G at
+// (x point p, y point q) is w_q (1 - i kappa r) exp(i kappa r)
+// <x_p - x_q, n_q> / (4 pi r^3), and 1/2 on the diagonal; G^* (side 1) takes
+// the row as the y point and conjugates.
+__device__ __forceinline__ double2 dlp_entry(const GeomDev& g, int64_t pi, int64_t pj, int side) {
+  if (pi == pj) return make_double2(0.5, 0.0);
+  const int64_t p = side == 0 ? pi : pj, q = side == 0 ? pj : pi;
+  const double* xp = g.pts + 4 * p;
+  const double* xq = g.pts + 4 * q;
+  const double* nq = g.nrm + 4 * q;
+  double dx = xp[0] - xq[0], dy = xp[1] - xq[1], dz = xp[2] - xq[2];
+  double r2 = dx * dx + dy * dy + dz * dz;
+  double ri = rsqrt_nr(r2);
+  double r = r2 * ri;
+  double s, c;
+  sincos_phase(g.kappa * r, s, c);
+  // (1 - i kappa r)(c + i s) = (c + kappa r s) + i (s - kappa r c)
+  double kr = g.kappa * r;
+  double a = xq[3] * kInv4Pi * (dx * nq[0] + dy * nq[1] + dz * nq[2]) * ri * ri * ri;
+  double re = a * (c + kr * s), im = a * (s - kr * c);
+  return make_double2(re, side == 0 ? im : -im);
+}
+
 template <int SRC>
 __device__ __forceinline__ double2 entry(const GeomDev& g, int64_t pi, int64_t pj, int side) {
   if constexpr (SRC == SRC_HELMHOLTZ)
     return helm_entry(g, pi, pj, side);
+  else if constexpr (SRC == SRC_DLP)
+    return dlp_entry(g, pi, pj, side);
   else
     return dense_entry(g, pi, pj, side);
 }
@@ -225,7 +250,7 @@ __global__ __launch_bounds__(256) void k_block_norm(GeomDev g, const int64_t* t_
   } else {
     for (int64_t i = to + ty; i < to + tl; i += 4)
       for (int64_t j = so + tx; j < so + sl; j += 64) {
-        double2 z = dense_entry(g, i, j, 0);
+        double2 z = entry<SRC>(g, i, j, 0);
         acc += z.x * z.x + z.y * z.y;
       }
   }
@@ -1307,7 +1332,9 @@ __global__ __launch_bounds__(256) void k_leaf_cols(GeomDev g, const ItemDev* ite
         const double* p = g.pts + 4 * pos;
         v = make_double4(p[0], p[1], p[2], en.scale * (side == 0 ? p[3] : 1.0) * kInv4Pi);
       } else {
-        v = make_double4(__longlong_as_double((long long)g.perm[pos]), 0.0, 0.0, en.scale);
+        // dense: original index; double layer: position
+        const int64_t id = SRC == SRC_DLP ? pos : g.perm[pos];
+        v = make_double4(__longlong_as_double((long long)id), 0.0, 0.0, en.scale);
       }
       out[en.col_start + q] = v;
     }
@@ -1330,7 +1357,7 @@ __device__ __forceinline__ RowData row_data(const GeomDev& g, const ItemDev& it,
       r.z = p[2];
       r.f = side == 1 ? p[3] : 1.0;
     } else {
-      r.x = __longlong_as_double((long long)g.perm[pos]);
+      r.x = __longlong_as_double((long long)(SRC == SRC_DLP ? pos : g.perm[pos]));
       r.f = 1.0;
     }
   }
@@ -1360,6 +1387,10 @@ __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw
       double a = f * ri;
       return make_double2(a * cs, side == 0 ? a * sn : -a * sn);
     }
+  } else if constexpr (SRC == SRC_DLP) {
+    int64_t i = (int64_t)__double_as_longlong(rw.x), j = (int64_t)__double_as_longlong(cc.x);
+    double2 v = dlp_entry(g, i, j, side);
+    return make_double2(v.x * f, v.y * f);
   } else {
     const double2* G = reinterpret_cast<const double2*>(g.G);
     int64_t i = (int64_t)__double_as_longlong(rw.x), j = (int64_t)__double_as_longlong(cc.x);
@@ -2237,6 +2268,9 @@ void launch_block_norm(int src, const GeomDev& g, const int64_t* t_off, const in
   if (src == SRC_HELMHOLTZ)
     hipLaunchKernelGGL(k_block_norm<SRC_HELMHOLTZ>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
                        t_off, t_len, s_off, s_len, nblocks, omega);
+  else if (src == SRC_DLP)
+    hipLaunchKernelGGL(k_block_norm<SRC_DLP>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
+                       t_off, t_len, s_off, s_len, nblocks, omega);
   else
     hipLaunchKernelGGL(k_block_norm<SRC_DENSE>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
                        t_off, t_len, s_off, s_len, nblocks, omega);
@@ -2248,6 +2282,9 @@ void launch_block_norm2(int src, const GeomDev& g, const int64_t* t_off, const i
   if (nblocks == 0) return;
   if (src == SRC_HELMHOLTZ)
     hipLaunchKernelGGL(k_block_norm2<SRC_HELMHOLTZ>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
+                       t_off, t_len, s_off, s_len, nblocks, max_iter, tol, omega);
+  else if (src == SRC_DLP)
+    hipLaunchKernelGGL(k_block_norm2<SRC_DLP>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
                        t_off, t_len, s_off, s_len, nblocks, max_iter, tol, omega);
   else
     hipLaunchKernelGGL(k_block_norm2<SRC_DENSE>, dim3((unsigned)nblocks), dim3(256), 0, st, g,
@@ -2282,6 +2319,9 @@ void launch_gram(int src, bool inner, bool mixed, const GeomDev& g, const ItemDe
     else
       hipLaunchKernelGGL((k_gram_leaf_w<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents,
                          units, nunits, side, partial);
+  } else if (src == SRC_DLP) {
+    hipLaunchKernelGGL((k_gram_leaf_w<SRC_DLP, false>), grid, blk, 0, st, g, items, ents, units,
+                       nunits, side, partial);
   } else {
     hipLaunchKernelGGL((k_gram_leaf_w<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents, units,
                        nunits, side, partial);
@@ -2321,6 +2361,9 @@ void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int
   if (src == SRC_HELMHOLTZ)
     hipLaunchKernelGGL(k_leaf_cols<SRC_HELMHOLTZ>, dim3(nl), dim3(256), 0, st, g, items, litems,
                        ents, side);
+  else if (src == SRC_DLP)
+    hipLaunchKernelGGL(k_leaf_cols<SRC_DLP>, dim3(nl), dim3(256), 0, st, g, items, litems, ents,
+                       side);
   else
     hipLaunchKernelGGL(k_leaf_cols<SRC_DENSE>, dim3(nl), dim3(256), 0, st, g, items, litems, ents,
                        side);
@@ -2391,6 +2434,9 @@ void launch_rprod_leaf(int src, bool mixed, const GeomDev& g, const ItemDev* ite
     else
       hipLaunchKernelGGL((k_rprod_leaf_w<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents,
                          units, side);
+  } else if (src == SRC_DLP) {
+    hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DLP, false>), grid, blk, 0, st, g, items, ents,
+                       units, side);
   } else {
     hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents,
                        units, side);
@@ -2505,6 +2551,9 @@ void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t*
   if (src == SRC_HELMHOLTZ)
     hipLaunchKernelGGL(k_near<SRC_HELMHOLTZ>, dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
                        t_len, s_off, s_len, out_off, out);
+  else if (src == SRC_DLP)
+    hipLaunchKernelGGL(k_near<SRC_DLP>, dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
+                       t_len, s_off, s_len, out_off, out);
   else
     hipLaunchKernelGGL(k_near<SRC_DENSE>, dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
                        t_len, s_off, s_len, out_off, out);
@@ -2557,6 +2606,9 @@ void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows
   if (nrows == 0) return;
   if (src == SRC_HELMHOLTZ)
     hipLaunchKernelGGL(k_direct<SRC_HELMHOLTZ>, dim3((unsigned)nrows), dim3(256), 0, st, g, rows,
+                       nrows, xp, adjoint, out);
+  else if (src == SRC_DLP)
+    hipLaunchKernelGGL(k_direct<SRC_DLP>, dim3((unsigned)nrows), dim3(256), 0, st, g, rows,
                        nrows, xp, adjoint, out);
   else
     hipLaunchKernelGGL(k_direct<SRC_DENSE>, dim3((unsigned)nrows), dim3(256), 0, st, g, rows,

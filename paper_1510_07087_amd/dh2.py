@@ -65,7 +65,8 @@ EXPORTED = [
     "dh2_opts_default", "dh2_last_error", "dh2_tree_build", "dh2_tree_free",
     "dh2_tree_get_info", "dh2_tree_export", "dh2_tree_directions", "dh2_blocks_build",
     "dh2_blocks_free", "dh2_blocks_get_info", "dh2_blocks_export", "dh2_blocks_colsets",
-    "dh2_compress_dense", "dh2_compress_helmholtz", "dh2_compress_batch", "dh2_matrix_free",
+    "dh2_compress_dense", "dh2_compress_helmholtz", "dh2_compress_helmholtz_dlp",
+    "dh2_compress_batch", "dh2_matrix_free",
     "dh2_matvec",
     "dh2_error_estimate", "dh2_rows_check", "dh2_get_stats", "dh2_basis_export",
     "dh2_coupling_export", "dh2_near_export", "dh2_release_cached_memory",
@@ -100,6 +101,7 @@ def lib():
         "dh2_blocks_colsets": (I32, [VP, I32, P(I32), P(I32), P(I64), P(I32), P(I32), P(I32)]),
         "dh2_compress_dense": (I32, [VP, VP, I64, D, P(Opts), VP, P(VP)]),
         "dh2_compress_helmholtz": (I32, [VP, P(D), D, P(Opts), VP, P(VP)]),
+        "dh2_compress_helmholtz_dlp": (I32, [VP, P(D), P(D), D, P(Opts), VP, P(VP)]),
         "dh2_compress_batch": (I32, [I32, P(VP), P(P(D)), D, P(Opts), VP, P(VP)]),
         "dh2_matrix_free": (None, [VP]),
         "dh2_matvec": (I32, [VP, C.c_char, I64, VP, VP, VP]),
@@ -257,6 +259,18 @@ def compress_helmholtz(b: Blocks, w, eps: float, o: Opts, stream=None) -> Matrix
     h = C.c_void_p()
     _check(lib().dh2_compress_helmholtz(b.h, _p(wa, C.c_double), float(eps), C.byref(o),
                                         _stream(stream), C.byref(h)))
+    return Matrix(h, keep=b)
+
+
+def compress_helmholtz_dlp(b: Blocks, w, normals, eps: float, o: Opts, stream=None) -> Matrix:
+    """Double-layer operator generated from points, weights and unit normals
+    (n x 3, original order); FP64 form."""
+    wa = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    na = np.ascontiguousarray(normals, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().dh2_compress_helmholtz_dlp(b.h, _p(wa, C.c_double), _p(na, C.c_double),
+                                            float(eps), C.byref(o), _stream(stream),
+                                            C.byref(h)))
     return Matrix(h, keep=b)
 
 
