@@ -29,7 +29,10 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_INT8_MFMA = 5.0e15
 # HBM bytes per launch of k_gram_i8<0> on the default workload: FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 (1 GiB copy calibration), profiles/compress_sphere131072_mixed.md
-TRAFFIC_GRAM_I8_LEAF = (2 * 1274170.2 + 305164.0) * 1024
+TRAFFIC_GRAM_I8_LEAF = (2 * 1274155.3 + 305164.0) * 1024
+# HBM bytes of all k_project_stacked launches of one compression on the default
+# workload (same counters and calibration, same profile)
+TRAFFIC_PROJECTION_STACKED = (2 * 9312310.5 + 5717289.25) * 1024
 
 
 def log(*a):
@@ -288,6 +291,12 @@ def main():
         work, peak, unit = st["flops_gram_leaf"], PEAK_FP64_MFMA, "TFLOP/s"
     achieved = work / st["t_gram_leaf"] if st["t_gram_leaf"] > 0 else 0.0
     pk_prj = PEAK_FP32_MFMA if head == "mixed" else PEAK_FP64_MFMA
+    # the stacked projection also against HBM: counter bytes per compression
+    prj_hbm = {}
+    if head == "mixed" and args.workload == "sphere131072" and st["t_prj"] > 0:
+        gbs = TRAFFIC_PROJECTION_STACKED / st["t_prj"] / 1e9
+        prj_hbm = {"traffic": TRAFFIC_PROJECTION_STACKED, "hbm_achieved_GBps": gbs,
+                   "hbm_frac": gbs / 8000.0}
     ach_prj = st["flops_prj"] / st["t_prj"] if st["t_prj"] > 0 else 0.0
     out = {
         "metric": METRIC,
@@ -316,7 +325,8 @@ def main():
                                            "by W, FP32 4x4x1 MFMA)" if head == "mixed" else
                                            "k_project_tiled (S_b = omega_b R|s W, FP64 MFMA)"),
                                 "achieved": ach_prj / 1e12, "peak": pk_prj / 1e12,
-                                "unit": "TFLOP/s", "frac": ach_prj / pk_prj},
+                                "unit": "TFLOP/s", "frac": ach_prj / pk_prj,
+                                **prj_hbm},
         "compression_s": {f: res[f]["s"] for f in res},
         "gflops": {f: res[f]["gflops"] for f in res},
         "rel_err_2": {f: res[f]["rel_err"] for f in res},
