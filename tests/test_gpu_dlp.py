@@ -131,3 +131,14 @@ def test_error_estimate_and_rows(dlp):
     rows = np.random.default_rng(5).choice(N, 16, replace=False)
     direct, approx, _ = dh2.rows_check(dlp["m"], rows, torch.from_numpy(x).to("cuda"))
     assert np.allclose(direct, (G @ x)[rows], rtol=0, atol=1e-12 * np.abs(G @ x).max())
+
+
+def test_dlp_rejects_mixed_form():
+    """The double layer runs in the FP64 form only."""
+    from paper_1510_07087_amd import dh2
+    p, nv, w = _surface("sphere")
+    o = dh2.opts(leaf_size=32, precision=dh2.MIXED)
+    b = dh2.blocks_build(dh2.tree_build(p, KAPPA, o), o)
+    with pytest.raises(dh2.DH2Error) as e:
+        dh2.compress_helmholtz_dlp(b, w, nv, EPS, o)
+    assert e.value.code == -5  # DH2_EUNSUPPORTED

@@ -60,3 +60,13 @@ def test_dlp_compression_error():
     G = Mx.dlp_dense_original(x, nv, w, 8.0)
     err = np.linalg.norm(G - D.reconstruct(cp), 2) / np.linalg.norm(G, 2)
     assert 1e-8 < err <= 1e-4
+
+
+def test_normals_are_outward_unit_vectors():
+    """The synthetic normals are unit vectors pointing away from the centre
+    (both surfaces are star-shaped about the origin)."""
+    x, _ = synth.ellipsoid(500)
+    for p_, n_ in ((x, synth.ellipsoid_normals(500)),
+                   (synth.fibonacci_sphere(500)[0], synth.sphere_normals(synth.fibonacci_sphere(500)[0]))):
+        assert np.allclose(np.linalg.norm(n_, axis=1), 1.0, atol=1e-15)
+        assert np.all(np.sum(p_ * n_, axis=1) > 0)
