@@ -212,8 +212,10 @@ dh2_status dh2_compress_helmholtz(dh2_blocks blocks, const double* w, double eps
  *   w       : host, n float64 weights (copied); NULL means 4*pi/n.
  *   normals : host, n x 3 row-major float64 unit normals in the ORIGINAL
  *             point order (copied).
- * FP64 form only (DH2_MIXED gives DH2_EUNSUPPORTED); errors otherwise as
- * for dh2_compress_helmholtz, EINVAL also for NULL or non-finite normals.  */
+ * Both forms; in the mixed form the double-layer entries are computed in
+ * FP64 and rounded to FP32 before the int8 slicing and the R-products.
+ * Errors as for dh2_compress_helmholtz, EINVAL also for NULL or non-finite
+ * normals.                                                                  */
 dh2_status dh2_compress_helmholtz_dlp(dh2_blocks blocks, const double* w,
                                       const double* normals, double eps,
                                       const dh2_opts* opts, void* stream,

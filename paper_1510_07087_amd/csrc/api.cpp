@@ -282,8 +282,6 @@ dh2_status dh2_compress_helmholtz_dlp(dh2_blocks b, const double* w, const doubl
                                       dh2_matrix* out) {
   DH2_TRY({
     check_compress_args(b, eps, opts, out);
-    if (opts->precision != DH2_FP64)
-      fail(DH2_EUNSUPPORTED, "the double layer is compressed in FP64 only");
     if (!normals) fail(DH2_EINVAL, "normals are NULL");
     int64_t n = b->d->tree->tr.n;
     for (int64_t i = 0; i < 3 * n; ++i)
@@ -291,6 +289,7 @@ dh2_status dh2_compress_helmholtz_dlp(dh2_blocks b, const double* w, const doubl
     if (w)
       for (int64_t i = 0; i < n; ++i)
         if (!(w[i] > 0) || !std::isfinite(w[i])) fail(DH2_EINVAL, "weights must be finite and > 0");
+    check_mixed_eps(opts, eps);
     auto m = compress(b->d, SRC_DLP, nullptr, 0, w, eps, *opts, stream_of(stream), normals);
     *out = new dh2_matrix_s{std::move(m)};
   })

@@ -793,11 +793,12 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       int32_t* d_ubegin = upload(mem, ubegin, st);
       tr_.mark("gram units", s, b, lv);
       tg.start();
-      const bool i8 = mixed && M.src == SRC_HELMHOLTZ;
+      const bool i8 = mixed && (M.src == SRC_HELMHOLTZ || M.src == SRC_DLP);
       if (nleafu > 0) {
         tgl.start();
         if (i8)
-          launch_gram_i8(false, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s, partial, st);
+          launch_gram_i8(false, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s, partial, st,
+                         M.src == SRC_DLP);
         else
           launch_gram(M.src, false, mixed, g, S.d_items, S.d_ents, d_units, nleafu, M.zeta, s,
                       partial, st);

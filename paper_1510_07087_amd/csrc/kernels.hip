@@ -1975,7 +1975,8 @@ __device__ __forceinline__ void i8_slice4(const float* v, float sc, unsigned* ou
   for (int p = 0; p < 4; ++p) out[p] = w[p];
 }
 
-template <int KIND>  // 0: generated leaf block rows, 1: non-leaf block rows from the sons' R
+template <int KIND>  // 0: generated leaf block rows, 1: non-leaf block rows from the sons' R,
+                     // 2: generated leaf block rows of the double layer
 __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev* items,
                                                  const EntDev* ents, const UnitDev* units,
                                                  int side, double zeta2, double2* partial) {
@@ -2002,10 +2003,11 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
   // ---- row data and row bounds ----
   for (int e = tid; e < ntile * 16; e += kI8Threads) {
     rmaxb[e] = 0u;
-    if constexpr (KIND == 0) rowd[e] = row_data<SRC_HELMHOLTZ>(g, it, row0(e >> 4) + (e & 15), side);
+    if constexpr (KIND != 1)
+      rowd[e] = row_data<KIND == 2 ? SRC_DLP : SRC_HELMHOLTZ>(g, it, row0(e >> 4) + (e & 15), side);
   }
   auto stage_cols = [&](int c, int buf) {
-    if constexpr (KIND == 0) {
+    if constexpr (KIND != 1) {
       if (tid < 64) {
         int64_t j = (int64_t)c * 64 + tid;
         cold[buf * 64 + tid] = (c < nch && j < ncols) ? it.cols[u.col_begin + j]
@@ -2029,7 +2031,24 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
     return nullptr;
   };
   __syncthreads();
-  if constexpr (KIND == 0) {
+  if constexpr (KIND == 2) {
+    // double layer: the largest component of every row over the unit's
+    // columns, from the entries themselves (a bound from the distances alone
+    // overestimates these rows many times, since <x - y, n(y)> is much
+    // smaller than |x - y| near the row point, and would waste slice bits)
+    const int nrow = ntile * 16, stride = kI8Threads / nrow;
+    if (tid < stride * nrow) {
+      const int rl = tid % nrow;
+      const RowData rw = rowd[rl];
+      double mx = 0.0;
+      if (rw.f != 0.0)
+        for (int64_t j = tid / nrow; j < ncols; j += stride) {
+          const double2 v = gen_entry<SRC_DLP, false>(g, rw, it.cols[u.col_begin + j], side);
+          mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+        }
+      if (mx > 0.0) atomicMax(&rmaxb[rl], __float_as_uint((float)mx));
+    }
+  } else if constexpr (KIND == 0) {
     // leaf rows: |entry| <= |f_i| scale_e wfac_e / (4 pi dist(x_i, box of s_e)) over
     // the column-set entries that meet the unit's column range
     __shared__ int64_t s_e0, s_e1;
@@ -2133,12 +2152,18 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
         int E = rexp[T * 16 + i];
         float sc = E > -100000 ? ldexpf(1.0f, 28 - E) : 0.0f;
         float vr[4], vi[4];
-        if constexpr (KIND == 0) {
+        if constexpr (KIND != 1) {
           const RowData rw = rowd[T * 16 + i];
           const double4* cc = cold + (c % 3) * 64 + 16 * gg + 4 * pp;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            float2 v = gen_entry_mx(g, rw, cc[q], side);
+            float2 v;
+            if constexpr (KIND == 0) {
+              v = gen_entry_mx(g, rw, cc[q], side);
+            } else {
+              const double2 d = gen_entry<SRC_DLP, false>(g, rw, cc[q], side);
+              v = make_float2((float)d.x, (float)d.y);
+            }
             vr[q] = v.x;
             vi[q] = v.y;
           }
@@ -2371,7 +2396,7 @@ void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int
 
 void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
                     const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
-                    hipStream_t st) {
+                    hipStream_t st, bool dlp) {
   if (nunits == 0) return;
   static std::once_flag attr;
   std::call_once(attr, [] {
@@ -2379,10 +2404,15 @@ void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const En
                         (int)kI8Lds);
     (void)hipFuncSetAttribute((const void*)k_gram_i8<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)kI8Lds);
+    (void)hipFuncSetAttribute((const void*)k_gram_i8<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)kI8Lds);
   });
   if (inner)
     hipLaunchKernelGGL(k_gram_i8<1>, dim3((unsigned)nunits), dim3(kI8Threads), kI8Lds, st, g, items,
                        ents, units, side, zeta * zeta, partial);
+  else if (dlp)
+    hipLaunchKernelGGL(k_gram_i8<2>, dim3((unsigned)nunits), dim3(kI8Threads), kI8Lds, st, g, items,
+                       ents, units, side, 1.0, partial);
   else
     hipLaunchKernelGGL(k_gram_i8<0>, dim3((unsigned)nunits), dim3(kI8Threads), kI8Lds, st, g, items,
                        ents, units, side, 1.0, partial);
@@ -2435,8 +2465,12 @@ void launch_rprod_leaf(int src, bool mixed, const GeomDev& g, const ItemDev* ite
       hipLaunchKernelGGL((k_rprod_leaf_w<SRC_HELMHOLTZ, false>), grid, blk, 0, st, g, items, ents,
                          units, side);
   } else if (src == SRC_DLP) {
-    hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DLP, false>), grid, blk, 0, st, g, items, ents,
-                       units, side);
+    if (mixed)
+      hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DLP, true>), grid, blk, 0, st, g, items, ents,
+                         units, side);
+    else
+      hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DLP, false>), grid, blk, 0, st, g, items, ents,
+                         units, side);
   } else {
     hipLaunchKernelGGL((k_rprod_leaf_w<SRC_DENSE, false>), grid, blk, 0, st, g, items, ents,
                        units, side);

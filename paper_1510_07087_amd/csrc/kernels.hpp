@@ -36,7 +36,7 @@ void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int
 // generated, non-leaf block rows from the sons' FP32 R).
 void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,
                     const UnitDev* units, int64_t nunits, double zeta, int side, double2* partial,
-                    hipStream_t st);
+                    hipStream_t st, bool dlp = false);
 // LDS bytes of the non-leaf R-product workgroup for an item (r rows, rank k)
 size_t rprod_inner_lds(bool mixed, int r, int k);
 size_t rprod_inner_lds_max();
