@@ -185,7 +185,8 @@ dh2_status dh2_blocks_colsets(dh2_blocks blocks, int32_t side, int32_t* item_t,
  *        G_ii = sqrt(w_i/pi)/2 + i kappa w_i/(4 pi).
  *   w  : host, n float64 weights (copied); NULL means 4*pi/n for all points.
  * opts->precision selects complex FP64 throughout (DH2_FP64) or the mixed
- * form (DH2_MIXED, dh2_compress_helmholtz and dh2_compress_batch only):
+ * form (DH2_MIXED; generated entries only: dh2_compress_helmholtz,
+ * dh2_compress_helmholtz_dlp and dh2_compress_batch):
  * entries with an FP64 phase reduction and FP32 polynomials, Gram matrices
  * of the weighted block rows from exact int8 slices of their rows (int32
  * accumulation on int8 MFMA, converted to FP64), R^T stored in complex FP32
