@@ -6,9 +6,13 @@ already on the device side of the call.  The default workload is the
 131072-point golden-spiral sphere, kappa = 64, leaf size 64, eps = 1e-4,
 eta1 = 20, eta2 = 5, entries generated on the fly.
 
-Prints ONE JSON line (the contract in the repository's README of the driver):
-metric/value/unit, roofline of the dominant kernel (the Gram kernel), and the
-CPU baseline (the FP64 oracle on a bounded sample of the same workload).
+Prints ONE JSON line: metric/value/unit (GFLOP/s = algorithmic flops of the
+compression -- 8 r^2 N per block row for the reduction, 8 k r N for the
+R-products, 8 k_t k_s #s per block for the projection -- over its seconds),
+the roofline of the dominant kernel (the leaf Gram kernel) and of the
+projection, with the counter figures of the committed profile when the
+kernels are the ones it was taken on, and the CPU baseline (the FP64 oracle
+timed per phase on smaller spheres, with the benchmark size extrapolated).
 """
 from __future__ import annotations
 
@@ -27,12 +31,44 @@ METRIC = "compression s & GFLOP/s, mixed vs FP64 form at equal eps, n=131072 kap
 PEAK_FP64_MFMA = 78.6e12   # MI355X dense matrix peaks (published)
 PEAK_FP32_MFMA = 157.3e12
 PEAK_INT8_MFMA = 5.0e15
-# HBM bytes per launch of k_gram_i8<0> on the default workload: FETCH_SIZE x 2 +
-# WRITE_SIZE x 1 (1 GiB copy calibration), profiles/compress_sphere131072_mixed.md
-TRAFFIC_GRAM_I8_LEAF = (2 * 1274155.3 + 305164.0) * 1024
-# HBM bytes of all k_project_stacked launches of one compression on the default
-# workload (same counters and calibration, same profile)
-TRAFFIC_PROJECTION_STACKED = (2 * 9312310.5 + 5717289.25) * 1024
+PEAK_HBM = 8.0e12
+# VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
+# 4 cycles at 2.4 GHz (16 lanes per SIMD and cycle)
+PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1510_07087_amd", "csrc", f)
+                  for f in ("kernels.hip", "common.hpp")]
+
+
+def sources_sha():
+    """First 16 hex digits of the SHA-256 of the kernel sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profile_figures(name):
+    """Counter figures of a committed profile summary (profiles/<name>.md):
+    its 'figures' block holds one 'key value' per line, e.g. the HBM bytes
+    per dispatch of a kernel.  Returns {} when the file is missing or when the
+    kernel sources changed since the counters were taken (the block records
+    their hash), since the figures then describe other code."""
+    path = os.path.join(PROFILES, name + ".md")
+    if not os.path.exists(path):
+        return {}
+    txt = open(path).read()
+    if "```figures" not in txt:
+        return {}
+    block = txt.split("```figures", 1)[1].split("```", 1)[0]
+    fig = {}
+    for line in block.strip().splitlines():
+        k, v = line.split(None, 1)
+        fig[k] = v.strip()
+    if fig.get("sources_sha256_16") != sources_sha():
+        return {}
+    return fig
 
 
 def log(*a):
@@ -59,46 +95,98 @@ def run_form(dh2, torch, blocks, w, eps, leaf, form, steps, warmup, groups):
     return m, st, times
 
 
-def cpu_baseline(points, w, kappa, leaf, eps, budget_s):
-    """The oracle on a bounded sample: leaf block rows of the row basis, in a
-    seeded random order, each with its block weights, weighted block row,
-    SVD and R product, until the time budget is used."""
+def _oracle_flops(plan, cp):
+    """Algorithmic real flops of a compression from the oracle's ranks, with
+    the counts of the hot-path table: per (t,c) of both bases 8 r^2 N for the
+    reduction and 8 k r N for R = Q^* A (r = #t for leaves, k1 + k2 above;
+    N = #F_tc), per admissible block 8 k_t k_s #s for the projection."""
+    tr, dr, bt = plan.tree, plan.dirs, plan.blocks
+    fl = 0.0
+    for basis, sets in ((cp.V, plan.rowsets), (cp.W, plan.colsets)):
+        for (t, c), k in basis.k.items():
+            N = float(sum(int(tr.size[s]) for (_, s, _) in sets.F[t][c]))
+            if tr.son1[t] < 0:
+                r = int(tr.size[t])
+            else:
+                cp_ = int(dr.sd[tr.level[t]][c])
+                r = sum(basis.k[(ts, cp_)] for ts in tr.sons(t))
+            fl += 8.0 * r * r * N + 8.0 * k * r * N
+    for b in range(len(bt.adm_t)):
+        t, s, c = int(bt.adm_t[b]), int(bt.adm_s[b]), int(bt.adm_c[b])
+        fl += 8.0 * cp.V.k[(t, c)] * cp.W.k[(s, c)] * int(tr.size[s])
+    return fl
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(budget_s, k_target, n_target):
+    """The FP64 oracle (NumPy/LAPACK, plan + weights + row basis + column basis
+    + projection + near field, exactly as the parity tests run it) timed per
+    phase on this host's cores: the 2048-point sphere (kappa 8, leaf 32, the
+    smallest workload) and, within the time budget, the 4608-point sphere
+    (kappa sqrt(n)/5.66, leaf 64, the leaf size of the benchmark workload).
+    The benchmark workload itself would take hours; its oracle time is
+    extrapolated from the larger timed run by keeping time / (n^2 k_max)
+    constant, as the paper observes for its own timings."""
     from threadpoolctl import threadpool_info
 
+    import synth
     from oracle import compress as OC
+    from oracle import dh2 as OD
     from oracle import matrix as OM
     from oracle import plan as OP
 
-    t_plan = time.perf_counter()
-    plan = OP.build_plan(points, kappa, leaf)
-    t_plan = time.perf_counter() - t_plan
-    M = OM.HelmholtzMatrix(points, w, kappa, plan.tree.perm)
-    tr, bt = plan.tree, plan.blocks
-    items = [(t, c) for t in range(tr.nc) if tr.son1[t] < 0 for c in plan.rowsets.used(t)]
-    order = np.random.default_rng(0).permutation(len(items))
-    omega = {}
-    flops, done = 0.0, 0
-    t0 = time.perf_counter()
-    for idx in order:
-        t, c = items[idx]
-        for (b, s, d) in plan.rowsets.F[t][c]:
-            if b not in omega:
-                omega[b] = np.linalg.norm(M.block(tr.rows(bt.adm_t[b]), tr.rows(bt.adm_s[b])))
-        A = OC.weighted_block_row(M, plan, plan.rowsets, t, c, omega, 2.0 / 3.0)
-        Q, sig, k = OC.truncated_left_singular(A, eps)
-        _ = Q.conj().T @ A
-        r, N = A.shape
-        flops += 4.0 * r * r * N + 8.0 * k * r * N
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
+    runs, last = {}, None
+    spent = 0.0
+    for name in ("sphere2048", "sphere4608"):
+        if runs and spent > 0.4 * budget_s:
             break
-    el = time.perf_counter() - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} of {len(items)} leaf block rows of the row basis "
-                      f"(weights, weighted block row, SVD, R product) in {el:.1f} s; "
-                      f"oracle plan {t_plan:.1f} s not timed",
-            "host_cpus": len(os.sched_getaffinity(0))}
+        p, w, kappa, leaf, eps = synth.workload(name)
+        t0 = time.perf_counter()
+        plan = OP.build_plan(p, kappa, leaf)
+        t1 = time.perf_counter()
+        M = OM.HelmholtzMatrix(p, w, kappa, plan.tree.perm)
+        omega = OC.block_weights(M, plan)
+        t2 = time.perf_counter()
+        V = OC.build_basis(M, plan, plan.rowsets, omega, eps, 2.0 / 3.0)
+        t3 = time.perf_counter()
+        W = OC.build_basis(OM.AdjointMatrix(M), plan, plan.colsets, omega, eps, 2.0 / 3.0)
+        t4 = time.perf_counter()
+        tr, bt = plan.tree, plan.blocks
+        S = [V.Qexp[(int(t), int(c))].conj().T @ M.block(tr.rows(t), tr.rows(s_))
+             @ W.Qexp[(int(s_), int(c))] for t, s_, c in zip(bt.adm_t, bt.adm_s, bt.adm_c)]
+        near = [M.block(tr.rows(t), tr.rows(s_)) for t, s_ in zip(bt.near_t, bt.near_s)]
+        t5 = time.perf_counter()
+        cp = OC.Compressed(plan, eps, 2.0 / 3.0, omega, V, W, S, near)
+        fl = _oracle_flops(plan, cp)
+        sto = OD.storage_stats(cp)
+        tot = t5 - t1
+        spent += t5 - t0
+        runs[name] = dict(n=len(p), kappa=kappa, leaf=leaf, eps=eps, t_plan=t1 - t0,
+                          t_weights=t2 - t1, t_row=t3 - t2, t_col=t4 - t3, t_prj=t5 - t4,
+                          t_total=tot, flops=fl, gflops=fl / tot / 1e9, k_max=sto["k_max"],
+                          mem_per_n_kib=sto["mem_per_n_kib"])
+        last = name
+        log(f"[bench] oracle {name}: {runs[name]}")
+    threads = max([q.get("num_threads", 1) for q in threadpool_info()] + [1])
+    L = runs[last]
+    t_extra = L["t_total"] * (n_target / L["n"]) ** 2 * (k_target / max(1, L["k_max"]))
+    return {"value": L["gflops"], "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"whole oracle compressions of {', '.join(runs)} (per-phase times below); "
+                      f"value = algorithmic flops / oracle seconds of {last}",
+            "host_cpus": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model(),
+            "blas_threads": int(threads), "runs": runs,
+            "extrapolated_s_benchmark_workload": t_extra,
+            "extrapolation": f"oracle seconds at n={n_target}, k_max={k_target} from {last} "
+                             f"with time / (n^2 k_max) held constant (not measured)"}
 
 
 def run_batch(args, dh2, torch, synth):
@@ -209,7 +297,7 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--groups", type=int, default=0)
     ap.add_argument("--err-iters", type=int, default=8)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", type=float, default=None,
                     help="HBM bytes per launch of the roofline kernel from the counter runs")
@@ -279,24 +367,40 @@ def main():
     r = res[head]
     st = r["stats"]
     nl = max(1, st["n_gram_leaf"])
-    traffic = args.traffic
+    # counter figures of the committed profile of this workload and form
+    # (empty when the kernels changed since they were taken)
+    fig = profile_figures(f"compress_{args.workload}_{head}")
     if head == "mixed":
-        # dominant kernel: the int8-sliced leaf Gram (k_gram_i8<0>)
+        # dominant kernel: the int8-sliced leaf Gram (k_gram_i8<0>); its work is
+        # the reduction's algorithmic 8 r^2 N real flops, against the peak of the
+        # MFMA it runs on (int8); the emulation's own int8 operations per flop
+        # are reported beside it
         kern = "k_gram_i8<0> (leaf Gram matrices, exact int8 slices on int8 MFMA)"
-        work, peak, unit = st["ops_gram_leaf_i8"], PEAK_INT8_MFMA, "TOP/s"
-        if traffic is None and args.workload == "sphere131072":
-            traffic = TRAFFIC_GRAM_I8_LEAF
+        peak, unit, key = PEAK_INT8_MFMA, "TOP/s", "k_gram_i8_0"
+        extra = {"int8_ops_per_flop": st["ops_gram_leaf_i8"] / max(1.0, st["flops_gram_leaf"])}
     else:
         kern = "k_gram_leaf_w (leaf Gram matrices on FP64 MFMA)"
-        work, peak, unit = st["flops_gram_leaf"], PEAK_FP64_MFMA, "TFLOP/s"
+        peak, unit, key = PEAK_FP64_MFMA, "TFLOP/s", "k_gram_leaf_w"
+        extra = {}
+    work = st["flops_gram_leaf"]
     achieved = work / st["t_gram_leaf"] if st["t_gram_leaf"] > 0 else 0.0
+    traffic = args.traffic
+    if traffic is None and f"{key}_hbm_bytes_per_dispatch" in fig:
+        traffic = float(fig[f"{key}_hbm_bytes_per_dispatch"])
+    if f"{key}_valu_insts_per_compression" in fig and st["t_gram_leaf"] > 0:
+        # VALU view of the same launches: wave instructions issued (counter run)
+        # over this run's event-timed durations, against the issue ceiling
+        extra["valu_issue_frac"] = (float(fig[f"{key}_valu_insts_per_compression"]) /
+                                    st["t_gram_leaf"] / PEAK_VALU_WAVE_INSTS)
+    if fig:
+        extra["profile"] = f"profiles/compress_{args.workload}_{head}.md"
     pk_prj = PEAK_FP32_MFMA if head == "mixed" else PEAK_FP64_MFMA
     # the stacked projection also against HBM: counter bytes per compression
     prj_hbm = {}
-    if head == "mixed" and args.workload == "sphere131072" and st["t_prj"] > 0:
-        gbs = TRAFFIC_PROJECTION_STACKED / st["t_prj"] / 1e9
-        prj_hbm = {"traffic": TRAFFIC_PROJECTION_STACKED, "hbm_achieved_GBps": gbs,
-                   "hbm_frac": gbs / 8000.0}
+    if "project_hbm_bytes_per_compression" in fig and st["t_prj"] > 0:
+        pb = float(fig["project_hbm_bytes_per_compression"])
+        prj_hbm = {"traffic": pb, "hbm_achieved_GBps": pb / st["t_prj"] / 1e9,
+                   "hbm_frac": pb / st["t_prj"] / PEAK_HBM}
     ach_prj = st["flops_prj"] / st["t_prj"] if st["t_prj"] > 0 else 0.0
     out = {
         "metric": METRIC,
@@ -319,7 +423,9 @@ def main():
                      "frac": achieved / peak, "traffic": traffic,
                      "launches": st["n_gram_leaf"],
                      "avg_launch_ms": st["t_gram_leaf"] / nl * 1e3,
-                     "work_per_launch": work / nl},
+                     "work_per_launch": work / nl,
+                     "work": "8 r^2 N real flops per leaf block row (r = #t, N = #F_tc)",
+                     **extra},
         "roofline_projection": {"bound": "mfma",
                                 "kernel": ("k_project_stacked (S_b = omega_b R|s W, stacked "
                                            "by W, FP32 4x4x1 MFMA)" if head == "mixed" else
@@ -340,7 +446,7 @@ def main():
     if "mixed" in res and "fp64" in res:
         out["speedup_mixed_vs_fp64"] = res["fp64"]["s"] / res["mixed"]["s"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, w, kappa, leaf, eps, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_budget, st["k_max"], n)
     print(json.dumps(out), flush=True)
 
 

@@ -61,7 +61,8 @@ typedef struct dh2_blocks_s* dh2_blocks; /* block tree, column sets          */
 typedef struct dh2_matrix_s* dh2_matrix; /* compressed DH2 representation    */
 
 /* Parameters.  Defaults (dh2_opts_default): leaf_size 32, eta1 20, eta2 5,
- * zeta 2/3, precision DH2_FP64, no memory cap, automatic subtree grouping.
+ * zeta 2/3, precision DH2_FP64, no memory cap, automatic subtree grouping,
+ * block weights DH2_WEIGHTS_BLOCK, 60 Jacobi sweeps at most.
  *   eta1 : direction parameter; D_l covers the unit sphere with
  *          max distance eta1/(kappa*delta_l) (Section 3).
  *   eta2 : admissibility parameter of conditions (b) and (c).
@@ -80,7 +81,10 @@ typedef struct dh2_matrix_s* dh2_matrix; /* compressed DH2 representation    */
  *          block gets (sum over admissible b' of ||G|_b'||_F^2)^(1/2), a
  *          global-relative tolerance.  DH2_WEIGHTS_SPECTRAL (2):
  *          omega_b = ||G|_b||_2 (power method on the device, clusters of at
- *          most 1024 points, else DH2_EUNSUPPORTED).  */
+ *          most 1024 points, else DH2_EUNSUPPORTED).
+ *   max_sweeps : limit of the one-sided Jacobi sweeps of each small SVD
+ *          (0 = 60); a factorisation that still rotates after that many
+ *          sweeps makes the compression fail with DH2_ENOTCONV.  */
 typedef struct {
   int32_t leaf_size;
   double eta1;
@@ -92,6 +96,7 @@ typedef struct {
   int32_t groups;
   int64_t max_device_bytes;
   int32_t weights;
+  int32_t max_sweeps;
 } dh2_opts;
 
 typedef enum { DH2_WEIGHTS_BLOCK = 0, DH2_WEIGHTS_GLOBAL = 1, DH2_WEIGHTS_SPECTRAL = 2 } dh2_weights;
@@ -281,13 +286,17 @@ typedef struct {
   double mem_bytes;        /* bases + transfer + coupling + near field      */
   double mem_per_n_kib;    /* KiB per degree of freedom (complex128 words)  */
   double t_row, t_col, t_prj, t_near, t_total; /* device seconds per phase   */
-  double flops_row, flops_col, flops_prj;      /* algorithmic real flops     */
+  /* algorithmic real flops (a complex multiply-add counts 8): per (t,c) with
+   * r factor rows, N columns and rank k, 8 r^2 N for the reduction of the
+   * block row and 8 k r N for R = Q^* A (columns actually formed); per
+   * admissible block 8 k_t k_s #s for the projection                        */
+  double flops_row, flops_col, flops_prj;
   double flops_gram, flops_rprod;              /* split of the basis flops   */
   double t_gram_kernel;    /* summed device seconds of the Gram kernels      */
   int32_t groups;          /* subtree groups used                            */
   int32_t precision;
   /* the leaf Gram kernel alone (the largest single kernel): algorithmic
-   * flops 4 r^2 N summed over its launches, summed device seconds measured
+   * flops 8 r^2 N summed over its launches, summed device seconds measured
    * with events on the call's stream, and the number of launches          */
   double flops_gram_leaf, t_gram_leaf;
   int32_t n_gram_leaf;

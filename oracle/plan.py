@@ -331,19 +331,3 @@ def build_plan(points: np.ndarray, kappa: float, leaf_size: int, eta1: float = 2
     rows = build_column_sets(tree, dr, own_row, bt.adm_c, bt.adm_s)
     cols = build_column_sets(tree, dr, own_col, bt.adm_c, bt.adm_t)
     return Plan(tree, dr, bt, rows, cols, kappa, eta1, eta2)
-
-
-def plan_stats(plan: Plan) -> dict:
-    """Counts used to describe a plan (blocks, near-field share, directions)."""
-    tr, bt = plan.tree, plan.blocks
-    near_entries = int(sum(tr.size[t] * tr.size[s] for t, s in zip(bt.near_t, bt.near_s)))
-    adm_entries = int(sum(tr.size[t] * tr.size[s] for t, s in zip(bt.adm_t, bt.adm_s)))
-    items = sum(len(f) for f in plan.rowsets.F)
-    cols = sum(sum(tr.size[s] for (_, s, _) in lst) * tr.size[t]
-               for t, f in enumerate(plan.rowsets.F) for lst in f.values())
-    return dict(
-        n=tr.n, clusters=tr.nc, depth=tr.depth, adm=len(bt.adm_t), near=len(bt.near_t),
-        near_fraction=near_entries / tr.n ** 2, adm_fraction=adm_entries / tr.n ** 2,
-        dirs_per_level=[len(d) for d in plan.dirs.dirs], row_items=items,
-        row_entries=int(cols),
-    )

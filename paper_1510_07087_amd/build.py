@@ -61,5 +61,56 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SAN_DIR = os.path.join(BUILD, "sanitize")
+SAN_LIB = os.path.join(SAN_DIR, "libdh2_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+             "-fno-omit-frame-pointer"]
+
+
+def build_sanitized() -> str:
+    """Host code (plan, engine, C ABI) built with g++ under AddressSanitizer
+    and UndefinedBehaviorSanitizer, linked with the regular gfx950 kernel
+    object; returns the library's path.  Load it with DH2_LIBRARY set to that
+    path and the sanitizer runtimes preloaded (see sanitizer_env)."""
+    kobj = os.path.join(BUILD, "kernels.hip.o")
+    if not os.path.exists(kobj):
+        build()
+    os.makedirs(SAN_DIR, exist_ok=True)
+    objs = []
+    for src in ("plan.cpp", "engine.cpp", "api.cpp"):
+        obj = os.path.join(SAN_DIR, src + ".o")
+        cmd = ["g++", "-O1", "-g", "-std=c++17", "-fPIC", "-ffp-contract=off",
+               "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-I", CSRC] + SAN_FLAGS + \
+              ["-c", os.path.join(CSRC, src), "-o", obj]
+        p = subprocess.run(cmd, capture_output=True, text=True)
+        if p.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{p.stdout}{p.stderr}")
+        objs.append(obj)
+    cmd = ["g++", "-shared", "-o", SAN_LIB] + objs + [kobj, "-L/opt/rocm/lib", "-lamdhip64",
+                                                     "-Wl,-rpath,/opt/rocm/lib"] + SAN_FLAGS
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{p.stdout}{p.stderr}")
+    return SAN_LIB
+
+
+def sanitizer_env() -> dict:
+    """Environment for a Python process that loads the sanitizer build: the
+    runtimes preloaded (libstdc++ too, so that the exception interceptor finds
+    its target), leak checks off (the interpreter's own allocations)."""
+    def lib(name):
+        return subprocess.run(["g++", f"-print-file-name={name}"], capture_output=True,
+                              text=True).stdout.strip()
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = " ".join([lib("libasan.so"), lib("libubsan.so"), lib("libstdc++.so")])
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
+    env["DH2_LIBRARY"] = SAN_LIB
+    return env
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized())
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -58,6 +58,7 @@ static void check_opts(const dh2_opts* o) {
   if (o->weights != DH2_WEIGHTS_BLOCK && o->weights != DH2_WEIGHTS_GLOBAL &&
       o->weights != DH2_WEIGHTS_SPECTRAL)
     fail(DH2_EINVAL, "unknown block weights");
+  if (o->max_sweeps < 0) fail(DH2_EINVAL, "max_sweeps must be >= 0");
 }
 
 static hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -93,6 +94,7 @@ void dh2_opts_default(dh2_opts* o) {
   o->groups = 0;
   o->max_device_bytes = 0;
   o->weights = DH2_WEIGHTS_BLOCK;
+  o->max_sweeps = 0;
 }
 
 const char* dh2_last_error(void) { return g_err.c_str(); }

@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <condition_variable>
 #include <mutex>
 #include <numeric>
 #include <random>
@@ -397,10 +398,18 @@ struct MatvecPlan {
   double2* yp = nullptr;
   double2* xh = nullptr;  // sized for the larger side
   double2* yh = nullptr;
+  int64_t maxh = 0;       // coefficients of the larger side
+};
+
+// work vectors of one product: permuted x and y (n each), coefficients of the
+// source and destination bases (maxh each)
+struct MatvecBufs {
+  double2 *xp, *yp, *xh, *yh;
 };
 
 MatrixData::~MatrixData() {
   mv.reset();
+  mem_col.reset();
   mem.reset();
 }
 
@@ -653,12 +662,48 @@ static int64_t npairs_of(int r) {
   return (int64_t)nt * (nt + 1) / 2;
 }
 
+// Hand-over between the two sweeps when they run at the same time: the
+// column sweep expands each level's column basis right after forming it and
+// marks the level ready (host flag plus an event on its stream); the row
+// sweep waits for that before projecting the blocks of the level (admissible
+// blocks join clusters of one level).
+struct LevelSync {
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<int> ready;         // per level
+  std::vector<hipEvent_t> ev;     // per level, recorded on the column stream
+  bool abort = false;             // the column sweep failed
+  ~LevelSync() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void mark(int lv, hipStream_t st) {
+    hip_check(hipEventRecord(ev[lv], st), "level event");
+    std::lock_guard<std::mutex> lk(mu);
+    ready[lv] = 1;
+    cv.notify_all();
+  }
+  void fail_all() {
+    std::lock_guard<std::mutex> lk(mu);
+    abort = true;
+    cv.notify_all();
+  }
+  void wait(int lv, hipStream_t st) {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [&] { return ready[lv] || abort; });
+    if (!ready[lv]) fail(DH2_EDEVICE, "column sweep failed");
+    lk.unlock();
+    hip_check(hipStreamWaitEvent(st, ev[lv], 0), "level wait");
+  }
+};
+
+static void expand_level(MatrixData& M, int s, int32_t lv, hipStream_t st, DevMem& mem);
+
 static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepStats& ss,
-                  int32_t* d_status) {
+                  int32_t* d_status, DevMem& mem, LevelSync* sync = nullptr) {
   const BlocksData& B = *M.blk;
   const ClusterTree& tr = B.tree->tr;
   Side& S = M.side[s];
-  DevMem& mem = *M.mem;
   PhaseTimer tg(st), tp(st), tgl(st);
   double2* partial = nullptr;
   size_t partial_cap = 0;
@@ -669,7 +714,10 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
     void* R_prev = nullptr;
     for (int32_t lv = tr.depth; lv >= 0; --lv) {
       auto [lo, hi] = S.P->range[b][lv];
-      if (lo == hi) continue;
+      if (lo == hi) {
+        if (sync && s == 1) sync->mark(lv, st);
+        continue;
+      }
       int32_t n = hi - lo;
       tr_.mark("level start", s, b, lv);
       // factor sizes of non-leaf items from the sons' ranks
@@ -772,8 +820,11 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
               slot += (int64_t)npair * 256;
               units.push_back(u);
             }
+            // the reduction's algorithmic work, 8 r^2 N real flops per block row
+            // (a Householder reduction of the N x r block row; the Gram matrix
+            // computes its Hermitian half, 4 r^2 N)
             double rr = it.r;
-            double fl = 4.0 * rr * rr * (double)std::min(width, it.N - c0);
+            double fl = 8.0 * rr * rr * (double)std::min(width, it.N - c0);
             ss.flops_gram += fl;
             if (it.leaf) ss.flops_gram_leaf += fl;
             // int8 slicing: 4 real products x 15 slice pairs x 2 ops on the lower triangle
@@ -843,8 +894,8 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         int32_t* d_fl = upload(mem, all, st);
         int64_t off = 0;
         for (int c = 0; c < kFacClasses; ++c) {
-          launch_factor(S.d_items, d_fl + off, (int32_t)fl[c].size(), rm[c], M.eps, 60, d_status,
-                        st);
+          launch_factor(S.d_items, d_fl + off, (int32_t)fl[c].size(), rm[c], M.eps,
+                        M.max_sweeps, d_status, st);
           off += (int64_t)fl[c].size();
         }
         launch_check("factor");
@@ -940,8 +991,14 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       launch_check("rprod (non-leaf)");
       if (trace_on()) hip_check(hipStreamSynchronize(st), "trace sync");
       tr_.mark("rprod", s, b, lv);
+      // column sweep run beside the row sweep: expand this level's basis now
+      if (sync && s == 1) {
+        expand_level(M, s, lv, st, mem);
+        sync->mark(lv, st);
+      }
       // projection of the admissible blocks of this level (row sweep)
       if (s == 0) {
+        if (sync) sync->wait(lv, st);
         // tasks in the plan's order (sorted by column item), coupling
         // matrices in that order; tiled kernel for ks <= 64, one launch per
         // (row tiles per pass, column tiles); ranks above 64 by the generic
@@ -1111,75 +1168,76 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
   ss.t_gram_leaf += tgl.total();
 }
 
-// expanded column bases, level by level from the leaves
-static void expand_side(MatrixData& M, int s, hipStream_t st) {
-  const ClusterTree& tr = M.blk->tree->tr;
+// Expanded column basis of one level (W_sc as an explicit #s x k matrix,
+// from the sons' expanded bases and the transfer matrices; leaves: Q), and in
+// the mixed form its complex FP32 copy for the projection.
+static void expand_level(MatrixData& M, int s, int32_t lv, hipStream_t st, DevMem& mem) {
   Side& S = M.side[s];
-  DevMem& mem = *M.mem;
-  for (int32_t lv = tr.depth; lv >= 0; --lv) {
-    std::vector<int32_t> idx;
-    int64_t total = 0;
-    for (int32_t b = 0; b < M.nbatch; ++b)
-      for (int32_t i = S.P->range[b][lv].first; i < S.P->range[b][lv].second; ++i) {
-        idx.push_back(i);
-        if (!S.items[i].leaf) total += (int64_t)S.items[i].m * S.items[i].k;
-      }
-    if (idx.empty()) continue;
-    double2* arena = total ? (double2*)mem.alloc(total * sizeof(double2)) : nullptr;
-    if (arena) S.keep.push_back(arena);
-    std::vector<ExpandDev> tasks;
-    int64_t o = 0;
-    for (int32_t i : idx) {
-      ItemDev& it = S.items[i];
-      if (it.leaf) {
-        S.wexp[i] = it.Q;
-        continue;
-      }
-      S.wexp[i] = arena + o;
-      int64_t rowo = 0;
-      int32_t koff = 0;
-      for (int q = 0; q < 2; ++q) {
-        const ItemDev& so = S.items[it.son[q]];
-        ExpandDev ed{};
-        ed.src = S.wexp[it.son[q]];
-        ed.E = it.Q + (int64_t)koff * it.k;
-        ed.dst = arena + o + rowo * it.k;
-        ed.rows = so.m;
-        ed.ks = so.k;
-        ed.k = it.k;
-        if (it.k > 0) tasks.push_back(ed);
-        rowo += so.m;
-        koff += so.k;
-      }
-      o += (int64_t)it.m * it.k;
+  std::vector<int32_t> idx;
+  int64_t total = 0, total32 = 0;
+  for (int32_t b = 0; b < M.nbatch; ++b)
+    for (int32_t i = S.P->range[b][lv].first; i < S.P->range[b][lv].second; ++i) {
+      idx.push_back(i);
+      if (!S.items[i].leaf) total += (int64_t)S.items[i].m * S.items[i].k;
+      total32 += (int64_t)S.items[i].m * S.items[i].k;
     }
-    ExpandDev* d_tasks = upload(mem, tasks, st);
-    launch_expand(d_tasks, (int64_t)tasks.size(), st);
-    launch_check("expand");
-    mem.sync(st, "expand sync");
-    mem.release(d_tasks);
+  if (idx.empty()) return;
+  if (S.wexp32.size() != (size_t)S.nitems) S.wexp32.assign(S.nitems, nullptr);
+  double2* arena = total ? (double2*)mem.alloc(total * sizeof(double2)) : nullptr;
+  if (arena) S.keep.push_back(arena);
+  std::vector<ExpandDev> tasks;
+  int64_t o = 0;
+  for (int32_t i : idx) {
+    ItemDev& it = S.items[i];
+    if (it.leaf) {
+      S.wexp[i] = it.Q;
+      continue;
+    }
+    S.wexp[i] = arena + o;
+    int64_t rowo = 0;
+    int32_t koff = 0;
+    for (int q = 0; q < 2; ++q) {
+      const ItemDev& so = S.items[it.son[q]];
+      ExpandDev ed{};
+      ed.src = S.wexp[it.son[q]];
+      ed.E = it.Q + (int64_t)koff * it.k;
+      ed.dst = arena + o + rowo * it.k;
+      ed.rows = so.m;
+      ed.ks = so.k;
+      ed.k = it.k;
+      if (it.k > 0) tasks.push_back(ed);
+      rowo += so.m;
+      koff += so.k;
+    }
+    o += (int64_t)it.m * it.k;
   }
+  ExpandDev* d_tasks = upload(mem, tasks, st);
+  launch_expand(d_tasks, (int64_t)tasks.size(), st);
+  launch_check("expand");
+  mem.release(d_tasks);
   if (M.precision == DH2_MIXED) {
-    // complex FP32 copies of the expanded bases for the FP32 projection
-    int64_t total = 0;
-    for (int32_t i = 0; i < S.nitems; ++i) total += (int64_t)S.items[i].m * S.items[i].k;
-    float2* arena = (float2*)mem.alloc(std::max<int64_t>(1, total) * sizeof(float2));
-    S.keep.push_back(arena);
-    S.wexp32.assign(S.nitems, nullptr);
-    std::vector<CvtDev> tasks;
-    int64_t o = 0;
-    for (int32_t i = 0; i < S.nitems; ++i) {
+    float2* a32 = (float2*)mem.alloc(std::max<int64_t>(1, total32) * sizeof(float2));
+    S.keep.push_back(a32);
+    std::vector<CvtDev> ct;
+    int64_t o32 = 0;
+    for (int32_t i : idx) {
       int64_t cnt = (int64_t)S.items[i].m * S.items[i].k;
-      S.wexp32[i] = arena + o;
-      if (cnt > 0) tasks.push_back(CvtDev{S.wexp[i], arena + o, cnt});
-      o += cnt;
+      S.wexp32[i] = a32 + o32;
+      if (cnt > 0) ct.push_back(CvtDev{S.wexp[i], a32 + o32, cnt});
+      o32 += cnt;
     }
-    CvtDev* d_tasks = upload(mem, tasks, st);
-    launch_cvt(d_tasks, (int64_t)tasks.size(), st);
+    CvtDev* d_ct = upload(mem, ct, st);
+    launch_cvt(d_ct, (int64_t)ct.size(), st);
     launch_check("basis conversion");
-    mem.sync(st, "conversion sync");
-    mem.release(d_tasks);
+    mem.release(d_ct);
   }
+}
+
+// expanded column bases, level by level from the leaves
+static void expand_side(MatrixData& M, int s, hipStream_t st, DevMem& mem) {
+  const ClusterTree& tr = M.blk->tree->tr;
+  for (int32_t lv = tr.depth; lv >= 0; --lv) expand_level(M, s, lv, st, mem);
+  mem.sync(st, "expand sync");
 }
 
 std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, const void* G,
@@ -1192,6 +1250,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   M.eps = eps;
   M.zeta = o.zeta;
   M.precision = o.precision;
+  M.max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 60;
   M.mem = std::make_unique<DevMem>(o.max_device_bytes);
   const ClusterTree& tr = blk->tree->tr;
   const BlockTree& bt = blk->bt;
@@ -1289,6 +1348,10 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   int32_t nb = o.groups > 0 ? o.groups : (int32_t)std::ceil(peak / std::max(1.0, budget));
   nb = std::max(1, std::min(nb, std::max(1, ngroups)));
   M.nbatch = nb;
+  // the row and column sweeps run at the same time, each on its own stream,
+  // when the sweep is one batch and the R matrices of both sides fit (with
+  // a memory cap they run one after the other so that the cap stays exact)
+  M.concurrent = nb == 1 && o.max_device_bytes == 0 && 2.0 * peak <= budget;
   std::vector<int32_t> batch_of(tr.nc(), 0);
   {
     double tot = std::accumulate(grpN.begin(), grpN.end(), 0.0), cum = 0;
@@ -1315,10 +1378,11 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   M.S_rows.assign(nadm, 0);
   M.S_cols.assign(nadm, 0);
 
-  // status[0]: error bits of the factorisation; status[1], status[2]: Jacobi
-  // sweeps and factorisations (statistics)
-  int32_t* d_status = (int32_t*)mem.alloc(4 * sizeof(int32_t));
-  hip_check(hipMemsetAsync(d_status, 0, 4 * sizeof(int32_t), st), "memset");
+  // per side (row sweep at 0, column sweep at 4): status[0]: error bits of
+  // the factorisation; status[1], status[2]: Jacobi sweeps and factorisations
+  // (statistics)
+  int32_t* d_status = (int32_t*)mem.alloc(8 * sizeof(int32_t));
+  hip_check(hipMemsetAsync(d_status, 0, 8 * sizeof(int32_t), st), "memset");
 
   // block weights and column scales
   hip_check(hipEventRecord(e0, st), "event");
@@ -1370,20 +1434,91 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   hip_check(hipEventElapsedTime(&ms_w, e0, e1), "event");
 
   SweepStats ss_col, ss_row;
-  hip_check(hipEventRecord(e0, st), "event");
-  sweep(M, 1, g, st, ss_col, d_status);
-  expand_side(M, 1, st);
-  hip_check(hipEventRecord(e1, st), "event");
-  hip_check(hipEventSynchronize(e1), "event");
-  float ms_col = 0;
-  hip_check(hipEventElapsedTime(&ms_col, e0, e1), "event");
-
-  hip_check(hipEventRecord(e0, st), "event");
-  sweep(M, 0, g, st, ss_row, d_status);
-  hip_check(hipEventRecord(e1, st), "event");
-  hip_check(hipEventSynchronize(e1), "event");
-  float ms_row = 0;
-  hip_check(hipEventElapsedTime(&ms_row, e0, e1), "event");
+  float ms_col = 0, ms_row = 0, ms_sweeps = 0;
+  if (!M.concurrent) {
+    // column basis (expanded), then the row basis with the projection
+    hip_check(hipEventRecord(e0, st), "event");
+    sweep(M, 1, g, st, ss_col, d_status + 4, mem);
+    expand_side(M, 1, st, mem);
+    hip_check(hipEventRecord(e1, st), "event");
+    hip_check(hipEventSynchronize(e1), "event");
+    hip_check(hipEventElapsedTime(&ms_col, e0, e1), "event");
+    hip_check(hipEventRecord(e0, st), "event");
+    sweep(M, 0, g, st, ss_row, d_status, mem);
+    hip_check(hipEventRecord(e1, st), "event");
+    hip_check(hipEventSynchronize(e1), "event");
+    hip_check(hipEventElapsedTime(&ms_row, e0, e1), "event");
+    ms_sweeps = ms_col + ms_row;
+  } else {
+    // both sweeps at once: the column sweep on a second stream (default
+    // priority) driven by a second host thread with its own device-memory
+    // owner; the row sweep projects each level once the column sweep has
+    // expanded it.  Kernels of the two sweeps fill each other's idle time
+    // (small factorisations, rank read-backs, launch tails).
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    LevelSync ls;
+    ls.ready.assign(tr.depth + 1, 0);
+    ls.ev.assign(tr.depth + 1, nullptr);
+    for (auto& e : ls.ev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    hipStream_t sc = nullptr;
+    hip_check(hipStreamCreateWithFlags(&sc, hipStreamNonBlocking), "stream create");
+    hipEvent_t c0 = nullptr, c1 = nullptr, r1 = nullptr;
+    struct Cleanup {
+      hipStream_t s;
+      hipEvent_t e[3];
+      ~Cleanup() {
+        if (s) {
+          (void)hipStreamSynchronize(s);
+          (void)hipStreamDestroy(s);
+        }
+        for (hipEvent_t x : e)
+          if (x) (void)hipEventDestroy(x);
+      }
+    } cleanup{sc, {nullptr, nullptr, nullptr}};
+    hip_check(hipEventCreate(&c0), "event");
+    cleanup.e[0] = c0;
+    hip_check(hipEventCreate(&c1), "event");
+    cleanup.e[1] = c1;
+    hip_check(hipEventCreate(&r1), "event");
+    cleanup.e[2] = r1;
+    hip_check(hipEventRecord(e0, st), "event");
+    hip_check(hipStreamWaitEvent(sc, e0, 0), "stream wait");
+    hip_check(hipEventRecord(c0, sc), "event");
+    M.mem_col = std::make_unique<DevMem>(0);
+    Error cerr{DH2_OK, ""};
+    std::thread th([&] {
+      try {
+        hip_check(hipSetDevice(dev), "hipSetDevice");
+        M.mem_col->begin_staging();
+        sweep(M, 1, g, sc, ss_col, d_status + 4, *M.mem_col, &ls);
+        hip_check(hipEventRecord(c1, sc), "event");
+        M.mem_col->end_staging(sc);
+      } catch (const Error& e) {
+        cerr = e;
+      } catch (const std::bad_alloc&) {
+        cerr = Error{DH2_ENOMEM, "host allocation failed"};
+      } catch (const std::exception& e) {
+        cerr = Error{DH2_EDEVICE, e.what()};
+      }
+      if (cerr.code != DH2_OK) ls.fail_all();
+    });
+    try {
+      sweep(M, 0, g, st, ss_row, d_status, mem, &ls);
+    } catch (...) {
+      th.join();
+      throw;
+    }
+    th.join();
+    if (cerr.code != DH2_OK) fail(cerr.code, cerr.msg);
+    hip_check(hipEventRecord(r1, st), "event");
+    hip_check(hipStreamWaitEvent(st, c1, 0), "stream wait");
+    hip_check(hipEventRecord(e1, st), "event");
+    hip_check(hipEventSynchronize(e1), "event");
+    hip_check(hipEventElapsedTime(&ms_sweeps, e0, e1), "event");
+    hip_check(hipEventElapsedTime(&ms_col, c0, c1), "event");
+    hip_check(hipEventElapsedTime(&ms_row, e0, r1), "event");
+  }
 
   // near field
   hip_check(hipEventRecord(e0, st), "event");
@@ -1424,10 +1559,12 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (trace_on()) {
-    int32_t stat[4];
-    copy_from(stat, d_status, 4, st);
-    std::fprintf(stderr, "[dh2 trace] factorisations %d, mean Jacobi sweeps %.2f\n", stat[2],
-                 stat[2] ? (double)stat[1] / stat[2] : 0.0);
+    int32_t stat[8];
+    copy_from(stat, d_status, 8, st);
+    std::fprintf(stderr, "[dh2 trace] factorisations %d, mean Jacobi sweeps %.2f, %s sweeps\n",
+                 stat[2] + stat[6],
+                 stat[2] + stat[6] ? (double)(stat[1] + stat[5]) / (stat[2] + stat[6]) : 0.0,
+                 M.concurrent ? "concurrent" : "sequential");
   }
   mem.release(d_status);
   // the dense matrix is borrowed only for this call
@@ -1457,7 +1594,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   S.t_prj = ss_row.t_prj;
   S.t_row = ms_row * 1e-3 - ss_row.t_prj;
   S.t_near = ms_near * 1e-3;
-  S.t_total = (ms_w + ms_col + ms_row + ms_near) * 1e-3;
+  S.t_total = (ms_w + ms_sweeps + ms_near) * 1e-3;
   S.flops_row = ss_row.flops_gram + ss_row.flops_rprod;
   S.flops_col = ss_col.flops_gram + ss_col.flops_rprod;
   S.flops_prj = ss_row.flops_prj;
@@ -1666,11 +1803,13 @@ static void build_mv(MatrixData& M, hipStream_t st) {
   P->yp = (double2*)mem.alloc(n * sizeof(double2));
   P->xh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * sizeof(double2));
   P->yh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * sizeof(double2));
+  P->maxh = maxh;
   M.mv = std::move(P);
 }
 
-void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st) {
-  if (!M.mv) build_mv(M, st);
+// one product into the given work vectors (no allocation, no wait)
+static void matvec_core(MatrixData& M, char op, const double2* x, double2* y,
+                        const MatvecBufs& w, hipStream_t st) {
   MatvecPlan& P = *M.mv;
   const ClusterTree& tr = M.blk->tree->tr;
   int64_t n = tr.n;
@@ -1680,20 +1819,27 @@ void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st
   Side& Bs = M.side[dst_side];
   SideMV& VA = P.s[src_side];
   SideMV& VB = P.s[dst_side];
-  launch_gather_perm(x, M.d_perm, n, P.xp, st);
-  launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, P.xp, P.xh, st);
+  launch_gather_perm(x, M.d_perm, n, w.xp, st);
+  launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, w.xp, w.xh, st);
   for (size_t q = 0; q < VA.d_fwd_lvl.size(); ++q)
-    launch_fwd_inner(A.d_items, VA.d_fwd_lvl[q], VA.fwd_count[q], VA.d_hoff, P.xh, st);
+    launch_fwd_inner(A.d_items, VA.d_fwd_lvl[q], VA.fwd_count[q], VA.d_hoff, w.xh, st);
   launch_coupling(Bs.d_items, Bs.nitems, VB.d_cbegin, VB.d_cblock, VB.d_cpartner, P.d_Sptr,
-                  P.d_Srows, P.d_Scols, VA.d_hoff, P.xh, VB.d_hoff, P.yh, adj, st);
+                  P.d_Srows, P.d_Scols, VA.d_hoff, w.xh, VB.d_hoff, w.yh, adj, st);
   for (size_t l = 0; l < VB.d_bl_items.size(); ++l)
     launch_bwd_inner(Bs.d_items, VB.d_bl_items[l], VB.bl_count[l], VB.d_bl_fbegin[l],
-                     VB.d_bl_fitem[l], VB.d_bl_fson[l], VB.d_hoff, P.yh, st);
+                     VB.d_bl_fitem[l], VB.d_bl_fson[l], VB.d_hoff, w.yh, st);
   launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near, VB.d_hoff,
-                  P.yh, P.xp, P.yp, adj, st);
-  launch_scatter_perm(P.yp, M.d_perm, n, y, st);
+                  w.yh, w.xp, w.yp, adj, st);
+  launch_scatter_perm(w.yp, M.d_perm, n, y, st);
   launch_check("matvec");
 }
+
+void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st) {
+  if (!M.mv) build_mv(M, st);
+  MatvecPlan& P = *M.mv;
+  matvec_core(M, op, x, y, MatvecBufs{P.xp, P.yp, P.xh, P.yh}, st);
+}
+
 
 // ---------------------------------------------------------------------------
 // error measures

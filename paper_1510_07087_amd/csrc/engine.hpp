@@ -135,11 +135,16 @@ struct MatrixData {
   std::shared_ptr<BlocksData> blk;
   std::shared_ptr<PlanCache> plan;
   std::unique_ptr<DevMem> mem;
+  // device memory of the column sweep when it runs beside the row sweep (its
+  // own owner, since it queues work on another stream)
+  std::unique_ptr<DevMem> mem_col;
+  bool concurrent = false;     // the two sweeps ran at the same time
   int src = SRC_HELMHOLTZ;
   int precision = DH2_FP64;
   double eps = 0, zeta = 0;
   int32_t nbatch = 1;
   int32_t lmin = 0;
+  int32_t max_sweeps = 60;     // Jacobi sweep limit of the small SVDs
   // device geometry
   double* d_pts = nullptr;     // permuted n x 4
   double* d_cbox = nullptr;    // per cluster: box and largest weight

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdh2.so")
+# DH2_LIBRARY may name another build of the same library (the sanitizer
+# build of build.py); by default the in-tree libdh2.so
+LIB_PATH = os.environ.get("DH2_LIBRARY") or os.path.join(_HERE, "libdh2.so")
 
 FP64, MIXED = 0, 1
 WEIGHTS_BLOCK, WEIGHTS_GLOBAL, WEIGHTS_SPECTRAL = 0, 1, 2
@@ -34,7 +36,7 @@ class Opts(C.Structure):
                 ("zeta", C.c_double), ("precision", C.c_int32),
                 ("lowfreq_zero_dir", C.c_int32), ("standard_only", C.c_int32),
                 ("groups", C.c_int32), ("max_device_bytes", C.c_int64),
-                ("weights", C.c_int32)]
+                ("weights", C.c_int32), ("max_sweeps", C.c_int32)]
 
 
 class TreeInfo(C.Structure):

@@ -62,6 +62,7 @@ def test_opts_layout_matches_library():
     assert (o.leaf_size, o.eta1, o.eta2, o.precision, o.weights) == (32, 20.0, 5.0, dh2.FP64,
                                                                       dh2.WEIGHTS_BLOCK)
     assert abs(o.zeta - 2.0 / 3.0) < 1e-16 and o.max_device_bytes == 0 and o.groups == 0
+    assert o.max_sweeps == 0
 
 
 def test_invalid_options_rejected():
@@ -69,7 +70,8 @@ def test_invalid_options_rejected():
     import numpy as np
     from paper_1510_07087_amd import dh2
     pts = np.random.default_rng(0).standard_normal((8, 3))
-    for kw in (dict(weights=7), dict(eta2=0.0), dict(zeta=0.8), dict(leaf_size=0)):
+    for kw in (dict(weights=7), dict(eta2=0.0), dict(zeta=0.8), dict(leaf_size=0),
+               dict(max_sweeps=-1)):
         with pytest.raises(dh2.DH2Error) as e:
             dh2.tree_build(pts, 1.0, dh2.opts(**kw))
         assert e.value.code == -1, kw  # DH2_EINVAL

@@ -78,7 +78,11 @@ def test_singular_values_and_ranks(dlp):
         for key, sig_ref in basis_ref.sigma.items():
             k, _, sig = data[key]
             fro2 = float(np.sum(sig_ref ** 2))
-            tl = 1e-13 * fro2 + 1e-4 * EPS ** 2
+            # rounding band plus the pivoted Cholesky's cut: the Schur
+            # complement it leaves has diagonal below tau = max(1e-4 eps^2 / r,
+            # 64 u max M_ii) and norm at most its trace r tau (Weyl's theorem)
+            tl = 1e-13 * fro2 + max(1e-4 * EPS ** 2,
+                                    64 * 2.220446049250313e-16 * len(sig_ref) * fro2)
             s_ref = np.zeros(len(sig))
             s_ref[:min(len(sig_ref), len(sig))] = sig_ref[:len(sig)]
             big = s_ref > EPS

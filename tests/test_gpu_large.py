@@ -1,11 +1,15 @@
 """The larger workloads at their full sizes, in the launch configuration of
 the benchmark: sampled leaf block rows of both bases against the oracle
-(singular values, ranks, projectors), the global error by power iteration,
+(singular values, ranks, projectors), sampled block rows one level above
+the leaves against G_hat formed by definition from the library's son bases,
+the global error by power iteration,
 16 rows against the direct O(n^2) FP64 sum, and for the mixed form the
 deviation from the FP64 form.
 
 Tolerances are those of the n = 2048 parity tests (see test_gpu_parity):
-FP64 |sigma_gpu^2 - sigma^2| <= 1e-13 ||A||_F^2 + 1e-10 sigma^2; mixed
+FP64 |sigma_gpu^2 - sigma^2| <= 1e-13 ||A||_F^2 + 1e-10 sigma^2 (plus the
+pivoted Cholesky's cut max(1e-4 eps^2, 64 u r ||A||_F^2) above the leaves,
+see test_gpu_groups); mixed
 |sigma_gpu - sigma| <= 2e-7 ||A||_F; ranks equal outside that band around
 eps; global error <= 1.1 eps."""
 import numpy as np
@@ -21,7 +25,7 @@ pytestmark = pytest.mark.gpu
 
 ZETA = 2.0 / 3.0
 CASES = [("sphere32768", "fp64"), ("ellip32768", "fp64"), ("ellip32768", "mixed"),
-         ("ellip32768e6", "fp64"), ("sphere131072", "mixed")]
+         ("ellip32768e6", "fp64"), ("sphere131072", "mixed"), ("sphere131072", "fp64")]
 _cache = {}
 
 
@@ -98,6 +102,76 @@ def _sampled_leaf_rows(pr, m, form, nsample, seed):
     return worst
 
 
+def _sampled_inner_rows(pr, m, form, nsample, seed):
+    """Block rows of clusters whose sons are leaves: G_hat_tc formed by
+    definition from the library's exported son bases and the oracle's
+    weighted block row, [Q_t1^* G^w|t1; Q_t2^* G^w|t2] (Section 6), against the
+    library's singular values, rank and projector of [E_t1c; E_t2c]."""
+    from paper_1510_07087_amd import dh2
+    plan, M, eps = pr["plan"], pr["M"], pr["eps"]
+    tr, bt, dr = plan.tree, plan.blocks, plan.dirs
+    rng = np.random.default_rng(seed)
+    worst, done = 0.0, 0
+    for side in (0, 1):
+        sets = plan.rowsets if side == 0 else plan.colsets
+        ex = dh2.basis_export(m, side)
+        index = {(int(t), int(c)): i for i, (t, c) in enumerate(zip(ex["item_t"], ex["item_c"]))}
+
+        def mat(i):
+            r, k, mo = int(ex["item_r"][i]), int(ex["item_k"][i]), int(ex["mat_off"][i])
+            return ex["mat"][mo:mo + r * k].reshape(r, k)
+
+        cand = [(t, c) for (t, c) in index if tr.son1[t] >= 0
+                and tr.son1[tr.son1[t]] < 0 and tr.son1[tr.son2[t]] < 0]
+        pick = rng.choice(len(cand), size=min(nsample, len(cand)), replace=False)
+        Mo = M if side == 0 else OM.AdjointMatrix(M)
+        for q in pick:
+            t, c = cand[q]
+            omega = {}
+            for (b, s, d) in sets.F[t][c]:
+                if b not in omega:
+                    omega[b] = np.linalg.norm(M.block(tr.rows(bt.adm_t[b]), tr.rows(bt.adm_s[b])))
+            A = OC.weighted_block_row(Mo, plan, sets, t, c, omega, ZETA)
+            cp = int(dr.sd[tr.level[t]][c])
+            parts = []
+            for ts in tr.sons(t):
+                loc = tr.rows(ts) - tr.off[t]
+                parts.append(mat(index[(ts, cp)]).conj().T @ A[loc, :])
+            Ghat = np.vstack(parts)
+            U, sig, k = OC.truncated_left_singular(Ghat, eps)
+            i = index[(t, c)]
+            r, kg = int(ex["item_r"][i]), int(ex["item_k"][i])
+            assert r == Ghat.shape[0]
+            so = int(ex["sig_off"][i])
+            sg = ex["sigma"][so:so + r]
+            fro = float(np.sqrt(np.sum(sig ** 2)))
+            n_ = min(len(sg), len(sig))
+            big = sig[:n_] > eps
+            if form == "mixed":
+                d = np.abs(sg[:n_][big] - sig[:n_][big]) / fro
+                assert np.all(d <= 2e-7), (side, t, c, d.max())
+                tie = np.any(np.abs(sig - eps) <= 2e-7 * fro)
+                tl = 2.0 * sig[0] * 2e-7 * fro + 1e-13 * fro ** 2
+            else:
+                tl = 1e-13 * fro ** 2 + max(1e-4 * eps ** 2, 64 * 2.220446049250313e-16 * r * fro ** 2)
+                d = np.abs(sg[:n_][big] ** 2 - sig[:n_][big] ** 2)
+                assert np.all(d <= tl + 1e-10 * sig[:n_][big] ** 2), (side, t, c)
+                d = d / fro ** 2
+                tie = np.any(np.abs(sig ** 2 - eps ** 2) <= tl + 1e-10 * eps ** 2)
+            worst = max(worst, float(d.max()) if d.size else 0.0)
+            done += 1
+            if tie:
+                assert abs(kg - k) <= 1
+                continue
+            assert kg == k, (side, t, c, kg, k)
+            if k:
+                P = mat(i) @ mat(i).conj().T - U[:, :k] @ U[:, :k].conj().T
+                gap = sig[k - 1] ** 2 - (sig[k] ** 2 if k < len(sig) else 0.0)
+                assert np.linalg.norm(P, 2) <= 10 * tl / gap + 1e-10, (side, t, c)
+    assert done > 0
+    return worst
+
+
 @pytest.mark.parametrize("name,form", CASES)
 def test_large_workload(name, form):
     from paper_1510_07087_amd import dh2
@@ -107,6 +181,13 @@ def test_large_workload(name, form):
     m = _compress(pr, form)
     worst = _sampled_leaf_rows(pr, m, form, 12, 7)
     print(f"[gpu large] {name} {form}: sampled leaf rows agree (worst {worst:.2e})", flush=True)
+    worst = _sampled_inner_rows(pr, m, form, 6, 8)
+    print(f"[gpu large] {name} {form}: sampled rows above the leaves agree (worst {worst:.2e})",
+          flush=True)
+    st0 = dh2.stats(m)
+    if name == "sphere131072" and form == "fp64":
+        # the benchmark's FP64 run sweeps the subtrees in groups
+        print(f"[gpu large] {name} {form}: groups {st0['groups']}", flush=True)
     err = dh2.error_estimate(m, None, iters=8, seed=1)
     rows = np.random.default_rng(5).choice(n, 16, replace=False)
     x = torch.from_numpy(synth.complex_gaussian(n, 6)).to("cuda")

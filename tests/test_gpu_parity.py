@@ -227,13 +227,36 @@ def test_rows_check(problem, gpu):
 
 
 def test_stats(problem, gpu):
+    """Block counts, k_max and storage (Mem/n, the paper's KiB per degree of
+    freedom) against the oracle; the storage also against a word count from
+    the library's own exported ranks and blocks."""
+    from oracle import dh2 as OD
     from paper_1510_07087_amd import dh2
     st = dh2.stats(gpu["m"])
-    ref = problem["ref"]
-    assert st["nadm"] == len(problem["plan"].blocks.adm_t)
+    ref, plan = problem["ref"], problem["plan"]
+    tr, bt = plan.tree, plan.blocks
+    assert st["nadm"] == len(bt.adm_t) and st["nnear"] == len(bt.near_t)
     kref = max(list(ref.V.k.values()) + list(ref.W.k.values()))
     assert abs(st["k_max"] - kref) <= 1
     assert st["t_total"] > 0 and st["flops_row"] > 0 and st["flops_col"] > 0
+    # words: leaf bases #t x k, transfer matrices (k1 + k2) x k, couplings
+    # k_t x k_s, near-field blocks #t x #s (complex128 each)
+    words = 0
+    for data in (gpu["dv"], gpu["dw"]):
+        for (t, c), (k, mat, sig) in data.items():
+            r = tr.size[t] if tr.son1[t] < 0 else mat.shape[0]
+            assert mat.shape == (r, k)
+            words += r * k
+    words += sum(S.size for S in gpu["S"])
+    words += sum(int(tr.size[t]) * int(tr.size[s]) for t, s in zip(bt.near_t, bt.near_s))
+    assert st["mem_bytes"] == 16.0 * words
+    assert st["k_max"] == max(k for data in (gpu["dv"], gpu["dw"]) for (k, _, _) in data.values())
+    so = OD.storage_stats(ref)
+    print(f"[gpu parity] {gpu['mode']}: Mem/n {st['mem_per_n_kib']:.4f} KiB, oracle "
+          f"{so['mem_per_n_kib']:.4f}; k_max {st['k_max']} oracle {so['k_max']}", flush=True)
+    # equal up to the few rank ties (+-1 rank on < 5 % of the items)
+    assert abs(st["mem_per_n_kib"] - so["mem_per_n_kib"]) <= 2e-3 * so["mem_per_n_kib"]
+    assert abs(st["k_max"] - so["k_max"]) <= 1
 
 
 def test_mixed_at_smallest_supported_eps(problem):

@@ -108,10 +108,13 @@ def test_singular_values_and_ranks(problem, gpu):
                 tie = np.any(np.abs(sig_ref - EPS) <= MIXED_SIGMA * np.sqrt(fro2))
             else:
                 # Gram eigenvalues: relative rounding band, plus the cut of
-                # the pivoted Cholesky (remaining diagonal below 1e-4 eps^2 / r,
-                # at most 1e-4 eps^2 in all), which dominates for the small
-                # weighted block rows of global weights
-                tl = 1e-13 * fro2 + 1e-4 * EPS ** 2
+                # the pivoted Cholesky, which dominates for the small weighted
+                # block rows of global weights: it stops once the remaining
+                # diagonal is below tau = max(1e-4 eps^2 / r, 64 u max M_ii),
+                # leaving a positive semidefinite Schur complement of norm at
+                # most its trace r tau, so (Weyl) no eigenvalue moves by more
+                r = len(sig_ref)
+                tl = 1e-13 * fro2 + max(1e-4 * EPS ** 2, 64 * 2.220446049250313e-16 * r * fro2)
                 d = np.abs(sig[big] ** 2 - s_ref[big] ** 2)
                 assert np.all(d <= tl + 1e-10 * s_ref[big] ** 2), (key, d.max(), tl)
                 tie = np.any(np.abs(sig_ref ** 2 - EPS ** 2) <= tl + 1e-10 * EPS ** 2)

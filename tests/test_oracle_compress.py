@@ -381,3 +381,57 @@ def test_spectral_weights_block_bound(small_sphere):
         # the weight is the block's largest singular value
         assert abs(np.linalg.svd(Gb, compute_uv=False)[0] - cs.omega[b]) <= 1e-13 * cs.omega[b]
     assert sum(cs.V.k.values()) >= sum(cf.V.k.values())
+
+
+def _words_from_ranks(pl, cp):
+    """Storage in complex words counted from the ranks and block lists only:
+    leaf bases #t x k, transfer matrices (sum of the sons' ranks) x k,
+    couplings k_t x k_s, near-field blocks #t x #s."""
+    tr, dr, bt = pl.tree, pl.dirs, pl.blocks
+    words = 0
+    for basis in (cp.V, cp.W):
+        for (t, c), k in basis.k.items():
+            if tr.son1[t] < 0:
+                words += int(tr.size[t]) * k
+            else:
+                cp_ = int(dr.sd[tr.level[t]][c])
+                words += sum(basis.k[(ts, cp_)] for ts in tr.sons(t)) * k
+    for b in range(len(bt.adm_t)):
+        t, s, c = int(bt.adm_t[b]), int(bt.adm_s[b]), int(bt.adm_c[b])
+        words += cp.V.k[(t, c)] * cp.W.k[(s, c)]
+    for t, s in zip(bt.near_t, bt.near_s):
+        words += int(tr.size[t]) * int(tr.size[s])
+    return words
+
+
+def test_storage_stats_word_count(sphere):
+    """storage_stats (k_max, Mem/n in KiB per degree of freedom, the paper's
+    storage column) equals the count from the ranks and the block lists."""
+    p, w, pl, M, cp, G = sphere
+    st = D.storage_stats(cp)
+    words = _words_from_ranks(pl, cp)
+    assert math.isclose(st["mem_per_n_kib"], words * 16 / 1024 / pl.tree.n, rel_tol=1e-14)
+    assert st["k_max"] == max(list(cp.V.k.values()) + list(cp.W.k.values()))
+    assert st["k_max"] > 0
+
+
+def test_storage_stats_closed_forms():
+    """Two closed forms on the 512-point sphere: with a threshold above every
+    singular value all ranks are 0 and only the near field is stored; with
+    an admissibility parameter so small that no block is admissible the near
+    field is the whole matrix, n^2 words, i.e. 16 n / 1024 KiB per point."""
+    p, w = synth.fibonacci_sphere(512)
+    pl = P.build_plan(p, 6.0, 16)
+    M = Mx.HelmholtzMatrix(p, w, 6.0, pl.tree.perm)
+    cp = C.compress(M, pl, 1e10, ZETA)
+    st = D.storage_stats(cp)
+    tr, bt = pl.tree, pl.blocks
+    near = sum(int(tr.size[t]) * int(tr.size[s]) for t, s in zip(bt.near_t, bt.near_s))
+    assert len(bt.adm_t) > 0 and st["k_max"] == 0
+    assert math.isclose(st["mem_per_n_kib"], near * 16 / 1024 / 512, rel_tol=1e-14)
+    pl0 = P.build_plan(p, 6.0, 16, eta2=1e-9)
+    assert len(pl0.blocks.adm_t) == 0
+    cp0 = C.compress(Mx.HelmholtzMatrix(p, w, 6.0, pl0.tree.perm), pl0, EPS, ZETA)
+    st0 = D.storage_stats(cp0)
+    assert st0["k_max"] == 0
+    assert math.isclose(st0["mem_per_n_kib"], 16 * 512 / 1024, rel_tol=1e-14)
