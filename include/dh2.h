@@ -257,6 +257,23 @@ void dh2_release_cached_memory(void);
 dh2_status dh2_matvec(dh2_matrix m, char op, int64_t nrhs, const void* x,
                       void* y, void* stream);
 
+/* Allocation-free variant of dh2_matvec, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, layout and result as dh2_matvec;
+ * it calls no hipMalloc, hipFree or allocating routine.
+ *   - Its work vectors (permuted x and y, n complex each, and the basis
+ *     coefficients of the larger side, twice) live in a static device array
+ *     of 64 MiB that the library holds on every device it runs on until the
+ *     process ends.  A matrix whose work vectors exceed it is refused with
+ *     DH2_EUNSUPPORTED (about n = 10^6 points at the benchmark's ranks).
+ *   - The product's index lists are built by the first dh2_matvec on the
+ *     matrix; before that this call returns DH2_EINVAL.
+ *   - The work is only enqueued on `stream` (no wait); y is complete when the
+ *     stream reaches this point.  Calls that overlap on one device share the
+ *     array and race: serialise them on one stream.                        */
+dh2_status dh2_matvec_noalloc(dh2_matrix m, char op, int64_t nrhs, const void* x,
+                              void* y, void* stream);
+
 /* Relative spectral error ||G - G~||_2 / ||G||_2 by the power method on
  * A^*A (Section 7), started from a seeded complex Gaussian vector; stops after
  * `iters` iterations or when the Rayleigh quotient changes by < 1e-4.

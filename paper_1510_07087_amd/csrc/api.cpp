@@ -337,6 +337,16 @@ dh2_status dh2_matvec(dh2_matrix m, char op, int64_t nrhs, const void* x, void* 
   })
 }
 
+dh2_status dh2_matvec_noalloc(dh2_matrix m, char op, int64_t nrhs, const void* x, void* y,
+                              void* stream) {
+  DH2_TRY({
+    if (!m || !x || !y) fail(DH2_EINVAL, "NULL argument");
+    if (op != 'N' && op != 'C' && op != 'n' && op != 'c') fail(DH2_EINVAL, "op must be N or C");
+    if (nrhs < 0) fail(DH2_EINVAL, "nrhs must be >= 0");
+    matvec_noalloc(*m->d, op, nrhs, (const double2*)x, (double2*)y, stream_of(stream));
+  })
+}
+
 dh2_status dh2_error_estimate(dh2_matrix m, const void* G, int64_t ld, int32_t iters,
                               uint64_t seed, double* rel_err, void* stream) {
   DH2_TRY({

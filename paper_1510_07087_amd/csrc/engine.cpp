@@ -1840,6 +1840,33 @@ void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st
   matvec_core(M, op, x, y, MatvecBufs{P.xp, P.yp, P.xh, P.yh}, st);
 }
 
+// The same product with its work vectors in the library's static scratch
+// array: no device allocation and no wait.  The plan of the product (its
+// index lists) must exist already; the first dh2_matvec on the matrix builds
+// it.  Calls that overlap on one device share the array and race.
+void matvec_noalloc(MatrixData& M, char op, int64_t nrhs, const double2* x, double2* y,
+                    hipStream_t st) {
+  if (!M.mv)
+    fail(DH2_EINVAL, "the matrix has no matvec plan yet: call dh2_matvec on it once first");
+  const int64_t n = M.blk->tree->tr.n;
+  const int64_t maxh = std::max<int64_t>(1, M.mv->maxh);
+  // 256-byte aligned parts: xp, yp (n each), xh, yh (maxh each)
+  auto part = [](int64_t cnt) { return ((size_t)cnt * sizeof(double2) + 255) / 256 * 256; };
+  const size_t need = 2 * part(n) + 2 * part(maxh);
+  if (need > noalloc_scratch_bytes())
+    fail(DH2_EUNSUPPORTED, "the allocation-free product needs " + std::to_string(need) +
+                               " bytes of scratch, more than the library's " +
+                               std::to_string(noalloc_scratch_bytes()));
+  void* base = nullptr;
+  hip_check(noalloc_scratch(&base), "scratch address");
+  char* p = static_cast<char*>(base);
+  MatvecBufs w;
+  w.xp = (double2*)p;
+  w.yp = (double2*)(p + part(n));
+  w.xh = (double2*)(p + 2 * part(n));
+  w.yh = (double2*)(p + 2 * part(n) + part(maxh));
+  for (int64_t q = 0; q < nrhs; ++q) matvec_core(M, op, x + q * n, y + q * n, w, st);
+}
 
 // ---------------------------------------------------------------------------
 // error measures

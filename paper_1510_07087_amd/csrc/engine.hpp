@@ -173,6 +173,10 @@ std::vector<std::unique_ptr<MatrixData>> compress_batch(
     const std::vector<std::shared_ptr<BlocksData>>& blks, const std::vector<const double*>& w,
     double eps, const dh2_opts& o, hipStream_t st, int nstreams);
 void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st);
+// nrhs products with the work vectors in the static scratch array (no
+// allocation, no wait); needs the matvec plan built by an earlier matvec()
+void matvec_noalloc(MatrixData& M, char op, int64_t nrhs, const double2* x, double2* y,
+                    hipStream_t st);
 double error_estimate(MatrixData& M, const void* G, int64_t ld, int iters, uint64_t seed,
                       hipStream_t st);
 void rows_check(MatrixData& M, const int64_t* rows, int32_t nrows, const double2* x,

@@ -2593,6 +2593,34 @@ void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t*
                        t_len, s_off, s_len, out_off, out);
 }
 
+// Scratch memory of the allocation-free matrix-vector product: one array per
+// device (its own copy on every GPU the library runs on), held until the
+// process ends.  Host code uses the device address returned by
+// noalloc_scratch(), never the array's name.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+size_t noalloc_scratch_bytes() { return kScratchBytes; }
+
+hipError_t noalloc_scratch(void** out) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDev] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
 void launch_gather_perm(const double2* x, const int64_t* perm, int64_t n, double2* xp,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, perm, n, xp);

@@ -66,6 +66,10 @@ void launch_project_tiled(bool mixed, int ni, int nj, bool split, const ProjDev*
 void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
                  const int64_t* s_off, const int64_t* s_len, const int64_t* out_off,
                  int64_t nblocks, double2* out, hipStream_t st);
+// Device address of this device's scratch array for the allocation-free
+// matrix-vector product (looked up once per device), and its size in bytes.
+hipError_t noalloc_scratch(void** out);
+size_t noalloc_scratch_bytes();
 void launch_gather_perm(const double2* x, const int64_t* perm, int64_t n, double2* xp,
                         hipStream_t st);
 void launch_scatter_perm(const double2* yp, const int64_t* perm, int64_t n, double2* y,

@@ -69,7 +69,7 @@ EXPORTED = [
     "dh2_blocks_free", "dh2_blocks_get_info", "dh2_blocks_export", "dh2_blocks_colsets",
     "dh2_compress_dense", "dh2_compress_helmholtz", "dh2_compress_helmholtz_dlp",
     "dh2_compress_batch", "dh2_matrix_free",
-    "dh2_matvec",
+    "dh2_matvec", "dh2_matvec_noalloc",
     "dh2_error_estimate", "dh2_rows_check", "dh2_get_stats", "dh2_basis_export",
     "dh2_coupling_export", "dh2_near_export", "dh2_release_cached_memory",
 ]
@@ -107,6 +107,7 @@ def lib():
         "dh2_compress_batch": (I32, [I32, P(VP), P(P(D)), D, P(Opts), VP, P(VP)]),
         "dh2_matrix_free": (None, [VP]),
         "dh2_matvec": (I32, [VP, C.c_char, I64, VP, VP, VP]),
+        "dh2_matvec_noalloc": (I32, [VP, C.c_char, I64, VP, VP, VP]),
         "dh2_error_estimate": (I32, [VP, VP, I64, I32, C.c_uint64, P(D), VP]),
         "dh2_rows_check": (I32, [VP, P(I64), I32, VP, P(D), P(D), P(D), VP]),
         "dh2_get_stats": (I32, [VP, P(Stats)]),
@@ -309,6 +310,18 @@ def matvec(m: Matrix, op: str, x, y, stream=None):
         assert x.stride(0) == 1 and y.stride(0) == 1
     _check(lib().dh2_matvec(m.h, op.encode(), nrhs, C.c_void_p(x.data_ptr()),
                             C.c_void_p(y.data_ptr()), _stream(stream)))
+    return y
+
+
+def matvec_noalloc(m: Matrix, op: str, x, y, stream=None):
+    """dh2_matvec_noalloc: as matvec, with the library's static scratch array
+    (no device allocation); only enqueued on the stream."""
+    n = x.shape[0]
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    if x.dim() == 2:
+        assert x.stride(0) == 1 and y.stride(0) == 1
+    _check(lib().dh2_matvec_noalloc(m.h, op.encode(), nrhs, C.c_void_p(x.data_ptr()),
+                                    C.c_void_p(y.data_ptr()), _stream(stream)))
     return y
 
 
