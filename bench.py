@@ -131,8 +131,9 @@ def cpu_baseline(budget_s, k_target, n_target):
     """The FP64 oracle (NumPy/LAPACK, plan + weights + row basis + column basis
     + projection + near field, exactly as the parity tests run it) timed per
     phase on this host's cores: the 2048-point sphere (kappa 8, leaf 32, the
-    smallest workload) and, within the time budget, the 4608-point sphere
-    (kappa sqrt(n)/5.66, leaf 64, the leaf size of the benchmark workload).
+    smallest workload) and, within the time budget, the 4608-point
+    and 8192-point spheres (kappa sqrt(n)/5.66, leaf 64, the leaf size of the
+    benchmark workload).
     The benchmark workload itself would take hours; its oracle time is
     extrapolated from the larger timed run by keeping time / (n^2 k_max)
     constant, as the paper observes for its own timings."""
@@ -146,8 +147,9 @@ def cpu_baseline(budget_s, k_target, n_target):
 
     runs, last = {}, None
     spent = 0.0
-    for name in ("sphere2048", "sphere4608"):
-        if runs and spent > 0.4 * budget_s:
+    for name in ("sphere2048", "sphere4608", "sphere8192"):
+        # the next sphere takes about four times the last one
+        if runs and spent + 4.0 * runs[last]["t_total"] > budget_s:
             break
         p, w, kappa, leaf, eps = synth.workload(name)
         t0 = time.perf_counter()
@@ -213,6 +215,9 @@ def run_batch(args, dh2, torch, synth):
         dt = time.perf_counter() - t0
         st = [dh2.stats(m) for m in ms]
         flops = sum(x["flops_row"] + x["flops_col"] + x["flops_prj"] for x in st)
+        gl_flops = sum(x["flops_gram_leaf"] for x in st)
+        gl_time = sum(x["t_gram_leaf"] for x in st)
+        gl_n = sum(x["n_gram_leaf"] for x in st)
         log(f"[bench] batch step {it} {'warmup' if it < args.warmup else 'timed'}: {dt:.3f} s")
         if it >= args.warmup:
             times.append(dt)
@@ -238,51 +243,75 @@ def run_batch(args, dh2, torch, synth):
                    "kappa": "sqrt(n)/5.66"},
         "batch_s": s_b, "sequential_s": seq[0], "batch_speedup": seq[0] / s_b,
         "host_plan_s": t_plan,
+        # leaf Gram kernels of all instances (the largest kernel of each):
+        # algorithmic 8 r^2 N flops over their event-timed launch durations on
+        # the instances' streams; launches of concurrent instances share the
+        # device, so this is a lower bound of the kernel's own rate
+        "roofline": {"bound": "mfma",
+                     "kernel": ("k_gram_i8<0> (leaf Gram matrices, exact int8 slices on int8 "
+                                "MFMA), all instances" if form == "mixed" else
+                                "k_gram_leaf_w (leaf Gram matrices on FP64 MFMA), all instances"),
+                     "achieved": gl_flops / gl_time / 1e12 if gl_time > 0 else 0.0,
+                     "peak": (PEAK_INT8_MFMA if form == "mixed" else PEAK_FP64_MFMA) / 1e12,
+                     "unit": "TOP/s" if form == "mixed" else "TFLOP/s",
+                     "frac": (gl_flops / gl_time / (PEAK_INT8_MFMA if form == "mixed"
+                                                     else PEAK_FP64_MFMA)) if gl_time > 0 else 0.0,
+                     "traffic": None, "launches": gl_n,
+                     "avg_launch_ms": gl_time / max(1, gl_n) * 1e3,
+                     "work_per_launch": gl_flops / max(1, gl_n),
+                     "work": "8 r^2 N real flops per leaf block row (r = #t, N = #F_tc)"},
     }
     print(json.dumps(out), flush=True)
 
 
 def run_matvec(args, dh2, torch, synth, blocks, w, eps, leaf, kappa, n, form):
-    """Matvec timing: one compression (untimed), then y = G~x and y = G~^*x on
-    one right-hand side, each timed over `steps` products after `warmup`.  The
-    representation (bases, transfer matrices, coupling matrices, near field)
-    is read once per product: its size over the product time is the HBM rate."""
+    """Matvec timing: one compression (untimed), then y = G~x and y = G~^*x,
+    each timed over `steps` calls after `warmup`, with one right-hand side
+    and with eight (one pass of the kernels, which read the representation
+    once for all eight).  The representation (bases, transfer matrices,
+    coupling matrices, near field) is read once per pass: its size over the
+    pass time is the HBM rate."""
     prec = dh2.FP64 if form == "fp64" else dh2.MIXED
     o = dh2.opts(leaf_size=leaf, precision=prec, groups=args.groups)
     m = dh2.compress_helmholtz(blocks, w, eps, o)
     torch.cuda.synchronize()
     st = dh2.stats(m)
     rep_bytes = st["mem_bytes"]
-    x = torch.from_numpy(synth.complex_gaussian(n, 6)).to("cuda")
-    y = torch.empty_like(x)
     ms = {}
-    for op in ("N", "C"):
-        for _ in range(args.warmup):
-            dh2.matvec(m, op, x, y)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        ev0.record()
-        for _ in range(args.steps):
-            dh2.matvec(m, op, x, y)
-        ev1.record()
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / args.steps * 1e3
-        ms[op] = ev0.elapsed_time(ev1) / args.steps
-        log(f"[bench] matvec {op}: {ms[op]:.3f} ms per product (wall {wall:.3f} ms), "
-            f"representation {rep_bytes / 1e9:.2f} GB")
-    ach = rep_bytes / (ms["N"] * 1e-3) / 1e9
+    for nrhs in (1, 8):
+        xn = synth.complex_gaussian(n, 6, nrhs if nrhs > 1 else None)
+        x = (torch.from_numpy(xn).to("cuda") if nrhs == 1 else
+             torch.from_numpy(np.ascontiguousarray(xn.T)).to("cuda").T)
+        y = torch.empty_like(x)
+        for op in ("N", "C"):
+            for _ in range(args.warmup):
+                dh2.matvec(m, op, x, y)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            ev0.record()
+            for _ in range(args.steps):
+                dh2.matvec(m, op, x, y)
+            ev1.record()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps * 1e3
+            ms[(op, nrhs)] = ev0.elapsed_time(ev1) / args.steps
+            log(f"[bench] matvec {op} nrhs {nrhs}: {ms[(op, nrhs)]:.3f} ms per call "
+                f"({ms[(op, nrhs)] / nrhs:.3f} ms per right-hand side, wall {wall:.3f} ms), "
+                f"representation {rep_bytes / 1e9:.2f} GB")
+    ach = rep_bytes / (ms[("N", 1)] * 1e-3) / 1e9
     out = {
         "metric": "matvec ms, y = G~x with the compressed representation, n=%d kappa=%g" % (n, kappa),
-        "value": ms["N"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms["N"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "value": ms[("N", 1)], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms[("N", 1)], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "kappa": kappa, "leaf_size": leaf,
                    "eps": eps, "form": form, "nrhs": 1},
-        "roofline": {"bound": "hbm", "kernel": "matvec (representation read once per product)",
+        "roofline": {"bound": "hbm", "kernel": "matvec (representation read once per pass)",
                      "achieved": ach, "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
                      "traffic": None},
-        "adjoint_ms": ms["C"],
+        "adjoint_ms": ms[("C", 1)],
+        "nrhs8_ms_per_rhs": {"N": ms[("N", 8)] / 8, "C": ms[("C", 8)] / 8},
         "representation_bytes": rep_bytes,
     }
     print(json.dumps(out), flush=True)

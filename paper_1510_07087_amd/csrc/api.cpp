@@ -330,9 +330,7 @@ dh2_status dh2_matvec(dh2_matrix m, char op, int64_t nrhs, const void* x, void* 
     if (!m || !x || !y) fail(DH2_EINVAL, "NULL argument");
     if (op != 'N' && op != 'C' && op != 'n' && op != 'c') fail(DH2_EINVAL, "op must be N or C");
     if (nrhs < 0) fail(DH2_EINVAL, "nrhs must be >= 0");
-    int64_t n = m->d->blk->tree->tr.n;
-    for (int64_t q = 0; q < nrhs; ++q)
-      matvec(*m->d, op, (const double2*)x + q * n, (double2*)y + q * n, stream_of(stream));
+    matvec(*m->d, op, nrhs, (const double2*)x, (double2*)y, stream_of(stream));
     hip_check(hipStreamSynchronize(stream_of(stream)), "matvec sync");
   })
 }

@@ -141,6 +141,7 @@ struct NearRefDev {
   int64_t row0;   // first row (op N) or column (op C) of the leaf inside the block
 };
 
-constexpr int kMaxR = 128;      // largest factor size handled by the kernels
+constexpr int kMaxR = 128;      // largest factor size of the LDS-resident kernels
+constexpr int kMaxRBig = 512;   // largest factor size of the kernels that stage in memory
 
 }  // namespace dh2

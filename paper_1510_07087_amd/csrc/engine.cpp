@@ -401,8 +401,12 @@ struct MatvecPlan {
   int64_t maxh = 0;       // coefficients of the larger side
 };
 
-// work vectors of one product: permuted x and y (n each), coefficients of the
-// source and destination bases (maxh each)
+// right-hand sides per pass of the matrix-vector product kernels
+constexpr int kMvRhs = 8;
+
+// work vectors of one pass: permuted x and y (n each), coefficients of the
+// source and destination bases (maxh each), times the right-hand sides of
+// the pass (interleaved)
 struct MatvecBufs {
   double2 *xp, *yp, *xh, *yh;
 };
@@ -725,10 +729,10 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       for (int32_t i = lo; i < hi; ++i) {
         ItemDev& it = S.items[i];
         if (!it.leaf) it.r = S.items[it.son[0]].k + S.items[it.son[1]].k;
-        if (it.r > kMaxR)
+        if (it.r > kMaxRBig)
           fail(DH2_EUNSUPPORTED, "block row with " + std::to_string(it.r) +
                                      " factor rows exceeds the kernel limit " +
-                                     std::to_string(kMaxR));
+                                     std::to_string(kMaxRBig));
         sum_r2 += (int64_t)it.r * it.r;
         sum_r += it.r;
       }
@@ -777,7 +781,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       int64_t totalN = 0;
       for (int32_t i = lo; i < hi; ++i) totalN += S.items[i].N;
       // FP64: one Gram unit per wave, about 8 waves of work per SIMD; mixed:
-      // one unit per workgroup of 8 waves (int8 slicing, 64-column chunks)
+      // one unit per workgroup of 16 waves (int8 slicing, 64-column chunks)
       int64_t width = mixed ? std::max<int64_t>(512, std::min<int64_t>(8192, totalN / 1024))
                             : std::max<int64_t>(256, std::min<int64_t>(2048, totalN / 8192));
       width = (width + 63) / 64 * 64;
@@ -793,17 +797,18 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           if (it.r == 0) continue;
           if (it.leaf && it.m > 64)
             fail(DH2_EUNSUPPORTED, "leaf clusters with more than 64 points are not supported");
-          // tile blocks per unit (register budget: at most 10 tile pairs per wave):
-          // nt <= 4: one diagonal block; otherwise the diagonal blocks of tiles
-          // 0..3 and 4..nt-1 and the off-diagonal part in bands of two tiles
+          // tile blocks per unit (register budget: at most 10 tile pairs per
+          // wave): the 16-row tiles in groups of four; a diagonal block per
+          // group and every pair of groups in bands of two row tiles against
+          // the column group's (up to) four tiles
           int nt = (it.r + 15) / 16;
           std::vector<std::array<int, 4>> blocksets;
-          if (nt <= 4) {
-            blocksets.push_back({0, nt, 0, nt});
-          } else {
-            blocksets.push_back({0, 4, 0, 4});
-            blocksets.push_back({4, nt - 4, 4, nt - 4});
-            for (int a0 = 4; a0 < nt; a0 += 2) blocksets.push_back({a0, std::min(2, nt - a0), 0, 4});
+          for (int g0 = 0; g0 < nt; g0 += 4) {
+            int gn = std::min(4, nt - g0);
+            blocksets.push_back({g0, gn, g0, gn});
+            for (int h0 = 0; h0 < g0; h0 += 4)
+              for (int a0 = g0; a0 < g0 + gn; a0 += 2)
+                blocksets.push_back({a0, std::min(2, g0 + gn - a0), h0, 4});
           }
           for (int64_t c0 = 0; c0 < it.N; c0 += width) {
             for (const auto& bs : blocksets) {
@@ -875,9 +880,14 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       {
         constexpr int kFacClasses = 4;
         constexpr int32_t kFacLimit[kFacClasses - 1] = {32, 48, 64};
-        std::vector<int32_t> fl[kFacClasses];
+        std::vector<int32_t> fl[kFacClasses], big;
         int32_t rm[kFacClasses] = {0, 0, 0, 0};
         for (int32_t i = lo; i < hi; ++i) {
+          // factors beyond the LDS-resident kernel stage X in device memory
+          if (S.items[i].r > kMaxR) {
+            big.push_back(i);
+            continue;
+          }
           int c = 0;
           while (c < kFacClasses - 1 && S.items[i].r > kFacLimit[c]) ++c;
           fl[c].push_back(i);
@@ -898,6 +908,24 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
                         M.max_sweeps, d_status, st);
           off += (int64_t)fl[c].size();
         }
+        double2* xws = nullptr;
+        int32_t* d_big = nullptr;
+        double2** d_xptr = nullptr;
+        if (!big.empty()) {
+          int64_t tot = 0;
+          for (int32_t i : big) tot += (int64_t)S.items[i].r * (S.items[i].r + 1);
+          xws = (double2*)mem.alloc((size_t)tot * sizeof(double2));
+          std::vector<double2*> xp;
+          int64_t o = 0;
+          for (int32_t i : big) {
+            xp.push_back(xws + o);
+            o += (int64_t)S.items[i].r * (S.items[i].r + 1);
+          }
+          d_big = upload(mem, big, st);
+          d_xptr = upload(mem, xp, st);
+          launch_factor_big(S.d_items, d_big, (int32_t)big.size(), M.eps, M.max_sweeps, d_status,
+                            d_xptr, st);
+        }
         launch_check("factor");
         // only the ranks come back to the host (4 bytes per item)
         int32_t* d_k = (int32_t*)mem.alloc((size_t)n * sizeof(int32_t));
@@ -906,9 +934,39 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         mem.sync(st, "factor sync");
         std::vector<int32_t> hk(n);
         copy_from(hk.data(), d_k, n, st);
+        // factors whose numerical rank outgrew the LDS-resident kernel's columns
+        // (rank -1) are factored again with X in device memory
+        std::vector<int32_t> redo;
+        for (int32_t i = 0; i < n; ++i)
+          if (hk[i] < 0) redo.push_back(lo + i);
+        if (!redo.empty()) {
+          int64_t tot = 0;
+          for (int32_t i : redo) tot += (int64_t)S.items[i].r * (S.items[i].r + 1);
+          double2* xw2 = (double2*)mem.alloc((size_t)tot * sizeof(double2));
+          std::vector<double2*> xp;
+          int64_t o = 0;
+          for (int32_t i : redo) {
+            xp.push_back(xw2 + o);
+            o += (int64_t)S.items[i].r * (S.items[i].r + 1);
+          }
+          int32_t* d_redo = upload(mem, redo, st);
+          double2** d_xp2 = upload(mem, xp, st);
+          launch_factor_big(S.d_items, d_redo, (int32_t)redo.size(), M.eps, M.max_sweeps,
+                            d_status, d_xp2, st);
+          launch_check("factor (memory-staged)");
+          launch_ranks(S.d_items + lo, n, d_k, st);
+          launch_check("ranks");
+          copy_from(hk.data(), d_k, n, st);
+          mem.release(xw2);
+          mem.release(d_redo);
+          mem.release(d_xp2);
+        }
         for (int32_t i = 0; i < n; ++i) S.items[lo + i].k = hk[i];
         mem.release(d_fl);
         mem.release(d_k);
+        mem.release(xws);
+        mem.release(d_big);
+        mem.release(d_xptr);
       }
       int32_t status = 0;
       copy_from(&status, d_status, 1, st);
@@ -945,24 +1003,52 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       // the inherited columns of R; the own-block columns are kept for the
       // projection of the row sweep and not formed in the column sweep.
       std::vector<UnitDev> ru;
-      int64_t nleafr = 0;
+      int64_t nleafr = 0, nbigr = 0;
       std::vector<std::array<int64_t, 3>> rlaunch;  // kt, count, lds bytes
+      // large transfer factors: Q_hat packed in 64-column chunks
+      std::vector<int32_t> pk_item, pk_chunk;
+      std::vector<void*> pk_dst, big_q;
+      void* pkbuf = nullptr;
       {
         const int64_t rwidth = 1024;
-        std::vector<UnitDev> inner_by_kt[9];
+        std::vector<UnitDev> inner_by_kt[9], big_units;
         size_t lds_kt[9] = {0};
+        int64_t pk_bytes = 0;
+        std::vector<int64_t> pk_off;
         for (int32_t i = lo; i < hi; ++i) {
           const ItemDev& it = S.items[i];
           if (it.k == 0) continue;
           int kt = (it.k + 15) / 16;
-          if (!it.leaf) lds_kt[kt] = std::max(lds_kt[kt], rprod_inner_lds(mixed, it.r, it.k));
+          const bool bigq = !it.leaf && (it.k > kMaxR || rprod_inner_lds(mixed, it.r, it.k) >
+                                                             rprod_inner_lds_max());
+          if (!it.leaf && !bigq)
+            lds_kt[kt] = std::max(lds_kt[kt], rprod_inner_lds(mixed, it.r, it.k));
           const int64_t nr = s == 0 ? it.N : S.P->ninh[i];
-          for (int64_t c0 = 0; c0 < nr; c0 += rwidth) {
-            UnitDev u{};
-            u.item = i;
-            u.col_begin = c0;
-            u.ncols = std::min(rwidth, nr - c0);
-            (it.leaf ? ru : inner_by_kt[kt]).push_back(u);
+          if (bigq) {
+            const int nch = (it.k + 63) / 64;
+            for (int c = 0; c < nch; ++c) {
+              pk_item.push_back(i);
+              pk_chunk.push_back(c);
+              pk_off.push_back(pk_bytes);
+              pk_bytes += (int64_t)(it.r + 8) * 64 * (mixed ? sizeof(float2) : sizeof(double2));
+              for (int64_t c0 = 0; c0 < nr; c0 += rwidth) {
+                UnitDev u{};
+                u.item = i;
+                u.a0 = (int8_t)c;
+                u.col_begin = c0;
+                u.ncols = std::min(rwidth, nr - c0);
+                big_units.push_back(u);
+                big_q.push_back((void*)(intptr_t)(pk_off.size() - 1));
+              }
+            }
+          } else {
+            for (int64_t c0 = 0; c0 < nr; c0 += rwidth) {
+              UnitDev u{};
+              u.item = i;
+              u.col_begin = c0;
+              u.ncols = std::min(rwidth, nr - c0);
+              (it.leaf ? ru : inner_by_kt[kt]).push_back(u);
+            }
           }
           ss.flops_rprod += 8.0 * it.k * (double)it.r * (double)nr;
           if (it.leaf) ss.flops_rprod_leaf += 8.0 * it.k * (double)it.r * (double)nr;
@@ -970,10 +1056,15 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         nleafr = (int64_t)ru.size();
         for (int kt = 1; kt <= 8; ++kt) {
           if (inner_by_kt[kt].empty()) continue;
-          if (lds_kt[kt] > rprod_inner_lds_max())
-            fail(DH2_EUNSUPPORTED, "transfer matrix too large for the R-product workgroup");
           rlaunch.push_back({kt, (int64_t)inner_by_kt[kt].size(), (int64_t)lds_kt[kt]});
           ru.insert(ru.end(), inner_by_kt[kt].begin(), inner_by_kt[kt].end());
+        }
+        nbigr = (int64_t)big_units.size();
+        ru.insert(ru.end(), big_units.begin(), big_units.end());
+        if (pk_bytes > 0) {
+          pkbuf = mem.alloc((size_t)pk_bytes);
+          for (int64_t off : pk_off) pk_dst.push_back((char*)pkbuf + off);
+          for (auto& q : big_q) q = pk_dst[(size_t)(intptr_t)q];
         }
       }
       UnitDev* d_ru = upload(mem, ru, st);
@@ -987,6 +1078,20 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
                              st);
           off += L[1];
         }
+      }
+      if (nbigr > 0) {
+        int32_t* d_pki = upload(mem, pk_item, st);
+        int32_t* d_pkc = upload(mem, pk_chunk, st);
+        void** d_pkd = upload(mem, pk_dst, st);
+        void** d_bq = upload(mem, big_q, st);
+        launch_pack_q(S.d_items, d_pki, d_pkc, d_pkd, (int64_t)pk_item.size(), mixed, st);
+        launch_rprod_inner_big(mixed, S.d_items, d_ru + (ru.size() - nbigr), nbigr, M.zeta, d_bq,
+                               st);
+        mem.release(d_pki);
+        mem.release(d_pkc);
+        mem.release(d_pkd);
+        mem.release(d_bq);
+        mem.release(pkbuf);
       }
       launch_check("rprod (non-leaf)");
       if (trace_on()) hip_check(hipStreamSynchronize(st), "trace sync");
@@ -1333,7 +1438,11 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
       if (group[t] >= 0) grpN[group[t]] += N;
     }
   }
-  double kest = std::min(48.0, (double)o.leaf_size);
+  // rank estimate: about 48 (at most the leaf size) with the directional
+  // admissibility; the standard condition alone admits blocks whose ranks
+  // grow with kappa (several times larger in the paper's comparison), so
+  // twice the leaf size there
+  double kest = o.standard_only ? 2.0 * o.leaf_size : std::min(48.0, (double)o.leaf_size);
   double peak = 0;
   const double csz = o.precision == DH2_MIXED ? 8.0 : 16.0;
   for (int32_t l = 0; l <= tr.depth; ++l) peak = std::max(peak, (lvlN[l] + lvlN[l + 1]) * kest * csz);
@@ -1799,16 +1908,18 @@ static void build_mv(MatrixData& M, hipStream_t st) {
   P->d_Srows = upload(mem, M.S_rows, st);
   P->d_Scols = upload(mem, M.S_cols, st);
   int64_t n = tr.n;
-  P->xp = (double2*)mem.alloc(n * sizeof(double2));
-  P->yp = (double2*)mem.alloc(n * sizeof(double2));
-  P->xh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * sizeof(double2));
-  P->yh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * sizeof(double2));
+  P->xp = (double2*)mem.alloc(n * kMvRhs * sizeof(double2));
+  P->yp = (double2*)mem.alloc(n * kMvRhs * sizeof(double2));
+  P->xh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * kMvRhs * sizeof(double2));
+  P->yh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * kMvRhs * sizeof(double2));
   P->maxh = maxh;
   M.mv = std::move(P);
 }
 
-// one product into the given work vectors (no allocation, no wait)
-static void matvec_core(MatrixData& M, char op, const double2* x, double2* y,
+// nr <= kMvRhs products (x, y column-major n x nr) in one pass of the
+// kernels, into the given work vectors (no allocation, no wait): each
+// element of the representation is read once for all nr right-hand sides
+static void matvec_core(MatrixData& M, char op, int nr, const double2* x, double2* y,
                         const MatvecBufs& w, hipStream_t st) {
   MatvecPlan& P = *M.mv;
   const ClusterTree& tr = M.blk->tree->tr;
@@ -1819,25 +1930,29 @@ static void matvec_core(MatrixData& M, char op, const double2* x, double2* y,
   Side& Bs = M.side[dst_side];
   SideMV& VA = P.s[src_side];
   SideMV& VB = P.s[dst_side];
-  launch_gather_perm(x, M.d_perm, n, w.xp, st);
-  launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, w.xp, w.xh, st);
+  launch_gather_perm(x, M.d_perm, n, w.xp, st, nr);
+  launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, w.xp, w.xh, nr, st);
   for (size_t q = 0; q < VA.d_fwd_lvl.size(); ++q)
-    launch_fwd_inner(A.d_items, VA.d_fwd_lvl[q], VA.fwd_count[q], VA.d_hoff, w.xh, st);
+    launch_fwd_inner(A.d_items, VA.d_fwd_lvl[q], VA.fwd_count[q], VA.d_hoff, w.xh, nr, st);
   launch_coupling(Bs.d_items, Bs.nitems, VB.d_cbegin, VB.d_cblock, VB.d_cpartner, P.d_Sptr,
-                  P.d_Srows, P.d_Scols, VA.d_hoff, w.xh, VB.d_hoff, w.yh, adj, st);
+                  P.d_Srows, P.d_Scols, VA.d_hoff, w.xh, VB.d_hoff, w.yh, adj, nr, st);
   for (size_t l = 0; l < VB.d_bl_items.size(); ++l)
     launch_bwd_inner(Bs.d_items, VB.d_bl_items[l], VB.bl_count[l], VB.d_bl_fbegin[l],
-                     VB.d_bl_fitem[l], VB.d_bl_fson[l], VB.d_hoff, w.yh, st);
+                     VB.d_bl_fitem[l], VB.d_bl_fson[l], VB.d_hoff, w.yh, nr, st);
   launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near, VB.d_hoff,
-                  w.yh, w.xp, w.yp, adj, st);
-  launch_scatter_perm(w.yp, M.d_perm, n, y, st);
+                  w.yh, w.xp, w.yp, adj, nr, st);
+  launch_scatter_perm(w.yp, M.d_perm, n, y, st, nr);
   launch_check("matvec");
 }
 
-void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st) {
+void matvec(MatrixData& M, char op, int64_t nrhs, const double2* x, double2* y, hipStream_t st) {
   if (!M.mv) build_mv(M, st);
   MatvecPlan& P = *M.mv;
-  matvec_core(M, op, x, y, MatvecBufs{P.xp, P.yp, P.xh, P.yh}, st);
+  const int64_t n = M.blk->tree->tr.n;
+  for (int64_t q = 0; q < nrhs; q += kMvRhs) {
+    const int nr = (int)std::min<int64_t>(kMvRhs, nrhs - q);
+    matvec_core(M, op, nr, x + q * n, y + q * n, MatvecBufs{P.xp, P.yp, P.xh, P.yh}, st);
+  }
 }
 
 // The same product with its work vectors in the library's static scratch
@@ -1850,9 +1965,12 @@ void matvec_noalloc(MatrixData& M, char op, int64_t nrhs, const double2* x, doub
     fail(DH2_EINVAL, "the matrix has no matvec plan yet: call dh2_matvec on it once first");
   const int64_t n = M.blk->tree->tr.n;
   const int64_t maxh = std::max<int64_t>(1, M.mv->maxh);
-  // 256-byte aligned parts: xp, yp (n each), xh, yh (maxh each)
+  // 256-byte aligned parts: xp, yp (n each), xh, yh (maxh each), per
+  // right-hand side of a pass; as many right-hand sides per pass as fit
   auto part = [](int64_t cnt) { return ((size_t)cnt * sizeof(double2) + 255) / 256 * 256; };
-  const size_t need = 2 * part(n) + 2 * part(maxh);
+  int nr = kMvRhs;
+  while (nr > 1 && 2 * part(n * nr) + 2 * part(maxh * nr) > noalloc_scratch_bytes()) --nr;
+  const size_t need = 2 * part(n * nr) + 2 * part(maxh * nr);
   if (need > noalloc_scratch_bytes())
     fail(DH2_EUNSUPPORTED, "the allocation-free product needs " + std::to_string(need) +
                                " bytes of scratch, more than the library's " +
@@ -1862,10 +1980,13 @@ void matvec_noalloc(MatrixData& M, char op, int64_t nrhs, const double2* x, doub
   char* p = static_cast<char*>(base);
   MatvecBufs w;
   w.xp = (double2*)p;
-  w.yp = (double2*)(p + part(n));
-  w.xh = (double2*)(p + 2 * part(n));
-  w.yh = (double2*)(p + 2 * part(n) + part(maxh));
-  for (int64_t q = 0; q < nrhs; ++q) matvec_core(M, op, x + q * n, y + q * n, w, st);
+  w.yp = (double2*)(p + part(n * nr));
+  w.xh = (double2*)(p + 2 * part(n * nr));
+  w.yh = (double2*)(p + 2 * part(n * nr) + part(maxh * nr));
+  for (int64_t q = 0; q < nrhs; q += nr) {
+    const int m = (int)std::min<int64_t>(nr, nrhs - q);
+    matvec_core(M, op, m, x + q * n, y + q * n, w, st);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1921,7 +2042,7 @@ double error_estimate(MatrixData& M, const void* G, int64_t ld, int iters, uint6
       copy_to(mem, x, hx.data(), n, st);
       direct_apply(M, src, g, x, y1, 0, tp, to, st);
       if (diff) {
-        matvec(M, 'N', x, y2, st);
+        matvec(M, 'N', 1, x, y2, st);
         copy_from(hy.data(), y1, n, st);
         copy_from(hz.data(), y2, n, st);
         for (int64_t i = 0; i < n; ++i) hy[i] = make_double2(hy[i].x - hz[i].x, hy[i].y - hz[i].y);
@@ -1929,7 +2050,7 @@ double error_estimate(MatrixData& M, const void* G, int64_t ld, int iters, uint6
       }
       direct_apply(M, src, g, y1, z, 1, tp, to, st);
       if (diff) {
-        matvec(M, 'C', y1, y2, st);
+        matvec(M, 'C', 1, y1, y2, st);
         copy_from(hz.data(), z, n, st);
         copy_from(hy.data(), y2, n, st);
         for (int64_t i = 0; i < n; ++i) hz[i] = make_double2(hz[i].x - hy[i].x, hz[i].y - hy[i].y);
@@ -1976,7 +2097,7 @@ void rows_check(MatrixData& M, const int64_t* rows, int32_t nrows, const double2
   launch_gather_perm(x, M.d_perm, n, xp, st);
   launch_direct(M.src, g, d_pos, nrows, xp, 0, out, st);
   launch_check("rows direct");
-  matvec(M, 'N', x, y, st);
+  matvec(M, 'N', 1, x, y, st);
   std::vector<double2> hd(nrows), hy(n);
   copy_from(hd.data(), out, nrows, st);
   copy_from(hy.data(), y, n, st);

@@ -172,7 +172,9 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> b, int src, con
 std::vector<std::unique_ptr<MatrixData>> compress_batch(
     const std::vector<std::shared_ptr<BlocksData>>& blks, const std::vector<const double*>& w,
     double eps, const dh2_opts& o, hipStream_t st, int nstreams);
-void matvec(MatrixData& M, char op, const double2* x, double2* y, hipStream_t st);
+// y = G~ x or G~^* x for nrhs right-hand sides (column-major, ld = n), in passes of up
+// to eight right-hand sides that read the representation once each
+void matvec(MatrixData& M, char op, int64_t nrhs, const double2* x, double2* y, hipStream_t st);
 // nrhs products with the work vectors in the static scratch array (no
 // allocation, no wait); needs the matvec plan built by an earlier matvec()
 void matvec_noalloc(MatrixData& M, char op, int64_t nrhs, const double2* x, double2* y,

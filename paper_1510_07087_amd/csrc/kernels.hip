@@ -409,20 +409,24 @@ __device__ __forceinline__ double wave_sum(double v, int width) {
   return v;
 }
 
+// RMAX bounds r; GX: X in global memory (xptr[blockIdx.x], r (r + 1)
+// elements) for factors too large for LDS, else in dynamic LDS.
+template <int RMAX, bool GX>
 __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const int32_t* litems,
                                                         double eps, int max_sweeps, int cap,
-                                                        int32_t* status) {
-  extern __shared__ double2 X[];  // column-major r x pmax
-  __shared__ double d[kMaxR];
-  __shared__ int done[kMaxR];
+                                                        int32_t* status, double2* const* xptr) {
+  extern __shared__ double2 Xs[];  // column-major r x pmax
+  double2* X = GX ? xptr[blockIdx.x] : Xs;
+  __shared__ double d[RMAX];
+  __shared__ int done[RMAX];
   __shared__ double bval[4];
   __shared__ int bidx[4];
   __shared__ int s_piv;
   __shared__ double s_dmax;
   __shared__ int s_p;
   __shared__ int s_rot;
-  __shared__ double s_norm[kMaxR];
-  __shared__ int s_rank[kMaxR];
+  __shared__ double s_norm[RMAX];
+  __shared__ int s_rank[RMAX];
 
   int32_t ii = litems[blockIdx.x];
   ItemDev& it = items[ii];
@@ -524,9 +528,20 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
     double rest = 0.0;
     for (int i = 0; i < r; ++i)
       if (!done[i]) rest += d[i];
-    if (p == pmax && rest > 0.1 * eps * eps) atomicMax(status, 1);
+    s_rot = 0;
+    if (p == pmax && rest > 0.1 * eps * eps) {
+      // X in memory holds all r columns, so this cannot happen there; the
+      // LDS-resident kernel marks the item (rank -1) for the host to factor it
+      // again with X in memory
+      if (GX) atomicMax(status, 1);
+      else s_rot = 1;
+    }
   }
   __syncthreads();
+  if (s_rot) {
+    if (tid == 0) it.k = -1;
+    return;
+  }
   p = s_p;
   int pe = p + (p & 1);
   for (int i = tid; i < r; i += 256)
@@ -713,6 +728,8 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
   int nti = (kt + 15) / 16, ntj = (ks + 15) / 16;
   const void* Wb = t.W;
   double2* Sb = t.S;
+  // column tiles of S in groups of eight (ranks beyond 128 take several)
+  for (int tj0 = 0; tj0 < ntj; tj0 += 8)
   for (int ti16 = 0; ti16 < nti; ++ti16) {
     SAcc<MX> acc[8];
     int ii = ti16 * 16 + row;
@@ -721,8 +738,8 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
       double2 a = (j < t.ns && ii < kt) ? rload<MX>(t.R, (int64_t)j * kt + ii) : make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        if (q < ntj) {
-          int jj = q * 16 + row;
+        if (tj0 + q < ntj) {
+          int jj = (tj0 + q) * 16 + row;
           double2 b = (j < t.ns && jj < ks) ? rload<MX>(Wb, (int64_t)j * ks + jj) : make_double2(0.0, 0.0);
           acc[q].mac(a, b);
         }
@@ -730,8 +747,8 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      if (q < ntj) {
-        int jj = q * 16 + row;
+      if (tj0 + q < ntj) {
+        int jj = (tj0 + q) * 16 + row;
         for (int v = 0; v < 4; ++v) {
           int i = ti16 * 16 + acc[q].row(lane, v);
           double2 z = acc[q].get(v);
@@ -1083,56 +1100,111 @@ __global__ __launch_bounds__(256) void k_near(GeomDev g, const int64_t* t_off, c
 // ---------------------------------------------------------------------------
 // Matrix-vector product kernels (verification path, VALU).
 // ---------------------------------------------------------------------------
-__global__ void k_gather_perm(const double2* x, const int64_t* perm, int64_t n, double2* xp) {
+// Work vectors hold nr right-hand sides interleaved: entry p of right-hand
+// side q at [p * nr + q] (nr <= NR, a compile-time bound); x and y of the
+// caller are column-major, x[q * n + i].  Every kernel reads each element of
+// the representation once for all nr right-hand sides.
+__global__ void k_gather_perm(const double2* x, const int64_t* perm, int64_t n, int nr,
+                              double2* xp) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) xp[p] = x[perm[p]];
+  if (p >= n) return;
+  const int64_t src = perm[p];
+  for (int q = 0; q < nr; ++q) xp[p * nr + q] = x[(int64_t)q * n + src];
 }
-__global__ void k_scatter_perm(const double2* yp, const int64_t* perm, int64_t n, double2* y) {
+__global__ void k_scatter_perm(const double2* yp, const int64_t* perm, int64_t n, int nr,
+                               double2* y) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) y[perm[p]] = yp[p];
+  if (p >= n) return;
+  const int64_t dst = perm[p];
+  for (int q = 0; q < nr; ++q) y[(int64_t)q * n + dst] = yp[p * nr + q];
+}
+
+// s[q] += sum_c op(a[c * as]) v[c * nr + q] over c < n for the nr right-hand
+// sides (op: conj when conj_a), with U terms loaded ahead of their products
+// (U = 4 for one or two right-hand sides, fewer for more) so that several
+// loads are in flight.
+template <int NR>
+__device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int64_t as,
+                                        const double2* v, int64_t n, int nr, bool conj_a) {
+  constexpr int U = NR <= 2 ? 4 : (NR <= 4 ? 2 : 1);
+  int64_t c = 0;
+  for (; c + U <= n; c += U) {
+    double2 av[U], xv[U][NR];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      av[u] = a[(c + u) * as];
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) xv[u][q] = v[(c + u) * nr + q];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) {
+          double2 t = conj_a ? cmulc(av[u], xv[u][q]) : cmul(av[u], xv[u][q]);
+          s[q].x += t.x;
+          s[q].y += t.y;
+        }
+  }
+  for (; c < n; ++c) {
+    const double2 ac = a[c * as];
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (q < nr) {
+        double2 t = conj_a ? cmulc(ac, v[c * nr + q]) : cmul(ac, v[c * nr + q]);
+        s[q].x += t.x;
+        s[q].y += t.y;
+      }
+  }
 }
 
 // forward, leaf items: xh = Q^* x|t
+template <int NR>
 __global__ __launch_bounds__(128) void k_fwd_leaf(const ItemDev* items, const int32_t* litems,
                                                   const int64_t* xh_off, const double2* xp,
-                                                  double2* xh) {
+                                                  double2* xh, int nr) {
   int32_t i = litems[blockIdx.x];
   const ItemDev& it = items[i];
   int k = it.k;
   for (int kk = threadIdx.x; kk < k; kk += blockDim.x) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int j = 0; j < it.m; ++j) {
-      double2 v = cmulc(it.Q[(int64_t)j * k + kk], xp[it.row_off + j]);
-      s.x += v.x;
-      s.y += v.y;
-    }
-    xh[xh_off[i] + kk] = s;
+    double2 s[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
+    dot_rhs<NR>(s, it.Q + kk, k, xp + it.row_off * nr, it.m, nr, true);
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (q < nr) xh[(xh_off[i] + kk) * nr + q] = s[q];
   }
 }
 
 // forward, non-leaf items: xh_tc = Q_hat^* [xh_t1c'; xh_t2c']
+template <int NR>
 __global__ __launch_bounds__(128) void k_fwd_inner(const ItemDev* items, const int32_t* litems,
-                                                   const int64_t* xh_off, double2* xh) {
+                                                   const int64_t* xh_off, double2* xh, int nr) {
   int32_t i = litems[blockIdx.x];
   const ItemDev& it = items[i];
   int k = it.k;
   const ItemDev& s1 = items[it.son[0]];
+  const int64_t o1 = xh_off[it.son[0]], o2 = xh_off[it.son[1]] - s1.k;
   for (int kk = threadIdx.x; kk < k; kk += blockDim.x) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int rho = 0; rho < it.r; ++rho) {
-      double2 z = rho < s1.k ? xh[xh_off[it.son[0]] + rho] : xh[xh_off[it.son[1]] + rho - s1.k];
-      double2 v = cmulc(it.Q[(int64_t)rho * k + kk], z);
-      s.x += v.x;
-      s.y += v.y;
-    }
-    xh[xh_off[i] + kk] = s;
+    double2 s[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
+    dot_rhs<NR>(s, it.Q + kk, k, xh + o1 * nr, s1.k, nr, true);
+    dot_rhs<NR>(s, it.Q + (int64_t)s1.k * k + kk, k, xh + (o2 + s1.k) * nr, it.r - s1.k, nr,
+                true);
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (q < nr) xh[(xh_off[i] + kk) * nr + q] = s[q];
   }
 }
 
 // coupling: yh_i = sum over the item's blocks of S_b xh_partner (or S_b^* for
 // the adjoint, where S_b is kr x kc with the item on the column side).  One
-// wave per item, lane kk one coefficient; the terms of a block are loaded
-// four at a time so that several loads are in flight.
+// wave per item, lane kk one coefficient; the partner's coefficients are
+// the same for all lanes.
+template <int NR>
 __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t nitems,
                                                   const int64_t* cbegin, const int32_t* cblock,
                                                   const int32_t* cpartner,
@@ -1140,128 +1212,110 @@ __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t 
                                                   const int32_t* S_rows, const int32_t* S_cols,
                                                   const int64_t* xh_off, const double2* xh,
                                                   const int64_t* yh_off, double2* yh,
-                                                  int adjoint) {
+                                                  int adjoint, int nr) {
   int32_t i = (int32_t)blockIdx.x * 4 + wave_id();
   if (i >= nitems) return;
   const int lane = threadIdx.x & 63;
   const int k = items[i].k;
   for (int kk0 = 0; kk0 < k; kk0 += 64) {
     const int kk = min(kk0 + lane, k - 1);
-    double2 s = make_double2(0.0, 0.0);
-    auto add = [&](double2 a, double2 x, bool conj_a) {
-      double2 v = conj_a ? cmulc(a, x) : cmul(a, x);
-      s.x += v.x;
-      s.y += v.y;
-    };
-    for (int64_t q = cbegin[i]; q < cbegin[i + 1]; ++q) {
-      const int32_t b = cblock[q];
+    double2 s[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
+    for (int64_t c = cbegin[i]; c < cbegin[i + 1]; ++c) {
+      const int32_t b = cblock[c];
       const double2* Sb = S_ptr[b];
       const int kr = S_rows[b], kc = S_cols[b];
-      const double2* x = xh + xh_off[cpartner[q]];
+      const double2* x = xh + xh_off[cpartner[c]] * nr;
       // op N: sum_jj S[kk, jj] x[jj]; adjoint: sum_jj conj(S[jj, kk]) x[jj]
       const int n = adjoint ? kr : kc;
       const int64_t st = adjoint ? 1 : kr;
       const double2* a0 = adjoint ? Sb + (int64_t)kk * kr : Sb + kk;
-      int jj = 0;
-      for (; jj + 3 < n; jj += 4) {
-        double2 a_0 = a0[jj * st], a_1 = a0[(jj + 1) * st], a_2 = a0[(jj + 2) * st],
-                a_3 = a0[(jj + 3) * st];
-        double2 x0 = x[jj], x1 = x[jj + 1], x2 = x[jj + 2], x3 = x[jj + 3];
-        add(a_0, x0, adjoint);
-        add(a_1, x1, adjoint);
-        add(a_2, x2, adjoint);
-        add(a_3, x3, adjoint);
-      }
-      for (; jj < n; ++jj) add(a0[jj * st], x[jj], adjoint);
+      dot_rhs<NR>(s, a0, st, x, n, nr, adjoint != 0);
     }
-    if (kk0 + lane < k) yh[yh_off[i] + kk0 + lane] = s;
+    if (kk0 + lane < k)
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) yh[(yh_off[i] + kk0 + lane) * nr + q] = s[q];
   }
 }
 
 // backward to the sons: yh_{t'c'} += sum over father items (fa,c+) with
 // sd(c+) = c' of E_{t'c+} yh_{fa c+}; E_{t'c+} = rows of the father's factor.
+template <int NR>
 __global__ __launch_bounds__(128) void k_bwd_inner(const ItemDev* items, const int32_t* litems,
                                                    const int64_t* fbegin, const int32_t* fitem,
                                                    const int32_t* fsonidx, const int64_t* yh_off,
-                                                   double2* yh) {
+                                                   double2* yh, int nr) {
   int32_t i = litems[blockIdx.x];
   const ItemDev& it = items[i];
   int k = it.k;
   for (int kk = threadIdx.x; kk < k; kk += blockDim.x) {
-    double2 s = yh[yh_off[i] + kk];
-    for (int64_t q = fbegin[blockIdx.x]; q < fbegin[blockIdx.x + 1]; ++q) {
-      const ItemDev& fa = items[fitem[q]];
-      int rowoff = fsonidx[q] == 0 ? 0 : items[fa.son[0]].k;
-      const double2* y = yh + yh_off[fitem[q]];
-      for (int jj = 0; jj < fa.k; ++jj) {
-        double2 v = cmul(fa.Q[(int64_t)(rowoff + kk) * fa.k + jj], y[jj]);
-        s.x += v.x;
-        s.y += v.y;
-      }
+    double2 s[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) s[q] = q < nr ? yh[(yh_off[i] + kk) * nr + q] : make_double2(0, 0);
+    for (int64_t c = fbegin[blockIdx.x]; c < fbegin[blockIdx.x + 1]; ++c) {
+      const ItemDev& fa = items[fitem[c]];
+      int rowoff = fsonidx[c] == 0 ? 0 : items[fa.son[0]].k;
+      const double2* y = yh + yh_off[fitem[c]] * nr;
+      dot_rhs<NR>(s, fa.Q + (int64_t)(rowoff + kk) * fa.k, 1, y, fa.k, nr, false);
     }
-    yh[yh_off[i] + kk] = s;
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (q < nr) yh[(yh_off[i] + kk) * nr + q] = s[q];
   }
 }
 
 // leaf rows: y|L = sum_c Q_Lc yh_Lc + near-field rows of L.  One workgroup
 // of four waves per leaf, lane j one row of the leaf (leaves have at most 64
 // rows): the waves take the leaf's basis terms and near-field blocks in
-// turn, with four columns' loads in flight, and the partial sums are added
-// through LDS in wave order.
+// turn, and the partial sums are added through LDS in wave order.
+template <int NR>
 __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const LeafDev* leaves,
                                                   const NearRefDev* nref, const NearDev* nears,
                                                   const double2* nearv, const int64_t* yh_off,
                                                   const double2* yh, const double2* xp,
-                                                  double2* yp, int adjoint) {
-  __shared__ double2 part[4][64];
+                                                  double2* yp, int adjoint, int nr) {
+  __shared__ double2 part[4][NR][64];
   const LeafDev L = leaves[blockIdx.x];
   const int w = wave_id(), lane = threadIdx.x & 63;
   for (int j0 = 0; j0 < L.len; j0 += 64) {
     const int j = min(j0 + lane, L.len - 1);
-    double2 s = make_double2(0.0, 0.0);
-    auto add = [&](double2 a, double2 x, bool conj_a) {
-      double2 v = conj_a ? cmulc(a, x) : cmul(a, x);
-      s.x += v.x;
-      s.y += v.y;
-    };
+    double2 s[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
     for (int q = L.item_first + w; q < L.item_first + L.item_count; q += 4) {
       const ItemDev& it = items[q];
-      const double2* Qr = it.Q + (int64_t)j * it.k;
-      const double2* y = yh + yh_off[q];
-      for (int kk = 0; kk < it.k; ++kk) add(Qr[kk], y[kk], false);
+      dot_rhs<NR>(s, it.Q + (int64_t)j * it.k, 1, yh + yh_off[q] * nr, it.k, nr, false);
     }
     for (int64_t q = L.near_begin + w; q < L.near_end; q += 4) {
       const NearRefDev ref = nref[q];
       const NearDev nb = nears[ref.b];
-      const int64_t row = ref.row0 + j;  // row of the block (column for the adjoint)
       const double2* B = nearv + nb.off;
-      // op N: sum_c B[row, c] x[s_off + c]; adjoint: sum_c conj(B[c, row]) x[t_off + c]
-      const int64_t n = adjoint ? nb.t_len : nb.s_len;
-      const int64_t st = adjoint ? 1 : nb.t_len;
-      const double2* a0 = adjoint ? B + row * nb.t_len : B + row;
-      const double2* x = xp + (adjoint ? nb.t_off : nb.s_off);
-      int64_t c = 0;
-      for (; c + 3 < n; c += 4) {
-        double2 a_0 = a0[c * st], a_1 = a0[(c + 1) * st], a_2 = a0[(c + 2) * st],
-                a_3 = a0[(c + 3) * st];
-        double2 x0 = x[c], x1 = x[c + 1], x2 = x[c + 2], x3 = x[c + 3];
-        add(a_0, x0, adjoint);
-        add(a_1, x1, adjoint);
-        add(a_2, x2, adjoint);
-        add(a_3, x3, adjoint);
-      }
-      for (; c < n; ++c) add(a0[c * st], x[c], adjoint);
+      // op N: sum_c B[row, c] x[s_off + c]; adjoint: sum_c conj(B[c, row])
+      // x[t_off + c], with row = ref.row0 + j
+      const int64_t row = ref.row0 + j;
+      if (!adjoint)
+        dot_rhs<NR>(s, B + row, nb.t_len, xp + nb.s_off * nr, nb.s_len, nr, false);
+      else
+        dot_rhs<NR>(s, B + row * nb.t_len, 1, xp + nb.t_off * nr, nb.t_len, nr, true);
     }
-    part[w][lane] = s;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) part[w][q][lane] = s[q];
     __syncthreads();
     if (w == 0 && j0 + lane < L.len) {
-      double2 t = part[0][lane];
 #pragma unroll
-      for (int q = 1; q < 4; ++q) {
-        t.x += part[q][lane].x;
-        t.y += part[q][lane].y;
+      for (int q = 0; q < NR; ++q) {
+        if (q < nr) {
+          double2 t = part[0][q][lane];
+#pragma unroll
+          for (int u = 1; u < 4; ++u) {
+            t.x += part[u][q][lane].x;
+            t.y += part[u][q][lane].y;
+          }
+          yp[(L.row_off + j0 + lane) * nr + q] = t;
+        }
       }
-      yp[L.row_off + j0 + lane] = t;
     }
     __syncthreads();
   }
@@ -1345,9 +1399,18 @@ struct RowData {
   double x, y, z, f;   // Helmholtz: coordinates and row factor; dense: original index in x
 };
 
+// Padding rows and columns of the Helmholtz block rows: factor 0 at points far
+// from every real point and from each other, so that their entries are 0
+// without a distance clamp.
+constexpr double kPadRow = 1.0e10;
+__device__ __forceinline__ double4 pad_col() { return make_double4(-1.0e10, 0.0, 0.0, 0.0); }
+
+// far: padding rows of the mixed-form generator sit at kPadRow (the FP64
+// generator clamps the distance and keeps them at the origin)
 template <int SRC>
-__device__ __forceinline__ RowData row_data(const GeomDev& g, const ItemDev& it, int rho, int side) {
-  RowData r{0.0, 0.0, 0.0, 0.0};
+__device__ __forceinline__ RowData row_data(const GeomDev& g, const ItemDev& it, int rho, int side,
+                                            bool far = false) {
+  RowData r{SRC == SRC_HELMHOLTZ && far ? kPadRow : 0.0, 0.0, 0.0, 0.0};
   if (rho < it.m) {
     int64_t pos = it.row_off + rho;
     if constexpr (SRC == SRC_HELMHOLTZ) {
@@ -1399,21 +1462,22 @@ __device__ __forceinline__ double2 gen_entry(const GeomDev& g, const RowData& rw
   }
 }
 
-// Mixed form, Helmholtz: the same entry as complex FP32.
+// Mixed form, Helmholtz: the same entry as complex FP32.  The distance and
+// the phase are formed in FP64, sin and cos and the amplitude in FP32.
+// Padding rows and columns sit far apart (see kPadRow, kPadCol) with factor
+// 0, so the entry needs no clamp.
 __device__ __forceinline__ float2 gen_entry_mx(const GeomDev& g, const RowData& rw, double4 cc,
                                                int side) {
   double dx = rw.x - cc.x, dy = rw.y - cc.y, dz = rw.z - cc.z;
-  double r2 = fmax(dx * dx + dy * dy + dz * dz, 1e-300);
-  // 1/r: the hardware estimate (r2 is positive and finite, so no special
-  // cases) refined by one Newton step; r = r2 / r to full FP64 accuracy
+  double r2 = dx * dx + dy * dy + dz * dz;
+  // 1/r: the hardware estimate (about 2^-24 relative) refined by one Newton
+  // step; r = r2 / r to full FP64 accuracy
   double r0 = __builtin_amdgcn_rsq(r2);
   double e = fma(-r2 * r0, r0, 1.0);
   double ri = fma(0.5 * r0, e, r0);
   float sn, cs;
   sincos_mixed(g.kappa * (r2 * ri), sn, cs);
-  // the amplitude only needs FP32 (1/r is capped so that a padding factor 0
-  // meets a finite value even where the distance was clamped)
-  float a = (float)rw.f * (float)cc.w * fminf((float)ri, 3.0e38f);
+  float a = (float)rw.f * (float)cc.w * (float)ri;
   return make_float2(a * cs, side == 0 ? a * sn : -a * sn);
 }
 
@@ -1718,7 +1782,7 @@ __device__ __forceinline__ void rmax_flush(const ItemDev& it, const unsigned* s_
 template <bool MX, int KT>
 __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
                                const UnitDev& u, double zeta, const ROp<MX>* Qs,
-                               unsigned* s_rmax) {
+                               unsigned* s_rmax, int kc0 = 0) {
   using OT = ROp<MX>;
   using S = typename std::conditional<MX, float, double>::type;
   typedef S E2 __attribute__((ext_vector_type(2)));
@@ -1787,7 +1851,7 @@ __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemD
     }
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
-      int kk = 16 * t + row;
+      int kk = kc0 + 16 * t + row;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int64_t jv = j0 + acc[t].row(lane, v);
@@ -1834,6 +1898,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX && KT <=
   }
 }
 
+// Large transfer factors (Q_hat beyond the LDS of one workgroup): Q_hat is
+// packed into 64-column chunks in memory, (r + 8) x 64 each with zero rows
+// and columns past r and k, and each unit forms the 64 columns of R^T of one
+// chunk (unit field a0: the chunk index) for its column range.
+template <bool MX>
+__global__ __launch_bounds__(256) void k_rprod_inner_big(const ItemDev* items,
+                                                         const UnitDev* units, double zeta,
+                                                         const ROp<MX>* const* qchunk) {
+  __shared__ unsigned s_rmax[kMaxRBig];
+  const UnitDev u = units[blockIdx.x];
+  const ItemDev& it = items[u.item];
+  if (it.k == 0) return;
+  for (int kk = threadIdx.x; kk < kMaxRBig; kk += 256) s_rmax[kk] = 0u;
+  __syncthreads();
+  rprod_inner_wg<MX, 4>(it, items[it.son[0]], items[it.son[1]], u, zeta, qchunk[blockIdx.x],
+                        s_rmax, 64 * u.a0);
+  if constexpr (MX) {
+    __syncthreads();
+    rmax_flush(it, s_rmax);
+  }
+}
+
+// Packs Q_hat of large transfer factors into the chunks read above: task q
+// writes chunk c of item i (rows 0 .. r + 8, 64 columns) at dst.
+__global__ __launch_bounds__(256) void k_pack_q(const ItemDev* items, const int32_t* item,
+                                                const int32_t* chunk, void* const* dst,
+                                                int mixed) {
+  const ItemDev& it = items[item[blockIdx.x]];
+  const int r = it.r, k = it.k, c0 = 64 * chunk[blockIdx.x];
+  for (int e = threadIdx.x; e < (r + 8) * 64; e += 256) {
+    int i = e >> 6, kk = c0 + (e & 63);
+    double2 v = (i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0);
+    if (mixed)
+      reinterpret_cast<float2*>(dst[blockIdx.x])[e] = make_float2((float)v.x, (float)v.y);
+    else
+      reinterpret_cast<double2*>(dst[blockIdx.x])[e] = v;
+  }
+}
+
 // R^T of a leaf block row: the workgroup's four waves share the item's factor
 // Q (in LDS, compute precision) and take 16-column groups in turn.
 template <int SRC, bool MX, int KT>
@@ -1845,7 +1948,9 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
   int nks = (r + 3) / 4;
   for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
     int64_t j = u.col_begin + j0 + row;
-    double4 cc = j0 + row < u.ncols ? it.cols[j] : make_double4(0.0, 0.0, 0.0, 0.0);
+    double4 cc = j0 + row < u.ncols ? it.cols[j]
+                                    : (MX && SRC == SRC_HELMHOLTZ
+                                           ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0));
     RAcc<MX> acc[KT];
     if constexpr (MX && SRC == SRC_HELMHOLTZ) {
       // the lane's entries of all k-steps first (independent chains), then
@@ -1908,7 +2013,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX ? 4 : 1)
     int i = e / ldq, kk = e - i * ldq;
     Qs[e] = rop<MX>((i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0));
   }
-  for (int i = threadIdx.x; i < 72; i += 256) rows[i] = row_data<SRC>(g, it, i, side);
+  for (int i = threadIdx.x; i < 72; i += 256) rows[i] = row_data<SRC>(g, it, i, side, MX);
   for (int kk = threadIdx.x; kk < 64; kk += 256) s_rmax[kk] = 0u;
   __syncthreads();
   switch (kt) {
@@ -1926,17 +2031,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX ? 4 : 1)
 // ---------------------------------------------------------------------------
 // Gram matrices of the mixed form on int8 MFMA (error-free slicing).
 // Each real component x of row i of the block row is written as
-//   x = 2^(E_i - 7) (q1 + q2 2^-7 + q3 2^-14 + q4 2^-21) + rest,
-// with integer slices |q| <= 127 taken by truncation (every step exact in
-// FP32) and E_i the exponent of a bound of the row's largest component over
-// the unit, so |rest| < 2^(E_i - 28).  Products of slices accumulate exactly
-// in int32 (16x16x64 MFMA); slice pairs with p + q <= 7 are kept (the
-// dropped ones are below 2^-42 of the product of the row maxima), summed per
-// p + q, and converted to FP64 once per unit.  The complex Gram
-// A A^* = (Ar Ar^T + Ai Ai^T) + i (Ai Ar^T - Ar Ai^T) takes four real
-// products per 16 x 16 tile pair.  One workgroup of 8 waves per unit: all
-// threads generate (leaf) or load (non-leaf) and slice the next 64 columns
-// into LDS while the waves run the MFMAs of the current 64 columns.
+//   x = 2^(E_i - 6) (d0 + d1 2^-8 + d2 2^-16 + d3 2^-24) + rest,
+// with signed digits d in [-128, 127] of the truncated fixed-point value
+// (balanced base 256) and E_i the exponent of a bound of the row's largest
+// component over the unit, so |rest| < 2^(E_i - 30).  Products of digits
+// accumulate exactly in int32 (16x16x64 MFMA); digit pairs with p + q <= 5
+// (0-based) are kept (each dropped pair is below 2^-46 of the product of the
+// row maxima per column), summed per p + q, and converted to FP64 once per
+// unit.  The complex Gram A A^* = (Ar Ar^T + Ai Ai^T) + i (Ai Ar^T - Ar Ai^T)
+// takes four real products per 16 x 16 tile pair.  One workgroup of 16 waves
+// per unit: all threads generate (leaf) or load (non-leaf) and slice the
+// next 64 columns into LDS while the waves run the MFMAs of the current 64
+// columns.
 // ---------------------------------------------------------------------------
 typedef int ivec4 __attribute__((ext_vector_type(4)));
 
@@ -1957,22 +2063,31 @@ __device__ __forceinline__ int i8_off(int T, int comp, int p, int g, int i) {
   return ((((T * 2 + comp) * 4 + p) * 4 + g) * 16 + i) * 16;
 }
 
-// Four int8 slices of 4 values, packed one dword each.  sc = 2^(28 - E)
-// with |v| < 2^E, so Y = trunc(v sc) fits 28 bits and
-// Y = q1 2^21 + q2 2^14 + q3 2^7 + q4 exactly, with q1 = floor(Y / 2^21) in
-// [-128, 127] and q2, q3, q4 in [0, 127] (two's complement bit fields).
+// Four int8 slices of 4 values, packed one dword each (out[p] holds slice p
+// of value q in byte q; slice 0 is the most significant).  sc = 2^(30 - E)
+// with |v| < 2^E, so Y = trunc(v sc) has |Y| < 2^30 and, in balanced base
+// 256, Y = d0 2^24 + d1 2^16 + d2 2^8 + d3 exactly with digits in
+// [-128, 127]: Z = Y + 0x808080 has the bytes z3 z2 z1 z0, the three low
+// digits are z - 128 (the byte XOR 0x80) and the top digit is z3 read as a
+// signed byte.  The bytes of the four Z are transposed with byte permutes.
 __device__ __forceinline__ void i8_slice4(const float* v, float sc, unsigned* out) {
-  unsigned w[4] = {0, 0, 0, 0};
+  unsigned z[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int Y = (int)(v[q] * sc);
-    unsigned u = (unsigned)Y;
-    unsigned b[4] = {(unsigned)(Y >> 21) & 0xffu, (u >> 14) & 0x7fu, (u >> 7) & 0x7fu, u & 0x7fu};
-#pragma unroll
-    for (int p = 0; p < 4; ++p) w[p] |= b[p] << (8 * q);
-  }
-#pragma unroll
-  for (int p = 0; p < 4; ++p) out[p] = w[p];
+  for (int q = 0; q < 4; ++q) z[q] = (unsigned)((int)(v[q] * sc) + 0x808080);
+  // {z0.b0, z1.b0, z0.b1, z1.b1} and {z0.b2, z1.b2, z0.b3, z1.b3}, same for z2, z3
+  const unsigned lo01 = __builtin_amdgcn_perm(z[1], z[0], 0x05010400u);
+  const unsigned hi01 = __builtin_amdgcn_perm(z[1], z[0], 0x07030602u);
+  const unsigned lo23 = __builtin_amdgcn_perm(z[3], z[2], 0x05010400u);
+  const unsigned hi23 = __builtin_amdgcn_perm(z[3], z[2], 0x07030602u);
+  // byte b of every value: {z0.bb, z1.bb, z2.bb, z3.bb}
+  const unsigned b0 = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+  const unsigned b1 = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+  const unsigned b2 = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+  const unsigned b3 = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+  out[0] = b3;
+  out[1] = b2 ^ 0x80808080u;
+  out[2] = b1 ^ 0x80808080u;
+  out[3] = b0 ^ 0x80808080u;
 }
 
 template <int KIND>  // 0: generated leaf block rows, 1: non-leaf block rows from the sons' R,
@@ -2004,14 +2119,17 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
   for (int e = tid; e < ntile * 16; e += kI8Threads) {
     rmaxb[e] = 0u;
     if constexpr (KIND != 1)
-      rowd[e] = row_data<KIND == 2 ? SRC_DLP : SRC_HELMHOLTZ>(g, it, row0(e >> 4) + (e & 15), side);
+      rowd[e] = row_data<KIND == 2 ? SRC_DLP : SRC_HELMHOLTZ>(g, it, row0(e >> 4) + (e & 15), side,
+                                                             true);
   }
   auto stage_cols = [&](int c, int buf) {
     if constexpr (KIND != 1) {
       if (tid < 64) {
         int64_t j = (int64_t)c * 64 + tid;
-        cold[buf * 64 + tid] = (c < nch && j < ncols) ? it.cols[u.col_begin + j]
-                                                      : make_double4(0.0, 0.0, 0.0, 0.0);
+        // double layer: the column data hold positions, padding reads point 0
+        cold[buf * 64 + tid] = (c < nch && j < ncols)
+                                   ? it.cols[u.col_begin + j]
+                                   : (KIND == 0 ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0));
       }
     }
   };
@@ -2150,7 +2268,7 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
       if (cb < ntile * 256) {
         int i = cb & 15, pp = (cb >> 4) & 3, gg = (cb >> 6) & 3, T = cb >> 8;
         int E = rexp[T * 16 + i];
-        float sc = E > -100000 ? ldexpf(1.0f, 28 - E) : 0.0f;
+        float sc = E > -100000 ? ldexpf(1.0f, 30 - E) : 0.0f;
         float vr[4], vi[4];
         if constexpr (KIND != 1) {
           const RowData rw = rowd[T * 16 + i];
@@ -2264,9 +2382,9 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
         int row = 4 * (lane >> 4) + v, col = lane & 15;
         double x = 0.0;
 #pragma unroll
-        for (int l = 5; l >= 0; --l) x = x * 0.0078125 + (double)acc[s][l][v];
+        for (int l = 5; l >= 0; --l) x = x * 0.00390625 + (double)acc[s][l][v];
         int Ea = rexp[TA * 16 + row], Eb = rexp[TB * 16 + col];
-        x = (Ea > -100000 && Eb > -100000) ? ldexp(x, Ea + Eb - 14) : 0.0;
+        x = (Ea > -100000 && Eb > -100000) ? ldexp(x, Ea + Eb - 12) : 0.0;
         conv[q * 256 + row * 16 + col] = x;
       }
     }
@@ -2371,13 +2489,23 @@ void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rm
   if (nl == 0) return;
   static std::once_flag attr;
   std::call_once(attr, [] {
-    (void)hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)(kEigLds * sizeof(double2)));
+    (void)hipFuncSetAttribute((const void*)k_factor<kMaxR, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kEigLds * sizeof(double2)));
   });
   // X needs r columns plus one for the even pairing
   int cap = std::min(kEigLds, std::max(2, rmax * (rmax + 1)));
-  hipLaunchKernelGGL(k_factor, dim3(nl), dim3(kFacThreads), (size_t)cap * sizeof(double2), st,
-                     items, litems, eps, max_sweeps, cap, status);
+  hipLaunchKernelGGL((k_factor<kMaxR, false>), dim3(nl), dim3(kFacThreads),
+                     (size_t)cap * sizeof(double2), st, items, litems, eps, max_sweeps, cap,
+                     status, nullptr);
+}
+
+void launch_factor_big(ItemDev* items, const int32_t* litems, int32_t nl, double eps,
+                       int max_sweeps, int32_t* status, double2* const* xptr, hipStream_t st) {
+  if (nl == 0) return;
+  // X of item q at xptr[q] with room for r (r + 1) elements: all r columns
+  hipLaunchKernelGGL((k_factor<kMaxRBig, true>), dim3(nl), dim3(kFacThreads), 0, st, items,
+                     litems, eps, max_sweeps, kMaxRBig * (kMaxRBig + 1), status, xptr);
 }
 
 void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int32_t* litems,
@@ -2484,6 +2612,25 @@ void launch_rprod_inner(bool mixed, int kt, const ItemDev* items, const UnitDev*
     launch_rpi_kt<true>(kt, items, units, nunits, zeta, lds, st);
   else
     launch_rpi_kt<false>(kt, items, units, nunits, zeta, lds, st);
+}
+
+void launch_pack_q(const ItemDev* items, const int32_t* item, const int32_t* chunk,
+                   void* const* dst, int64_t ntasks, bool mixed, hipStream_t st) {
+  if (ntasks == 0) return;
+  hipLaunchKernelGGL(k_pack_q, dim3((unsigned)ntasks), dim3(256), 0, st, items, item, chunk, dst,
+                     mixed ? 1 : 0);
+}
+
+void launch_rprod_inner_big(bool mixed, const ItemDev* items, const UnitDev* units,
+                            int64_t nunits, double zeta, const void* const* qchunk,
+                            hipStream_t st) {
+  if (nunits == 0) return;
+  if (mixed)
+    hipLaunchKernelGGL(k_rprod_inner_big<true>, dim3((unsigned)nunits), dim3(256), 0, st, items,
+                       units, zeta, (const float2* const*)qchunk);
+  else
+    hipLaunchKernelGGL(k_rprod_inner_big<false>, dim3((unsigned)nunits), dim3(256), 0, st, items,
+                       units, zeta, (const double2* const*)qchunk);
 }
 
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st) {
@@ -2622,46 +2769,72 @@ hipError_t noalloc_scratch(void** out) {
 }
 
 void launch_gather_perm(const double2* x, const int64_t* perm, int64_t n, double2* xp,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, perm, n, xp);
+                        hipStream_t st, int nr) {
+  hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, perm, n, nr,
+                     xp);
 }
 void launch_scatter_perm(const double2* yp, const int64_t* perm, int64_t n, double2* y,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter_perm, dim3(blocks_for(n, 256)), dim3(256), 0, st, yp, perm, n, y);
+                         hipStream_t st, int nr) {
+  hipLaunchKernelGGL(k_scatter_perm, dim3(blocks_for(n, 256)), dim3(256), 0, st, yp, perm, n, nr,
+                     y);
 }
+
+// the right-hand-side bound of the kernel instance: 1, 2, 4 or 8
+#define DH2_NR_DISPATCH(nr, ...)                        \
+  do {                                                  \
+    if ((nr) <= 1) {                                    \
+      constexpr int NR = 1;                             \
+      __VA_ARGS__;                                      \
+    } else if ((nr) <= 2) {                             \
+      constexpr int NR = 2;                             \
+      __VA_ARGS__;                                      \
+    } else if ((nr) <= 4) {                             \
+      constexpr int NR = 4;                             \
+      __VA_ARGS__;                                      \
+    } else {                                            \
+      constexpr int NR = 8;                             \
+      __VA_ARGS__;                                      \
+    }                                                   \
+  } while (0)
+
 void launch_fwd_leaf(const ItemDev* items, const int32_t* litems, int32_t nl,
-                     const int64_t* xh_off, const double2* xp, double2* xh, hipStream_t st) {
+                     const int64_t* xh_off, const double2* xp, double2* xh, int nr,
+                     hipStream_t st) {
   if (nl == 0) return;
-  hipLaunchKernelGGL(k_fwd_leaf, dim3(nl), dim3(128), 0, st, items, litems, xh_off, xp, xh);
+  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_fwd_leaf<NR>, dim3(nl), dim3(128), 0, st, items, litems,
+                                         xh_off, xp, xh, nr));
 }
 void launch_fwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
-                      const int64_t* xh_off, double2* xh, hipStream_t st) {
+                      const int64_t* xh_off, double2* xh, int nr, hipStream_t st) {
   if (nl == 0) return;
-  hipLaunchKernelGGL(k_fwd_inner, dim3(nl), dim3(128), 0, st, items, litems, xh_off, xh);
+  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_fwd_inner<NR>, dim3(nl), dim3(128), 0, st, items,
+                                         litems, xh_off, xh, nr));
 }
 void launch_coupling(const ItemDev* items, int32_t nitems, const int64_t* cbegin,
                      const int32_t* cblock, const int32_t* cpartner, const double2* const* S_ptr,
                      const int32_t* S_rows, const int32_t* S_cols, const int64_t* xh_off,
-                     const double2* xh, const int64_t* yh_off, double2* yh, int adjoint,
+                     const double2* xh, const int64_t* yh_off, double2* yh, int adjoint, int nr,
                      hipStream_t st) {
   if (nitems == 0) return;
-  hipLaunchKernelGGL(k_coupling, dim3((nitems + 3) / 4), dim3(256), 0, st, items, nitems, cbegin, cblock,
-                     cpartner, S_ptr, S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint);
+  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_coupling<NR>, dim3((nitems + 3) / 4), dim3(256), 0, st,
+                                         items, nitems, cbegin, cblock, cpartner, S_ptr, S_rows,
+                                         S_cols, xh_off, xh, yh_off, yh, adjoint, nr));
 }
 void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* fbegin, const int32_t* fitem, const int32_t* fsonidx,
-                      const int64_t* yh_off, double2* yh, hipStream_t st) {
+                      const int64_t* yh_off, double2* yh, int nr, hipStream_t st) {
   if (nl == 0) return;
-  hipLaunchKernelGGL(k_bwd_inner, dim3(nl), dim3(128), 0, st, items, litems, fbegin, fitem,
-                     fsonidx, yh_off, yh);
+  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_bwd_inner<NR>, dim3(nl), dim3(128), 0, st, items,
+                                         litems, fbegin, fitem, fsonidx, yh_off, yh, nr));
 }
 void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleaves,
                      const NearRefDev* nref, const NearDev* nears, const double2* nearv,
                      const int64_t* yh_off, const double2* yh, const double2* xp, double2* yp,
-                     int adjoint, hipStream_t st) {
+                     int adjoint, int nr, hipStream_t st) {
   if (nleaves == 0) return;
-  hipLaunchKernelGGL(k_bwd_leaf, dim3(nleaves), dim3(256), 0, st, items, leaves, nref, nears,
-                     nearv, yh_off, yh, xp, yp, adjoint);
+  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_bwd_leaf<NR>, dim3(nleaves), dim3(256), 0, st, items,
+                                         leaves, nref, nears, nearv, yh_off, yh, xp, yp, adjoint,
+                                         nr));
 }
 void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
                    const double2* xp, int adjoint, double2* out, hipStream_t st) {

@@ -29,6 +29,10 @@ void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
 void launch_ranks(const ItemDev* items, int32_t n, int32_t* out, hipStream_t st);
 void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rmax, double eps,
                    int max_sweeps, int32_t* status, hipStream_t st);
+// factors with r up to kMaxRBig, X of the q-th listed item at xptr[q]
+// (r (r + 1) complex elements)
+void launch_factor_big(ItemDev* items, const int32_t* litems, int32_t nl, double eps,
+                       int max_sweeps, int32_t* status, double2* const* xptr, hipStream_t st);
 // Column data (x, y, z, factor) of the listed leaf items into their it.cols.
 void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int32_t* litems,
                       int32_t nl, const EntDev* ents, int side, hipStream_t st);
@@ -47,6 +51,14 @@ void launch_rprod_leaf(int src, bool mixed, const GeomDev& g, const ItemDev* ite
                        hipStream_t st);
 void launch_rprod_inner(bool mixed, int kt, const ItemDev* items, const UnitDev* units,
                         int64_t nunits, double zeta, size_t lds, hipStream_t st);
+// Large transfer factors: Q_hat of item[q] packed into 64-column chunk
+// chunk[q] at dst[q] ((r + 8) x 64, compute precision); R^T units with the
+// chunk index in UnitDev::a0 and the chunk's address in qchunk[unit]
+void launch_pack_q(const ItemDev* items, const int32_t* item, const int32_t* chunk,
+                   void* const* dst, int64_t ntasks, bool mixed, hipStream_t st);
+void launch_rprod_inner_big(bool mixed, const ItemDev* items, const UnitDev* units,
+                            int64_t nunits, double zeta, const void* const* qchunk,
+                            hipStream_t st);
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_cvt(const CvtDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
@@ -70,26 +82,30 @@ void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t*
 // matrix-vector product (looked up once per device), and its size in bytes.
 hipError_t noalloc_scratch(void** out);
 size_t noalloc_scratch_bytes();
+// Matrix-vector product kernels.  Work vectors hold nr <= 8 right-hand
+// sides interleaved (entry p of right-hand side q at [p * nr + q]); the
+// caller's vectors are column-major (x[q * n + i]).
 void launch_gather_perm(const double2* x, const int64_t* perm, int64_t n, double2* xp,
-                        hipStream_t st);
+                        hipStream_t st, int nr = 1);
 void launch_scatter_perm(const double2* yp, const int64_t* perm, int64_t n, double2* y,
-                         hipStream_t st);
+                         hipStream_t st, int nr = 1);
 void launch_fwd_leaf(const ItemDev* items, const int32_t* litems, int32_t nl,
-                     const int64_t* xh_off, const double2* xp, double2* xh, hipStream_t st);
+                     const int64_t* xh_off, const double2* xp, double2* xh, int nr,
+                     hipStream_t st);
 void launch_fwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
-                      const int64_t* xh_off, double2* xh, hipStream_t st);
+                      const int64_t* xh_off, double2* xh, int nr, hipStream_t st);
 void launch_coupling(const ItemDev* items, int32_t nitems, const int64_t* cbegin,
                      const int32_t* cblock, const int32_t* cpartner, const double2* const* S_ptr,
                      const int32_t* S_rows, const int32_t* S_cols, const int64_t* xh_off,
-                     const double2* xh, const int64_t* yh_off, double2* yh, int adjoint,
+                     const double2* xh, const int64_t* yh_off, double2* yh, int adjoint, int nr,
                      hipStream_t st);
 void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* fbegin, const int32_t* fitem, const int32_t* fsonidx,
-                      const int64_t* yh_off, double2* yh, hipStream_t st);
+                      const int64_t* yh_off, double2* yh, int nr, hipStream_t st);
 void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleaves,
                      const NearRefDev* nref, const NearDev* nears, const double2* nearv,
                      const int64_t* yh_off, const double2* yh, const double2* xp, double2* yp,
-                     int adjoint, hipStream_t st);
+                     int adjoint, int nr, hipStream_t st);
 void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
                    const double2* xp, int adjoint, double2* out, hipStream_t st);
 

@@ -77,3 +77,67 @@ def test_batch_empty_and_invalid():
     om = dh2.opts(leaf_size=64, precision=dh2.MIXED)
     with pytest.raises(dh2.DH2Error):
         dh2.compress_batch([b], [None], 1e-6, om)
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_batch_against_oracle(form):
+    """One instance of each surface of the batch workload (sphere, rotated
+    ellipsoid, cube surface with uniform random points), compressed in one
+    batched call, against the FP64 oracle: singular values and ranks of every
+    block row of both bases (tolerances of test_gpu_parity), and the exact
+    relative spectral error <= 1.1 eps and within 10 % of the oracle's."""
+    import math
+
+    from dh2_export import exported_bases, exported_dense
+    from oracle import compress as OC
+    from oracle import dh2 as OD
+    from oracle import plan as OP
+    from paper_1510_07087_amd import dh2
+    surf = [("sphere", *synth.fibonacci_sphere(1800)),
+            ("ellipsoid", *synth.ellipsoid(2100, (0.9, 0.6, 0.35), seed=5)),
+            ("cube", *synth.cube_surface(2400, 6))]
+    prec = dh2.MIXED if form == "mixed" else dh2.FP64
+    o = dh2.opts(leaf_size=64, precision=prec)
+    blocks = [dh2.blocks_build(dh2.tree_build(p, math.sqrt(len(p)) / 5.66, o), o)
+              for _, p, _ in surf]
+    ms = dh2.compress_batch(blocks, [w for _, _, w in surf], EPS, o)
+    torch.cuda.synchronize()
+    for (name, p, w), m in zip(surf, ms):
+        n, kappa = len(p), math.sqrt(len(p)) / 5.66
+        plan = OP.build_plan(p, kappa, 64)
+        M = OM.HelmholtzMatrix(p, w, kappa, plan.tree.perm)
+        ref = OC.compress(M, plan, EPS)
+        n_tie = n_chk = 0
+        for side, basis_ref in ((0, ref.V), (1, ref.W)):
+            data, _ = exported_bases(m, plan, side)
+            for key, sig_ref in basis_ref.sigma.items():
+                k, _, sig = data[key]
+                fro = float(np.sqrt(np.sum(sig_ref ** 2)))
+                s_ref = np.zeros(len(sig))
+                s_ref[:min(len(sig_ref), len(sig))] = sig_ref[:len(sig)]
+                big = s_ref > EPS
+                if form == "mixed":
+                    d = np.abs(sig[big] - s_ref[big]) / fro
+                    assert np.all(d <= 2e-7), (name, key, d.max())
+                    tie = np.any(np.abs(sig_ref - EPS) <= 2e-7 * fro)
+                else:
+                    tl = 1e-13 * fro ** 2 + max(1e-4 * EPS ** 2,
+                                                64 * 2.220446049250313e-16 * len(sig_ref) * fro ** 2)
+                    d = np.abs(sig[big] ** 2 - s_ref[big] ** 2)
+                    assert np.all(d <= tl + 1e-10 * s_ref[big] ** 2), (name, key)
+                    tie = np.any(np.abs(sig_ref ** 2 - EPS ** 2) <= tl + 1e-10 * EPS ** 2)
+                n_chk += 1
+                if tie:
+                    n_tie += 1
+                    assert abs(k - basis_ref.k[key]) <= 1
+                else:
+                    assert k == basis_ref.k[key], (name, key, k, basis_ref.k[key])
+        G = OM.helmholtz_dense_original(p, w, kappa)
+        Gt = exported_dense(m, plan)[0]
+        err = np.linalg.norm(G - Gt, 2) / np.linalg.norm(G, 2)
+        err_ref = np.linalg.norm(G - OD.reconstruct(ref), 2) / np.linalg.norm(G, 2)
+        print(f"[gpu batch] {form} {name} n={n}: {n_chk} block rows ({n_tie} ties), rel err "
+              f"{err:.3e}, oracle {err_ref:.3e}", flush=True)
+        assert n_tie < max(2, n_chk // 20)
+        assert err <= 1.1 * EPS
+        assert 0.9 * err_ref <= err <= 1.1 * err_ref + 1e-3 * EPS
