@@ -105,6 +105,13 @@ struct CvtDev {
   int64_t count;
 };
 
+// Copy task: bytes (a multiple of 8) from src to dst, both 8-byte aligned.
+struct CopyDev {
+  const void* src;
+  void* dst;
+  int64_t bytes;
+};
+
 // Expansion task: rows of one son inside Wexp_sc = Wexp_{s_i c'} E_{s_i c}.
 struct ExpandDev {
   const double2* src; // Wexp of the son (rows x ks) row-major

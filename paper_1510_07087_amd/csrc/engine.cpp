@@ -6,12 +6,14 @@
 // entries generated from the points; other clusters: zeta [R_t1c'; R_t2c']
 // read from the sons' coefficient matrices), factorisation into singular
 // values and left singular vectors, rank read-back, then R_tc = Q^* A.  The
-// column basis (rows of G^*) is built first and expanded level by level; the
-// row sweep then projects every admissible block right after its R_tc is
-// formed: S_b = omega_b R_tc|s W_sc = V^* G|_b W.  Subtrees rooted above the
-// first level with admissible blocks are independent and are swept in
-// batches to bound the memory of the R matrices (the paper parallelises
-// over independent subtrees in the same way).
+// column basis (rows of G^*) and the row basis are independent and are built
+// at the same time on two streams; the column basis is expanded level by
+// level, the row sweep keeps the own-block columns of every R_tc, and after
+// both every admissible block is projected: S_b = omega_b R_tc|s W_sc =
+// V^* G|_b W.  Subtrees rooted above the first level with admissible blocks
+// are independent and are swept in batches to bound the memory of the R
+// matrices (the paper parallelises over independent subtrees in the same
+// way).
 #include "engine.hpp"
 
 #include <algorithm>
@@ -666,49 +668,43 @@ static int64_t npairs_of(int r) {
   return (int64_t)nt * (nt + 1) / 2;
 }
 
-// Hand-over between the two sweeps when they run at the same time: the
-// column sweep expands each level's column basis right after forming it and
-// marks the level ready (host flag plus an event on its stream); the row
-// sweep waits for that before projecting the blocks of the level (admissible
-// blocks join clusters of one level).
-struct LevelSync {
-  std::mutex mu;
-  std::condition_variable cv;
-  std::vector<int> ready;         // per level
-  std::vector<hipEvent_t> ev;     // per level, recorded on the column stream
-  bool abort = false;             // the column sweep failed
-  ~LevelSync() {
-    for (hipEvent_t e : ev)
-      if (e) (void)hipEventDestroy(e);
+// The own-block columns of the row sweep's R for items [lo, hi) (the tail
+// [ninh, N) of each column set, one contiguous piece of R^T) copied into an
+// arena kept until the projection; S.own[i] points at item i's piece.
+static void keep_own_columns(MatrixData& M, int32_t lo, int32_t hi, size_t esz, hipStream_t st,
+                             DevMem& mem) {
+  Side& S = M.side[0];
+  int64_t total = 0;
+  for (int32_t i = lo; i < hi; ++i)
+    total += (S.items[i].N - S.P->ninh[i]) * (int64_t)S.items[i].k;
+  if (total == 0) return;
+  char* arena = (char*)mem.alloc((size_t)total * esz);
+  S.own_keep.push_back(arena);
+  std::vector<CopyDev> tasks;
+  int64_t o = 0;
+  for (int32_t i = lo; i < hi; ++i) {
+    const ItemDev& it = S.items[i];
+    const int64_t cnt = (it.N - S.P->ninh[i]) * (int64_t)it.k;
+    S.own[i] = arena + o * esz;
+    if (cnt > 0)
+      tasks.push_back(CopyDev{(const char*)it.R + S.P->ninh[i] * it.k * esz, arena + o * esz,
+                              (int64_t)(cnt * esz)});
+    o += cnt;
   }
-  void mark(int lv, hipStream_t st) {
-    hip_check(hipEventRecord(ev[lv], st), "level event");
-    std::lock_guard<std::mutex> lk(mu);
-    ready[lv] = 1;
-    cv.notify_all();
-  }
-  void fail_all() {
-    std::lock_guard<std::mutex> lk(mu);
-    abort = true;
-    cv.notify_all();
-  }
-  void wait(int lv, hipStream_t st) {
-    std::unique_lock<std::mutex> lk(mu);
-    cv.wait(lk, [&] { return ready[lv] || abort; });
-    if (!ready[lv]) fail(DH2_EDEVICE, "column sweep failed");
-    lk.unlock();
-    hip_check(hipStreamWaitEvent(st, ev[lv], 0), "level wait");
-  }
-};
+  CopyDev* d_tasks = upload(mem, tasks, st);
+  launch_copy_bytes(d_tasks, (int64_t)tasks.size(), st);
+  launch_check("own columns");
+  mem.release(d_tasks);
+}
 
 static void expand_level(MatrixData& M, int s, int32_t lv, hipStream_t st, DevMem& mem);
 
 static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepStats& ss,
-                  int32_t* d_status, DevMem& mem, LevelSync* sync = nullptr) {
+                  int32_t* d_status, DevMem& mem) {
   const BlocksData& B = *M.blk;
   const ClusterTree& tr = B.tree->tr;
   Side& S = M.side[s];
-  PhaseTimer tg(st), tp(st), tgl(st);
+  PhaseTimer tg(st), tgl(st);
   double2* partial = nullptr;
   size_t partial_cap = 0;
   const bool mixed = M.precision == DH2_MIXED;
@@ -718,10 +714,7 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
     void* R_prev = nullptr;
     for (int32_t lv = tr.depth; lv >= 0; --lv) {
       auto [lo, hi] = S.P->range[b][lv];
-      if (lo == hi) {
-        if (sync && s == 1) sync->mark(lv, st);
-        continue;
-      }
+      if (lo == hi) continue;
       int32_t n = hi - lo;
       tr_.mark("level start", s, b, lv);
       // factor sizes of non-leaf items from the sons' ranks
@@ -1096,161 +1089,9 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       launch_check("rprod (non-leaf)");
       if (trace_on()) hip_check(hipStreamSynchronize(st), "trace sync");
       tr_.mark("rprod", s, b, lv);
-      // column sweep run beside the row sweep: expand this level's basis now
-      if (sync && s == 1) {
-        expand_level(M, s, lv, st, mem);
-        sync->mark(lv, st);
-      }
-      // projection of the admissible blocks of this level (row sweep)
-      if (s == 0) {
-        if (sync) sync->wait(lv, st);
-        // tasks in the plan's order (sorted by column item), coupling
-        // matrices in that order; tiled kernel for ks <= 64, one launch per
-        // (row tiles per pass, column tiles); ranks above 64 by the generic
-        // kernel
-        const auto& pl = M.plan->proj[(size_t)b * (tr.depth + 1) + lv];
-        int64_t sumS = 0;
-        for (const ProjPlan& q : pl)
-          sumS += (int64_t)S.items[q.item].k * M.side[1].items[q.witem].k;
-        double2* Sarena = (double2*)mem.alloc(std::max<int64_t>(1, sumS) * sizeof(double2));
-        S.keep.push_back(Sarena);
-        // launch class: (row tiles per pass, column tiles, split) or the generic kernel
-        constexpr int kGeneric = 32;
-        std::vector<uint8_t> key(pl.size(), 255);
-        int64_t count[kGeneric + 1] = {0};
-        std::vector<ProjDev> tasks(pl.size());
-        int64_t o = 0;
-        for (size_t x = 0; x < pl.size(); ++x) {
-          const ProjPlan& q = pl[x];
-          const ItemDev& it = S.items[q.item];
-          int32_t ks = M.side[1].items[q.witem].k;
-          ProjDev& pd = tasks[x];
-          pd.R = (const char*)it.R + q.col * it.k * esz;
-          pd.W = mixed ? (const void*)M.side[1].wexp32[q.witem] : (const void*)M.side[1].wexp[q.witem];
-          pd.S = Sarena + o;
-          pd.kt = it.k;
-          pd.ks = ks;
-          pd.ns = q.ns;
-          pd.b = q.b;
-          M.S_ptr[q.b] = Sarena + o;
-          M.S_rows[q.b] = it.k;
-          M.S_cols[q.b] = ks;
-          o += (int64_t)it.k * ks;
-          ss.flops_prj += 8.0 * it.k * (double)ks * (double)q.ns;
-          if (it.k == 0 || ks == 0) continue;
-          if (mixed && ks <= 64) continue;  // stacked kernel below
-          int nj = (ks + 15) / 16, ni = (it.k + 15) / 16;
-          int kx = kGeneric;
-          if (nj <= 4)
-            kx = (q.ns >= 128 ? 16 : 0) +
-                 (std::min(ni, project_rows_per_pass(mixed, nj)) - 1) * 4 + (nj - 1);
-          key[x] = (uint8_t)kx;
-          ++count[kx];
-        }
-        // stable counting sort by launch class
-        std::vector<ProjDev> sorted;
-        std::vector<std::array<int64_t, 4>> launches;  // ni, nj, split, count
-        {
-          int64_t start[kGeneric + 1], run = 0;
-          for (int kx = 0; kx <= kGeneric; ++kx) {
-            start[kx] = run;
-            run += count[kx];
-            if (count[kx] == 0) continue;
-            if (kx < kGeneric)
-              launches.push_back({(kx % 16) / 4 + 1, kx % 4 + 1, kx / 16, count[kx]});
-            else
-              launches.push_back({0, 0, 0, count[kx]});
-          }
-          sorted.resize(run);
-          for (size_t x = 0; x < pl.size(); ++x)
-            if (key[x] != 255) sorted[start[key[x]]++] = tasks[x];
-        }
-        // mixed form, ks <= 64: the blocks of each run of equal column item
-        // (the plan is sorted by it) stacked row-wise, cut into tiles of up
-        // to 64 rows, tiles sorted by ceil(ks / 4)
-        std::vector<PBlkDev> pblk;
-        std::vector<PTileDev> ptile;
-        int64_t ncount[17] = {0};
-        if (mixed) {
-          std::vector<uint8_t> tnc;
-          for (size_t g0 = 0; g0 < pl.size();) {
-            size_t g1 = g0;
-            while (g1 < pl.size() && pl[g1].witem == pl[g0].witem) ++g1;
-            const int32_t ks = M.side[1].items[pl[g0].witem].k;
-            if (ks == 0 || ks > 64) {
-              g0 = g1;
-              continue;
-            }
-            const int32_t b0 = (int32_t)pblk.size();
-            for (size_t x = g0; x < g1; ++x)
-              if (tasks[x].kt > 0)
-                pblk.push_back(PBlkDev{(const float2*)tasks[x].R, tasks[x].S, tasks[x].kt, tasks[x].b});
-            const int32_t b1 = (int32_t)pblk.size();
-            int32_t bi = b0, i0 = 0;
-            while (bi < b1) {
-              PTileDev t;
-              t.W = M.side[1].wexp32[pl[g0].witem];
-              t.blk0 = bi;
-              t.i0 = i0;
-              t.ns = pl[g0].ns;
-              t.ks = ks;
-              int32_t rows = 0, nblk = 0;
-              while (rows < 64 && bi < b1) {
-                int32_t take = std::min(64 - rows, pblk[bi].kt - i0);
-                rows += take;
-                i0 += take;
-                ++nblk;
-                if (i0 == pblk[bi].kt) {
-                  ++bi;
-                  i0 = 0;
-                }
-              }
-              t.rows = rows;
-              t.nblk = nblk;
-              ptile.push_back(t);
-              tnc.push_back((uint8_t)((ks + 3) / 4));
-              ++ncount[(ks + 3) / 4];
-            }
-            g0 = g1;
-          }
-          std::vector<PTileDev> tsorted(ptile.size());
-          int64_t start[17], run = 0;
-          for (int c = 0; c <= 16; ++c) {
-            start[c] = run;
-            run += ncount[c];
-          }
-          for (size_t x = 0; x < ptile.size(); ++x) tsorted[start[tnc[x]]++] = ptile[x];
-          ptile.swap(tsorted);
-        }
-        ProjDev* d_tasks = upload(mem, sorted, st);
-        PBlkDev* d_pblk = upload(mem, pblk, st);
-        PTileDev* d_ptile = upload(mem, ptile, st);
-        tr_.mark("proj tasks", s, b, lv);
-        tp.start();
-        {
-          int64_t toff = 0;
-          for (int c = 1; c <= 16; ++c) {
-            launch_project_stacked(c, d_ptile + toff, ncount[c], d_pblk, M.d_omega, st);
-            toff += ncount[c];
-          }
-          launch_check("project (stacked)");
-        }
-        int64_t off = 0;
-        for (const auto& L : launches) {
-          if (L[0] > 0)
-            launch_project_tiled(mixed, (int)L[0], (int)L[1], L[2] != 0, d_tasks + off, L[3],
-                                 M.d_omega, st);
-          else
-            launch_project(mixed, d_tasks + off, L[3], M.d_omega, st);
-          launch_check("project");
-          off += L[3];
-        }
-        tp.stop();
-        tr_.mark("project", s, b, lv);
-        mem.release(d_tasks);
-        mem.release(d_pblk);
-        mem.release(d_ptile);
-      }
+      // row sweep: keep the own-block columns of R (the tail of each item's
+      // column set, contiguous in R^T) for the projection after both sweeps
+      if (s == 0) keep_own_columns(M, lo, hi, esz, st, mem);
       // no wait here: the next level's host work overlaps this level's
       // kernels, and the released blocks are reused only after a sync
       mem.release(d_units);
@@ -1269,7 +1110,6 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
   }
   mem.release(partial);
   ss.t_gram += tg.total();
-  ss.t_prj += tp.total();
   ss.t_gram_leaf += tgl.total();
 }
 
@@ -1343,6 +1183,258 @@ static void expand_side(MatrixData& M, int s, hipStream_t st, DevMem& mem) {
   const ClusterTree& tr = M.blk->tree->tr;
   for (int32_t lv = tr.depth; lv >= 0; --lv) expand_level(M, s, lv, st, mem);
   mem.sync(st, "expand sync");
+}
+
+// Projection of every admissible block after both sweeps:
+// S_b = omega_b R_tc|s W_sc from the kept own-block columns of the row
+// sweep's R and the expanded column basis, in one set of launches for all
+// levels.  Tiled kernel for ks <= 64 (one launch per (row tiles per pass,
+// column tiles)), the generic kernel above; in the mixed form the blocks of
+// ks <= 64 that share W_sc are stacked (k_project_stacked).
+static void project_all(MatrixData& M, hipStream_t st, DevMem& mem, SweepStats& ss) {
+  Trace tr_;
+  const ClusterTree& tr = M.blk->tree->tr;
+  Side& S = M.side[0];
+  const Side& C = M.side[1];
+  const bool mixed = M.precision == DH2_MIXED;
+  const size_t esz = mixed ? 2 * sizeof(float) : sizeof(double2);
+  constexpr int kGeneric = 32;
+  // The task lists are built by a few host threads over chunks of the plan
+  // (whole runs of one column item, so that stacking stays within a chunk),
+  // then joined in plan order.
+  struct PChunk {
+    size_t plan, q0, q1;
+    int64_t s_off;
+    std::vector<ProjDev> tasks;
+    std::vector<uint8_t> key;
+    std::vector<PBlkDev> pblk;
+    std::vector<PTileDev> ptile;
+    std::vector<uint8_t> tnc;
+    int64_t count[kGeneric + 1] = {0};
+    int64_t ncount[17] = {0};
+    double flops = 0.0;
+  };
+  const auto& plans = M.plan->proj;
+  int64_t nblk_all = 0;
+  for (const auto& pl : plans) nblk_all += (int64_t)pl.size();
+  const int nth = (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const int64_t target = std::max<int64_t>(2048, nblk_all / (4 * nth));
+  std::vector<PChunk> chunks;
+  int64_t sumS = 0;
+  for (size_t p = 0; p < plans.size(); ++p) {
+    const auto& pl = plans[p];
+    size_t q0 = 0;
+    int64_t s0 = sumS;
+    for (size_t q = 0; q < pl.size(); ++q) {
+      if (q > q0 && (int64_t)(q - q0) >= target && pl[q].witem != pl[q - 1].witem) {
+        chunks.emplace_back();
+        chunks.back().plan = p;
+        chunks.back().q0 = q0;
+        chunks.back().q1 = q;
+        chunks.back().s_off = s0;
+        q0 = q;
+        s0 = sumS;
+      }
+      sumS += (int64_t)S.items[pl[q].item].k * C.items[pl[q].witem].k;
+    }
+    if (q0 < pl.size()) {
+      chunks.emplace_back();
+      chunks.back().plan = p;
+      chunks.back().q0 = q0;
+      chunks.back().q1 = pl.size();
+      chunks.back().s_off = s0;
+    }
+  }
+  double2* Sarena = (double2*)mem.alloc(std::max<int64_t>(1, sumS) * sizeof(double2));
+  S.keep.push_back(Sarena);
+  auto build = [&](PChunk& ch) {
+    const auto& pl = plans[ch.plan];
+    int64_t o = ch.s_off;
+    ch.tasks.reserve(ch.q1 - ch.q0);
+    ch.key.reserve(ch.q1 - ch.q0);
+    for (size_t x = ch.q0; x < ch.q1; ++x) {
+      const ProjPlan& q = pl[x];
+      const ItemDev& it = S.items[q.item];
+      const int32_t ks = C.items[q.witem].k;
+      ProjDev pd{};
+      pd.R = (const char*)S.own[q.item] + (q.col - S.P->ninh[q.item]) * it.k * esz;
+      pd.W = mixed ? (const void*)C.wexp32[q.witem] : (const void*)C.wexp[q.witem];
+      pd.S = Sarena + o;
+      pd.kt = it.k;
+      pd.ks = ks;
+      pd.ns = q.ns;
+      pd.b = q.b;
+      M.S_ptr[q.b] = Sarena + o;
+      M.S_rows[q.b] = it.k;
+      M.S_cols[q.b] = ks;
+      o += (int64_t)it.k * ks;
+      ch.flops += 8.0 * it.k * (double)ks * (double)q.ns;
+      uint8_t kx = 255;
+      if (it.k > 0 && ks > 0 && !(mixed && ks <= 64)) {
+        int nj = (ks + 15) / 16, ni = (it.k + 15) / 16;
+        int c = kGeneric;
+        if (nj <= 4)
+          c = (q.ns >= 128 ? 16 : 0) + (std::min(ni, project_rows_per_pass(mixed, nj)) - 1) * 4 +
+              (nj - 1);
+        kx = (uint8_t)c;
+        ++ch.count[c];
+      }
+      ch.tasks.push_back(pd);
+      ch.key.push_back(kx);
+    }
+    if (!mixed) return;
+    // blocks of each run of equal column item (the plan of a level is
+    // sorted by it) stacked row-wise and cut into tiles of up to 64 rows;
+    // tile block indices are local to the chunk until the join
+    for (size_t g0 = ch.q0; g0 < ch.q1;) {
+      size_t g1 = g0;
+      while (g1 < ch.q1 && pl[g1].witem == pl[g0].witem) ++g1;
+      const int32_t ks = C.items[pl[g0].witem].k;
+      if (ks == 0 || ks > 64) {
+        g0 = g1;
+        continue;
+      }
+      const int32_t b0 = (int32_t)ch.pblk.size();
+      for (size_t x = g0; x < g1; ++x) {
+        const ProjDev& pd = ch.tasks[x - ch.q0];
+        if (pd.kt > 0) ch.pblk.push_back(PBlkDev{(const float2*)pd.R, pd.S, pd.kt, pd.b});
+      }
+      const int32_t b1 = (int32_t)ch.pblk.size();
+      int32_t bi = b0, i0 = 0;
+      while (bi < b1) {
+        PTileDev t;
+        t.W = C.wexp32[pl[g0].witem];
+        t.blk0 = bi;
+        t.i0 = i0;
+        t.ns = pl[g0].ns;
+        t.ks = ks;
+        int32_t rows = 0, nblk = 0;
+        while (rows < 64 && bi < b1) {
+          int32_t take = std::min(64 - rows, ch.pblk[bi].kt - i0);
+          rows += take;
+          i0 += take;
+          ++nblk;
+          if (i0 == ch.pblk[bi].kt) {
+            ++bi;
+            i0 = 0;
+          }
+        }
+        t.rows = rows;
+        t.nblk = nblk;
+        ch.ptile.push_back(t);
+        ch.tnc.push_back((uint8_t)((ks + 3) / 4));
+        ++ch.ncount[(ks + 3) / 4];
+      }
+      g0 = g1;
+    }
+  };
+  {
+    std::vector<std::thread> th;
+    std::atomic<size_t> next{0};
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&] {
+        for (size_t c; (c = next.fetch_add(1)) < chunks.size();) build(chunks[c]);
+      });
+    for (auto& t : th) t.join();
+  }
+  // join the chunks in plan order
+  int64_t count[kGeneric + 1] = {0};
+  int64_t ncount[17] = {0};
+  std::vector<ProjDev> tasks;
+  std::vector<uint8_t> key;
+  std::vector<PBlkDev> pblk;
+  std::vector<PTileDev> ptile;
+  std::vector<uint8_t> tnc;
+  {
+    size_t nt = 0, nb = 0, np = 0;
+    for (const auto& ch : chunks) {
+      nt += ch.tasks.size();
+      nb += ch.pblk.size();
+      np += ch.ptile.size();
+    }
+    tasks.reserve(nt);
+    key.reserve(nt);
+    pblk.reserve(nb);
+    ptile.reserve(np);
+    tnc.reserve(np);
+  }
+  for (auto& ch : chunks) {
+    const int32_t base = (int32_t)pblk.size();
+    tasks.insert(tasks.end(), ch.tasks.begin(), ch.tasks.end());
+    key.insert(key.end(), ch.key.begin(), ch.key.end());
+    pblk.insert(pblk.end(), ch.pblk.begin(), ch.pblk.end());
+    for (PTileDev t : ch.ptile) {
+      t.blk0 += base;
+      ptile.push_back(t);
+    }
+    tnc.insert(tnc.end(), ch.tnc.begin(), ch.tnc.end());
+    for (int c = 0; c <= kGeneric; ++c) count[c] += ch.count[c];
+    for (int c = 0; c <= 16; ++c) ncount[c] += ch.ncount[c];
+    ss.flops_prj += ch.flops;
+  }
+  // stable counting sorts: tasks by launch class, tiles by ceil(ks / 4)
+  std::vector<ProjDev> sorted;
+  std::vector<std::array<int64_t, 4>> launches;  // ni, nj, split, count
+  {
+    int64_t start[kGeneric + 1], run = 0;
+    for (int kx = 0; kx <= kGeneric; ++kx) {
+      start[kx] = run;
+      run += count[kx];
+      if (count[kx] == 0) continue;
+      if (kx < kGeneric)
+        launches.push_back({(kx % 16) / 4 + 1, kx % 4 + 1, kx / 16, count[kx]});
+      else
+        launches.push_back({0, 0, 0, count[kx]});
+    }
+    sorted.resize(run);
+    for (size_t x = 0; x < tasks.size(); ++x)
+      if (key[x] != 255) sorted[start[key[x]]++] = tasks[x];
+  }
+  {
+    std::vector<PTileDev> tsorted(ptile.size());
+    int64_t start[17], run = 0;
+    for (int c = 0; c <= 16; ++c) {
+      start[c] = run;
+      run += ncount[c];
+    }
+    for (size_t x = 0; x < ptile.size(); ++x) tsorted[start[tnc[x]]++] = ptile[x];
+    ptile.swap(tsorted);
+  }
+  tr_.mark("proj build", 0, -1, -1);
+  ProjDev* d_tasks = upload(mem, sorted, st);
+  PBlkDev* d_pblk = upload(mem, pblk, st);
+  PTileDev* d_ptile = upload(mem, ptile, st);
+  tr_.mark("proj upload", 0, -1, -1);
+  PhaseTimer tp(st);
+  tp.start();
+  {
+    int64_t toff = 0;
+    for (int c = 1; c <= 16; ++c) {
+      launch_project_stacked(c, d_ptile + toff, ncount[c], d_pblk, M.d_omega, st);
+      toff += ncount[c];
+    }
+    launch_check("project (stacked)");
+  }
+  int64_t off = 0;
+  for (const auto& L : launches) {
+    if (L[0] > 0)
+      launch_project_tiled(mixed, (int)L[0], (int)L[1], L[2] != 0, d_tasks + off, L[3], M.d_omega,
+                           st);
+    else
+      launch_project(mixed, d_tasks + off, L[3], M.d_omega, st);
+    launch_check("project");
+    off += L[3];
+  }
+  tp.stop();
+  tr_.mark("proj launch", 0, -1, -1);
+  ss.t_prj += tp.total();
+  tr_.mark("proj done", 0, -1, -1);
+  mem.release(d_tasks);
+  mem.release(d_pblk);
+  mem.release(d_ptile);
+  for (void* q : S.own_keep) mem.release(q);
+  S.own_keep.clear();
+  std::fill(S.own.begin(), S.own.end(), nullptr);
 }
 
 std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, const void* G,
@@ -1454,13 +1546,16 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   }
   double budget = 0.75 * (double)freeb;
   if (o.max_device_bytes > 0) budget = std::min(budget, 0.75 * (double)o.max_device_bytes);
-  int32_t nb = o.groups > 0 ? o.groups : (int32_t)std::ceil(peak / std::max(1.0, budget));
+  // The row and column sweeps are independent (the projection follows both),
+  // so they run at the same time, each on its own stream, unless a memory
+  // cap is set (then one after the other, so that the cap stays exact).
+  // Running together they hold the R matrices of both sides: the batch
+  // count leaves room for that.
+  M.concurrent = o.max_device_bytes == 0;
+  const double need = M.concurrent ? 2.0 * peak : peak;
+  int32_t nb = o.groups > 0 ? o.groups : (int32_t)std::ceil(need / std::max(1.0, budget));
   nb = std::max(1, std::min(nb, std::max(1, ngroups)));
   M.nbatch = nb;
-  // the row and column sweeps run at the same time, each on its own stream,
-  // when the sweep is one batch and the R matrices of both sides fit (with
-  // a memory cap they run one after the other so that the cap stays exact)
-  M.concurrent = nb == 1 && o.max_device_bytes == 0 && 2.0 * peak <= budget;
   std::vector<int32_t> batch_of(tr.nc(), 0);
   {
     double tot = std::accumulate(grpN.begin(), grpN.end(), 0.0), cum = 0;
@@ -1481,6 +1576,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     S.nitems = S.P->nitems;
     S.items = S.P->items0;
     S.wexp.assign(S.nitems, nullptr);
+    S.own.assign(S.nitems, nullptr);
   }
   trc.mark("plan", -1, -1, -1);
   M.S_ptr.assign(nadm, nullptr);
@@ -1545,7 +1641,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   SweepStats ss_col, ss_row;
   float ms_col = 0, ms_row = 0, ms_sweeps = 0;
   if (!M.concurrent) {
-    // column basis (expanded), then the row basis with the projection
+    // column basis (expanded), then the row basis
     hip_check(hipEventRecord(e0, st), "event");
     sweep(M, 1, g, st, ss_col, d_status + 4, mem);
     expand_side(M, 1, st, mem);
@@ -1559,23 +1655,17 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     hip_check(hipEventElapsedTime(&ms_row, e0, e1), "event");
     ms_sweeps = ms_col + ms_row;
   } else {
-    // both sweeps at once: the column sweep on a second stream (default
-    // priority) driven by a second host thread with its own device-memory
-    // owner; the row sweep projects each level once the column sweep has
-    // expanded it.  Kernels of the two sweeps fill each other's idle time
-    // (small factorisations, rank read-backs, launch tails).
+    // both sweeps at once: the column sweep (and the expansion of its basis)
+    // on a second stream (default priority), driven by a second host thread
+    // with its own device-memory owner.  Kernels of the two sweeps fill each
+    // other's idle time (small factorisations, rank read-backs, launch tails).
     int dev = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
-    LevelSync ls;
-    ls.ready.assign(tr.depth + 1, 0);
-    ls.ev.assign(tr.depth + 1, nullptr);
-    for (auto& e : ls.ev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
     hipStream_t sc = nullptr;
     hip_check(hipStreamCreateWithFlags(&sc, hipStreamNonBlocking), "stream create");
-    hipEvent_t c0 = nullptr, c1 = nullptr, r1 = nullptr;
     struct Cleanup {
-      hipStream_t s;
-      hipEvent_t e[3];
+      hipStream_t s = nullptr;
+      hipEvent_t e[3] = {nullptr, nullptr, nullptr};
       ~Cleanup() {
         if (s) {
           (void)hipStreamSynchronize(s);
@@ -1584,13 +1674,10 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
         for (hipEvent_t x : e)
           if (x) (void)hipEventDestroy(x);
       }
-    } cleanup{sc, {nullptr, nullptr, nullptr}};
-    hip_check(hipEventCreate(&c0), "event");
-    cleanup.e[0] = c0;
-    hip_check(hipEventCreate(&c1), "event");
-    cleanup.e[1] = c1;
-    hip_check(hipEventCreate(&r1), "event");
-    cleanup.e[2] = r1;
+    } cleanup;
+    cleanup.s = sc;
+    for (auto& x : cleanup.e) hip_check(hipEventCreate(&x), "event");
+    hipEvent_t c0 = cleanup.e[0], c1 = cleanup.e[1], r1 = cleanup.e[2];
     hip_check(hipEventRecord(e0, st), "event");
     hip_check(hipStreamWaitEvent(sc, e0, 0), "stream wait");
     hip_check(hipEventRecord(c0, sc), "event");
@@ -1600,7 +1687,8 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
       try {
         hip_check(hipSetDevice(dev), "hipSetDevice");
         M.mem_col->begin_staging();
-        sweep(M, 1, g, sc, ss_col, d_status + 4, *M.mem_col, &ls);
+        sweep(M, 1, g, sc, ss_col, d_status + 4, *M.mem_col);
+        expand_side(M, 1, sc, *M.mem_col);
         hip_check(hipEventRecord(c1, sc), "event");
         M.mem_col->end_staging(sc);
       } catch (const Error& e) {
@@ -1610,10 +1698,9 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
       } catch (const std::exception& e) {
         cerr = Error{DH2_EDEVICE, e.what()};
       }
-      if (cerr.code != DH2_OK) ls.fail_all();
     });
     try {
-      sweep(M, 0, g, st, ss_row, d_status, mem, &ls);
+      sweep(M, 0, g, st, ss_row, d_status, mem);
     } catch (...) {
       th.join();
       throw;
@@ -1628,6 +1715,9 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     hip_check(hipEventElapsedTime(&ms_col, c0, c1), "event");
     hip_check(hipEventElapsedTime(&ms_row, e0, r1), "event");
   }
+  // projection of every admissible block (needs both bases)
+  project_all(M, st, mem, ss_row);
+  ms_sweeps += (float)(ss_row.t_prj * 1e3);
 
   // near field
   hip_check(hipEventRecord(e0, st), "event");
@@ -1701,7 +1791,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   S.mem_per_n_kib = S.mem_bytes / 1024.0 / (double)n;
   S.t_col = ms_col * 1e-3;
   S.t_prj = ss_row.t_prj;
-  S.t_row = ms_row * 1e-3 - ss_row.t_prj;
+  S.t_row = ms_row * 1e-3;
   S.t_near = ms_near * 1e-3;
   S.t_total = (ms_w + ms_sweeps + ms_near) * 1e-3;
   S.flops_row = ss_row.flops_gram + ss_row.flops_rprod;

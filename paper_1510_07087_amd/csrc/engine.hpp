@@ -127,6 +127,9 @@ struct Side {
   // expanded basis (column side): per internal item pointer, rows x k row-major
   std::vector<double2*> wexp;
   std::vector<float2*> wexp32;      // mixed form: FP32 copies for the projection
+  // row sweep: own-block columns of each item's R^T kept for the projection
+  std::vector<void*> own;
+  std::vector<void*> own_keep;      // their arenas, released after the projection
 };
 
 struct MatvecPlan;

@@ -2638,6 +2638,18 @@ void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st) {
   hipLaunchKernelGGL(k_expand, dim3((unsigned)ntasks), dim3(256), 0, st, tasks);
 }
 
+__global__ __launch_bounds__(256) void k_copy_bytes(const CopyDev* tasks) {
+  const CopyDev t = tasks[blockIdx.x];
+  const uint64_t* s = reinterpret_cast<const uint64_t*>(t.src);
+  uint64_t* d = reinterpret_cast<uint64_t*>(t.dst);
+  for (int64_t e = threadIdx.x; e < t.bytes / 8; e += 256) d[e] = s[e];
+}
+
+void launch_copy_bytes(const CopyDev* tasks, int64_t ntasks, hipStream_t st) {
+  if (ntasks == 0) return;
+  hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)ntasks), dim3(256), 0, st, tasks);
+}
+
 void launch_cvt(const CvtDev* tasks, int64_t ntasks, hipStream_t st) {
   if (ntasks == 0) return;
   hipLaunchKernelGGL(k_cvt, dim3((unsigned)ntasks), dim3(256), 0, st, tasks);

@@ -61,6 +61,8 @@ void launch_rprod_inner_big(bool mixed, const ItemDev* items, const UnitDev* uni
                             hipStream_t st);
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_cvt(const CvtDev* tasks, int64_t ntasks, hipStream_t st);
+// one workgroup per task, 8-byte words
+void launch_copy_bytes(const CopyDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
                    int64_t count, hipStream_t st);
 void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const double* omega,
