@@ -325,7 +325,9 @@ def main():
     ap.add_argument("--workload", default="sphere131072")
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--groups", type=int, default=0)
-    ap.add_argument("--err-iters", type=int, default=8)
+    ap.add_argument("--err-iters", type=int, default=50,
+                    help="power iterations of the error estimate (it also stops once the "
+                         "Rayleigh quotient changes by less than 1e-4)")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", type=float, default=None,

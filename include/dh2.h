@@ -261,11 +261,13 @@ dh2_status dh2_matvec(dh2_matrix m, char op, int64_t nrhs, const void* x,
  * device memory: code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  Same arguments, layout and result as dh2_matvec;
  * it calls no hipMalloc, hipFree or allocating routine.
- *   - Its work vectors (permuted x and y, n complex each, and the basis
- *     coefficients of the larger side, twice) live in a static device array
- *     of 64 MiB that the library holds on every device it runs on until the
- *     process ends.  A matrix whose work vectors exceed it is refused with
- *     DH2_EUNSUPPORTED (about n = 10^6 points at the benchmark's ranks).
+ *   - Its work vectors (permuted x and y, n complex each, the basis
+ *     coefficients of the larger side, twice, and 64 complex partial sums
+ *     per extra task of leaves whose near field is split over several tasks)
+ *     live in a static device array of 64 MiB that the library holds on
+ *     every device it runs on until the process ends.  A matrix whose work
+ *     vectors exceed it is refused with DH2_EUNSUPPORTED (about n = 10^6
+ *     points at the benchmark's ranks).
  *   - The product's index lists are built by the first dh2_matvec on the
  *     matrix; before that this call returns DH2_EINVAL.
  *   - The work is only enqueued on `stream` (no wait); y is complete when the

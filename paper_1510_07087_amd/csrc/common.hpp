@@ -33,7 +33,11 @@ struct ItemDev {
   int64_t ent_begin; // leaf: first column-set entry
   int64_t ent_end;
   int64_t col_off;   // non-leaf: offset of F_tc inside the sons' sets
-  void* R;           // R^T (N x k, complex FP64 or FP32), in the arena of its level
+  int64_t ninh;      // columns of F_tc inherited from the father (the first ninh)
+  void* R;           // R^T of the inherited columns (ninh x k, complex FP64 or FP32),
+                     // in the arena of its level
+  void* Rown;        // row basis: R^T of the own-block columns ((N - ninh) x k), kept
+                     // for the projection; null in the column basis (not formed)
   double2* M;        // Gram (r x r, column-major)
   double2* Q;        // factor: r x k row-major (leaf: Q_tc, other: [E_t1c; E_t2c])
   double* sig;       // singular values (r)
@@ -105,13 +109,6 @@ struct CvtDev {
   int64_t count;
 };
 
-// Copy task: bytes (a multiple of 8) from src to dst, both 8-byte aligned.
-struct CopyDev {
-  const void* src;
-  void* dst;
-  int64_t bytes;
-};
-
 // Expansion task: rows of one son inside Wexp_sc = Wexp_{s_i c'} E_{s_i c}.
 struct ExpandDev {
   const double2* src; // Wexp of the son (rows x ks) row-major
@@ -123,14 +120,19 @@ struct ExpandDev {
   int32_t pad;
 };
 
-// Leaf cluster of the matrix-vector product: its rows, its items in the basis
-// being applied, and its references into the near field.
+// Task of the matrix-vector product's last step: rows of one leaf cluster,
+// its items in the basis being applied (first task of the leaf only), and a
+// range of its references into the near field.  slot < 0: the task holds all
+// of the leaf's work and writes its rows; otherwise it writes partial sums
+// into slot `slot` of the partial buffer (64 rows x nr), added per leaf in
+// slot order afterwards.  For that reduction item_first / item_count give
+// the leaf's first slot and slot count.
 struct LeafDev {
   int64_t row_off;
   int32_t len;
   int32_t item_first;
   int32_t item_count;
-  int32_t pad;
+  int32_t slot;
   int64_t near_begin;
   int64_t near_end;
 };

@@ -86,6 +86,9 @@ struct CachedBlock {
 std::mutex g_cache_mu;
 std::vector<CachedBlock> g_cache;
 size_t g_cached = 0;
+// serialises the check of the driver's free memory with the allocation that
+// follows it, so that two sweeps allocating at once cannot both pass it
+std::mutex g_alloc_mu;
 
 size_t size_class(size_t b) {
   if (b < 4096) return (b + 255) & ~size_t(255);
@@ -244,26 +247,36 @@ void* DevMem::alloc(size_t bytes) {
   if (!p) {
     // keep cached blocks from pushing the device past its memory: the driver
     // would evict allocations to host memory instead of failing
+    const size_t margin = size_t(2) << 30;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      fr = ~size_t(0) >> 1;
+    }
+    if (fr < bytes + margin && !released_.empty()) {
+      hip_check(hipDeviceSynchronize(), "release sync");
+      pin_off_ = 0;
+      flush_released();
+    }
+    hipError_t e;
     {
-      size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-        const size_t margin = size_t(2) << 30;
-        if (fr < bytes + margin && !released_.empty()) {
-          hip_check(hipDeviceSynchronize(), "release sync");
-          pin_off_ = 0;
-          flush_released();
-        }
+      // the free-memory check and the allocation that relies on it, under
+      // one lock, so that two sweeps allocating at once cannot both pass it
+      std::lock_guard<std::mutex> alk(g_alloc_mu);
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        fr = ~size_t(0) >> 1;
+      }
+      {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         while (fr < bytes + margin && !g_cache.empty()) {
           size_t big = g_cache_largest_locked();
           trim_cache_locked(g_cached - std::min(g_cached, big));
           fr += big;
         }
-      } else {
-        (void)hipGetLastError();
       }
+      e = hipMalloc(&p, bytes);
     }
-    hipError_t e = hipMalloc(&p, bytes);
     while (e != hipSuccess) {
       (void)hipGetLastError();
       // blocks released since the last sync: wait for the device, then they
@@ -373,6 +386,8 @@ struct SideMV {
   int64_t* d_cbegin = nullptr;
   int32_t* d_cblock = nullptr;
   int32_t* d_cpartner = nullptr;
+  int32_t* d_corder = nullptr;  // items by descending coupling work (launch order)
+  int32_t nheavy = 0;           // the first nheavy of them: one workgroup each
   // backward: per level, items with fathers
   std::vector<int32_t*> d_bl_items;
   std::vector<int32_t> bl_count;
@@ -384,10 +399,14 @@ struct SideMV {
   int32_t n_fwd_leaf = 0;
   std::vector<int32_t*> d_fwd_lvl;
   std::vector<int32_t> fwd_count;
-  // leaves
+  // tasks of the last step (leaves, or parts of a leaf's near field)
   LeafDev* d_leaves = nullptr;
   NearRefDev* d_nref = nullptr;
   int32_t nleaves = 0;
+  // leaves whose work is split over several tasks, and the partial slots
+  LeafDev* d_split = nullptr;
+  int32_t nsplit = 0;
+  int32_t nslots = 0;
 };
 
 struct MatvecPlan {
@@ -396,11 +415,15 @@ struct MatvecPlan {
   double2* const* d_Sptr = nullptr;
   int32_t* d_Srows = nullptr;
   int32_t* d_Scols = nullptr;
+  double2* const* d_STptr = nullptr;  // transposed copies S_b^T for the adjoint
   double2* xp = nullptr;
   double2* yp = nullptr;
   double2* xh = nullptr;  // sized for the larger side
   double2* yh = nullptr;
+  double2* part = nullptr;  // partial sums of split leaves (64 rows x kMvRhs per slot)
   int64_t maxh = 0;       // coefficients of the larger side
+  int32_t maxslots = 0;   // partial slots of the larger side
+  double2* d_nearT = nullptr;  // near-field blocks transposed (#s x #t column-major)
 };
 
 // right-hand sides per pass of the matrix-vector product kernels
@@ -410,7 +433,7 @@ constexpr int kMvRhs = 8;
 // source and destination bases (maxh each), times the right-hand sides of
 // the pass (interleaved)
 struct MatvecBufs {
-  double2 *xp, *yp, *xh, *yh;
+  double2 *xp, *yp, *xh, *yh, *part;
 };
 
 MatrixData::~MatrixData() {
@@ -498,6 +521,8 @@ static std::shared_ptr<SidePlan> build_side_plan(const BlocksData& B, int s, int
     S.t[i] = t;
     S.c[i] = c;
     S.ninh[i] = Ninh[e];
+    it.ninh = Ninh[e];
+    it.Rown = nullptr;
     it.row_off = tr.off[t];
     it.N = Next[e];
     it.m = (int32_t)tr.size[t];
@@ -661,40 +686,14 @@ struct SweepStats {
   double t_gram = 0, t_prj = 0;
   double flops_gram_leaf = 0, t_gram_leaf = 0, flops_rprod_leaf = 0, ops_gram_leaf_i8 = 0;
   int32_t n_gram_leaf = 0;
+  int64_t n_fac[5] = {0, 0, 0, 0, 0};  // factorisations by size class (last: X in memory)
+  int64_t n_redo = 0;                  // factored again (wide LDS pass)
+  int64_t n_redo_mem = 0;              // factored a third time with X in memory
 };
 
 static int64_t npairs_of(int r) {
   int nt = (r + 15) / 16;
   return (int64_t)nt * (nt + 1) / 2;
-}
-
-// The own-block columns of the row sweep's R for items [lo, hi) (the tail
-// [ninh, N) of each column set, one contiguous piece of R^T) copied into an
-// arena kept until the projection; S.own[i] points at item i's piece.
-static void keep_own_columns(MatrixData& M, int32_t lo, int32_t hi, size_t esz, hipStream_t st,
-                             DevMem& mem) {
-  Side& S = M.side[0];
-  int64_t total = 0;
-  for (int32_t i = lo; i < hi; ++i)
-    total += (S.items[i].N - S.P->ninh[i]) * (int64_t)S.items[i].k;
-  if (total == 0) return;
-  char* arena = (char*)mem.alloc((size_t)total * esz);
-  S.own_keep.push_back(arena);
-  std::vector<CopyDev> tasks;
-  int64_t o = 0;
-  for (int32_t i = lo; i < hi; ++i) {
-    const ItemDev& it = S.items[i];
-    const int64_t cnt = (it.N - S.P->ninh[i]) * (int64_t)it.k;
-    S.own[i] = arena + o * esz;
-    if (cnt > 0)
-      tasks.push_back(CopyDev{(const char*)it.R + S.P->ninh[i] * it.k * esz, arena + o * esz,
-                              (int64_t)(cnt * esz)});
-    o += cnt;
-  }
-  CopyDev* d_tasks = upload(mem, tasks, st);
-  launch_copy_bytes(d_tasks, (int64_t)tasks.size(), st);
-  launch_check("own columns");
-  mem.release(d_tasks);
 }
 
 static void expand_level(MatrixData& M, int s, int32_t lv, hipStream_t st, DevMem& mem);
@@ -894,6 +893,8 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           }
         std::vector<int32_t> all;
         for (int c = 0; c < kFacClasses; ++c) all.insert(all.end(), fl[c].begin(), fl[c].end());
+        for (int c = 0; c < kFacClasses; ++c) ss.n_fac[c] += (int64_t)fl[c].size();
+        ss.n_fac[kFacClasses] += (int64_t)big.size();
         int32_t* d_fl = upload(mem, all, st);
         int64_t off = 0;
         for (int c = 0; c < kFacClasses; ++c) {
@@ -932,7 +933,26 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
         std::vector<int32_t> redo;
         for (int32_t i = 0; i < n; ++i)
           if (hk[i] < 0) redo.push_back(lo + i);
+        ss.n_redo += (int64_t)redo.size();
         if (!redo.empty()) {
+          // again in LDS with room for every column (one workgroup per CU)
+          int32_t rmx = 0;
+          for (int32_t i : redo) rmx = std::max(rmx, S.items[i].r);
+          int32_t* d_redo = upload(mem, redo, st);
+          launch_factor(S.d_items, d_redo, (int32_t)redo.size(), rmx, M.eps, M.max_sweeps,
+                        d_status, st, true);
+          launch_check("factor (wide)");
+          launch_ranks(S.d_items + lo, n, d_k, st);
+          launch_check("ranks");
+          copy_from(hk.data(), d_k, n, st);
+          mem.release(d_redo);
+          redo.clear();
+          for (int32_t i = 0; i < n; ++i)
+            if (hk[i] < 0) redo.push_back(lo + i);
+          ss.n_redo_mem += (int64_t)redo.size();
+        }
+        if (!redo.empty()) {
+          // the rest (more columns than the LDS holds) with X in memory
           int64_t tot = 0;
           for (int32_t i : redo) tot += (int64_t)S.items[i].r * (S.items[i].r + 1);
           double2* xw2 = (double2*)mem.alloc((size_t)tot * sizeof(double2));
@@ -969,9 +989,14 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       tr_.mark("factor", s, b, lv);
       mem.release(Marena);
       for (int32_t i = lo; i < hi; ++i) S.items[i].M = nullptr;
-      // coefficient matrices R of this level
-      int64_t sumNk = 0;
-      for (int32_t i = lo; i < hi; ++i) sumNk += S.items[i].N * S.items[i].k;
+      // coefficient matrices R of this level: the inherited columns (read by
+      // the fathers) in the level's arena; in the row sweep the own-block
+      // columns go straight into an arena kept for the projection
+      int64_t sumNk = 0, sumOwn = 0;
+      for (int32_t i = lo; i < hi; ++i) {
+        sumNk += S.P->ninh[i] * S.items[i].k;
+        if (s == 0) sumOwn += (S.items[i].N - S.P->ninh[i]) * S.items[i].k;
+      }
       // R^T in complex FP64, or complex FP32 in the mixed form followed by the
       // row maxima of every R (k floats per item, for the parents' int8 Gram)
       size_t esz = mixed ? 2 * sizeof(float) : sizeof(double2);
@@ -980,13 +1005,22 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       size_t rbytes = ((size_t)sumNk * esz + 255) / 256 * 256;
       size_t mbytes = mixed ? (size_t)sumk * sizeof(float) : 0;
       char* Rarena = (char*)mem.alloc(rbytes + mbytes);
+      char* Oarena = sumOwn > 0 ? (char*)mem.alloc((size_t)sumOwn * esz) : nullptr;
+      if (Oarena) S.own_keep.push_back(Oarena);
       {
-        int64_t o = 0, ok = 0;
+        int64_t o = 0, ok = 0, oo = 0;
         for (int32_t i = lo; i < hi; ++i) {
-          S.items[i].R = Rarena + o * esz;
-          S.items[i].rmax = mixed ? (float*)(Rarena + rbytes) + ok : nullptr;
-          o += S.items[i].N * S.items[i].k;
-          ok += S.items[i].k;
+          ItemDev& it = S.items[i];
+          it.R = Rarena + o * esz;
+          it.rmax = mixed ? (float*)(Rarena + rbytes) + ok : nullptr;
+          it.Rown = nullptr;
+          if (s == 0) {
+            it.Rown = Oarena ? Oarena + oo * esz : nullptr;
+            S.own[i] = it.Rown;
+            oo += (it.N - S.P->ninh[i]) * it.k;
+          }
+          o += S.P->ninh[i] * it.k;
+          ok += it.k;
         }
       }
       if (mbytes) hip_check(hipMemsetAsync(Rarena + rbytes, 0, mbytes, st), "row maxima clear");
@@ -1089,9 +1123,6 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       launch_check("rprod (non-leaf)");
       if (trace_on()) hip_check(hipStreamSynchronize(st), "trace sync");
       tr_.mark("rprod", s, b, lv);
-      // row sweep: keep the own-block columns of R (the tail of each item's
-      // column set, contiguous in R^T) for the projection after both sweeps
-      if (s == 0) keep_own_columns(M, lo, hi, esz, st, mem);
       // no wait here: the next level's host work overlaps this level's
       // kernels, and the released blocks are reused only after a sync
       mem.release(d_units);
@@ -1104,9 +1135,25 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       mem.release(R_prev);
       R_prev = Rarena;
       tr_.mark("level end", s, b, lv);
+      if (trace_on()) {
+        size_t fr = 0, tot = 0;
+        (void)hipMemGetInfo(&fr, &tot);
+        size_t cached = 0;
+        {
+          std::lock_guard<std::mutex> lk(g_cache_mu);
+          cached = g_cached;
+        }
+        std::fprintf(stderr,
+                     "[dh2 mem] side %d batch %d level %d: owner %.1f GB (peak %.1f), cache %.1f "
+                     "GB, driver free %.1f GB\n",
+                     s, b, lv, mem.used() * 1e-9, mem.peak() * 1e-9, cached * 1e-9, fr * 1e-9);
+      }
     }
     mem.release(R_prev);
-    for (int32_t i = 0; i < S.nitems; ++i) S.items[i].R = nullptr;
+    for (int32_t i = 0; i < S.nitems; ++i) {
+      S.items[i].R = nullptr;
+      S.items[i].Rown = nullptr;
+    }
   }
   mem.release(partial);
   ss.t_gram += tg.total();
@@ -1337,68 +1384,72 @@ static void project_all(MatrixData& M, hipStream_t st, DevMem& mem, SweepStats& 
       });
     for (auto& t : th) t.join();
   }
-  // join the chunks in plan order
+  // final positions: tasks sorted (stably) by launch class, tiles by
+  // ceil(ks / 4), blocks of the stacked tiles in plan order; each chunk
+  // scatters its own lists into place in parallel
+  const size_t nch = chunks.size();
   int64_t count[kGeneric + 1] = {0};
   int64_t ncount[17] = {0};
-  std::vector<ProjDev> tasks;
-  std::vector<uint8_t> key;
-  std::vector<PBlkDev> pblk;
-  std::vector<PTileDev> ptile;
-  std::vector<uint8_t> tnc;
-  {
-    size_t nt = 0, nb = 0, np = 0;
-    for (const auto& ch : chunks) {
-      nt += ch.tasks.size();
-      nb += ch.pblk.size();
-      np += ch.ptile.size();
-    }
-    tasks.reserve(nt);
-    key.reserve(nt);
-    pblk.reserve(nb);
-    ptile.reserve(np);
-    tnc.reserve(np);
+  std::vector<int64_t> pbase(nch + 1, 0);
+  for (size_t c = 0; c < nch; ++c) {
+    for (int k = 0; k <= kGeneric; ++k) count[k] += chunks[c].count[k];
+    for (int k = 0; k <= 16; ++k) ncount[k] += chunks[c].ncount[k];
+    pbase[c + 1] = pbase[c] + (int64_t)chunks[c].pblk.size();
+    ss.flops_prj += chunks[c].flops;
   }
-  for (auto& ch : chunks) {
-    const int32_t base = (int32_t)pblk.size();
-    tasks.insert(tasks.end(), ch.tasks.begin(), ch.tasks.end());
-    key.insert(key.end(), ch.key.begin(), ch.key.end());
-    pblk.insert(pblk.end(), ch.pblk.begin(), ch.pblk.end());
-    for (PTileDev t : ch.ptile) {
-      t.blk0 += base;
-      ptile.push_back(t);
-    }
-    tnc.insert(tnc.end(), ch.tnc.begin(), ch.tnc.end());
-    for (int c = 0; c <= kGeneric; ++c) count[c] += ch.count[c];
-    for (int c = 0; c <= 16; ++c) ncount[c] += ch.ncount[c];
-    ss.flops_prj += ch.flops;
-  }
-  // stable counting sorts: tasks by launch class, tiles by ceil(ks / 4)
-  std::vector<ProjDev> sorted;
   std::vector<std::array<int64_t, 4>> launches;  // ni, nj, split, count
+  std::vector<std::array<int64_t, kGeneric + 1>> toff(nch);
+  std::vector<std::array<int64_t, 17>> noff(nch);
+  int64_t ntask = 0, ntile = 0;
   {
-    int64_t start[kGeneric + 1], run = 0;
+    int64_t start[kGeneric + 1];
     for (int kx = 0; kx <= kGeneric; ++kx) {
-      start[kx] = run;
-      run += count[kx];
+      start[kx] = ntask;
+      ntask += count[kx];
       if (count[kx] == 0) continue;
       if (kx < kGeneric)
         launches.push_back({(kx % 16) / 4 + 1, kx % 4 + 1, kx / 16, count[kx]});
       else
         launches.push_back({0, 0, 0, count[kx]});
     }
-    sorted.resize(run);
-    for (size_t x = 0; x < tasks.size(); ++x)
-      if (key[x] != 255) sorted[start[key[x]]++] = tasks[x];
-  }
-  {
-    std::vector<PTileDev> tsorted(ptile.size());
-    int64_t start[17], run = 0;
-    for (int c = 0; c <= 16; ++c) {
-      start[c] = run;
-      run += ncount[c];
+    int64_t nstart[17];
+    for (int k = 0; k <= 16; ++k) {
+      nstart[k] = ntile;
+      ntile += ncount[k];
     }
-    for (size_t x = 0; x < ptile.size(); ++x) tsorted[start[tnc[x]]++] = ptile[x];
-    ptile.swap(tsorted);
+    for (size_t c = 0; c < nch; ++c) {
+      for (int k = 0; k <= kGeneric; ++k) {
+        toff[c][k] = start[k];
+        start[k] += chunks[c].count[k];
+      }
+      for (int k = 0; k <= 16; ++k) {
+        noff[c][k] = nstart[k];
+        nstart[k] += chunks[c].ncount[k];
+      }
+    }
+  }
+  std::vector<ProjDev> sorted(ntask);
+  std::vector<PBlkDev> pblk(pbase[nch]);
+  std::vector<PTileDev> ptile(ntile);
+  {
+    auto scatter = [&](size_t c) {
+      PChunk& ch = chunks[c];
+      for (size_t x = 0; x < ch.tasks.size(); ++x)
+        if (ch.key[x] != 255) sorted[toff[c][ch.key[x]]++] = ch.tasks[x];
+      std::copy(ch.pblk.begin(), ch.pblk.end(), pblk.begin() + pbase[c]);
+      for (size_t x = 0; x < ch.ptile.size(); ++x) {
+        PTileDev t = ch.ptile[x];
+        t.blk0 += (int32_t)pbase[c];
+        ptile[noff[c][ch.tnc[x]]++] = t;
+      }
+    };
+    std::vector<std::thread> th;
+    std::atomic<size_t> next{0};
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&] {
+        for (size_t c; (c = next.fetch_add(1)) < nch;) scatter(c);
+      });
+    for (auto& t : th) t.join();
   }
   tr_.mark("proj build", 0, -1, -1);
   ProjDev* d_tasks = upload(mem, sorted, st);
@@ -1437,6 +1488,31 @@ static void project_all(MatrixData& M, hipStream_t st, DevMem& mem, SweepStats& 
   std::fill(S.own.begin(), S.own.end(), nullptr);
 }
 
+static std::shared_ptr<const SweepSizes> sweep_sizes(const BlocksData& B) {
+  const ClusterTree& tr = B.tree->tr;
+  auto Z = std::make_shared<SweepSizes>();
+  Z->lmin = B.bt.adm_t.empty() ? 0 : first_adm_level(B);
+  const int32_t lg = std::max(0, Z->lmin - 1);
+  Z->group.assign(tr.nc(), -1);
+  for (int32_t t = 0; t < tr.nc(); ++t) {
+    if (tr.level[t] == lg) Z->group[t] = Z->ngroups++;
+    else if (tr.level[t] > lg) Z->group[t] = Z->group[tr.father[t]];
+  }
+  Z->lvlN.assign(tr.depth + 2, 0.0);
+  Z->grpN.assign(std::max(1, Z->ngroups), 0.0);
+  for (int s = 0; s < 2; ++s) {
+    const ColumnSets& cs = B.cs[s];
+    for (int32_t e = 0; e < cs.nitems(); ++e) {
+      int32_t t = cs.item_t[e];
+      double N = 0;
+      for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) N += (double)tr.size[cs.ent[q].s];
+      Z->lvlN[tr.level[t]] += N * 0.5;
+      if (Z->group[t] >= 0) Z->grpN[Z->group[t]] += N;
+    }
+  }
+  return Z;
+}
+
 std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, const void* G,
                                      int64_t ld, const double* w, double eps, const dh2_opts& o,
                                      hipStream_t st, const double* nrm) {
@@ -1454,6 +1530,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   int64_t n = tr.n;
   int64_t nadm = (int64_t)bt.adm_t.size();
   DevMem& mem = *M.mem;
+  Trace trc;
   // uploads of the compression go through pinned staging, without waits
   mem.begin_staging();
 
@@ -1508,28 +1585,21 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   g.n = n;
   g.kappa = blk->tree->kappa;
 
+  trc.mark("geometry", -1, -1, -1);
   // batches: subtrees rooted one level above the first admissible level
-  M.lmin = nadm ? first_adm_level(*blk) : 0;
-  int32_t lg = std::max(0, M.lmin - 1);
-  std::vector<int32_t> group(tr.nc(), -1);
-  int32_t ngroups = 0;
-  for (int32_t t = 0; t < tr.nc(); ++t) {
-    if (tr.level[t] == lg) group[t] = ngroups++;
-    else if (tr.level[t] > lg) group[t] = group[tr.father[t]];
+  std::shared_ptr<const SweepSizes> SZ;
+  {
+    std::lock_guard<std::mutex> lk(blk->cache_mu);
+    if (!blk->sizes) blk->sizes = sweep_sizes(*blk);
+    SZ = blk->sizes;
   }
+  M.lmin = SZ->lmin;
+  const int32_t ngroups = SZ->ngroups;
+  const std::vector<int32_t>& group = SZ->group;
+  const std::vector<double>& lvlN = SZ->lvlN;
+  const std::vector<double>& grpN = SZ->grpN;
   // estimated R memory per level (rank estimate, 16 bytes per coefficient in
   // the FP64 form, 8 in the mixed form)
-  std::vector<double> lvlN(tr.depth + 2, 0.0), grpN(std::max(1, ngroups), 0.0);
-  for (int s = 0; s < 2; ++s) {
-    const ColumnSets& cs = blk->cs[s];
-    for (int32_t e = 0; e < cs.nitems(); ++e) {
-      int32_t t = cs.item_t[e];
-      double N = 0;
-      for (int64_t q = cs.begin[e]; q < cs.begin[e + 1]; ++q) N += (double)tr.size[cs.ent[q].s];
-      lvlN[tr.level[t]] += N * 0.5;
-      if (group[t] >= 0) grpN[group[t]] += N;
-    }
-  }
   // rank estimate: about 48 (at most the leaf size) with the directional
   // admissibility; the standard condition alone admits blocks whose ranks
   // grow with kappa (several times larger in the paper's comparison), so
@@ -1567,8 +1637,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     for (int32_t t = 0; t < tr.nc(); ++t) batch_of[t] = group[t] >= 0 ? gb[group[t]] : 0;
   }
 
-  Trace trc;
-  trc.mark("setup", -1, -1, -1);
+  trc.mark("batches", -1, -1, -1);
   M.plan = plan_cache(*blk, nb, batch_of);
   for (int s = 0; s < 2; ++s) {
     Side& S = M.side[s];
@@ -1764,6 +1833,16 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
                  stat[2] + stat[6],
                  stat[2] + stat[6] ? (double)(stat[1] + stat[5]) / (stat[2] + stat[6]) : 0.0,
                  M.concurrent ? "concurrent" : "sequential");
+    std::fprintf(stderr,
+                 "[dh2 trace] factor classes r<=32 %lld, <=48 %lld, <=64 %lld, <=128 %lld, "
+                 "in memory %lld; factored again %lld, in memory %lld\n",
+                 (long long)(ss_row.n_fac[0] + ss_col.n_fac[0]),
+                 (long long)(ss_row.n_fac[1] + ss_col.n_fac[1]),
+                 (long long)(ss_row.n_fac[2] + ss_col.n_fac[2]),
+                 (long long)(ss_row.n_fac[3] + ss_col.n_fac[3]),
+                 (long long)(ss_row.n_fac[4] + ss_col.n_fac[4]),
+                 (long long)(ss_row.n_redo + ss_col.n_redo),
+                 (long long)(ss_row.n_redo_mem + ss_col.n_redo_mem));
   }
   mem.release(d_status);
   // the dense matrix is borrowed only for this call
@@ -1912,6 +1991,25 @@ static void build_mv(MatrixData& M, hipStream_t st) {
     V.d_cbegin = upload(mem, cb, st);
     V.d_cblock = upload(mem, cblk, st);
     V.d_cpartner = upload(mem, cpar, st);
+    {
+      // the items with the most coupling entries first: one wave per item,
+      // and an item has up to several times the mean number of blocks
+      std::vector<int64_t> work(S.nitems, 0);
+      for (int32_t i = 0; i < S.nitems; ++i)
+        for (int64_t c = cb[i]; c < cb[i + 1]; ++c)
+          work[i] += (int64_t)M.S_rows[cblk[c]] * M.S_cols[cblk[c]];
+      std::vector<int32_t> ord(S.nitems);
+      for (int32_t i = 0; i < S.nitems; ++i) ord[i] = i;
+      std::stable_sort(ord.begin(), ord.end(),
+                       [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+      V.d_corder = upload(mem, ord, st);
+      // items with more than four times the mean work get four waves
+      int64_t tot = 0;
+      for (int64_t x : work) tot += x;
+      const double lim = 4.0 * (double)tot / std::max<int32_t>(1, S.nitems);
+      V.nheavy = 0;
+      while (V.nheavy < S.nitems && (double)work[ord[V.nheavy]] > lim) ++V.nheavy;
+    }
     // forward lists
     std::vector<int32_t> leafs;
     std::vector<std::vector<int32_t>> byl(tr.depth + 1);
@@ -1972,8 +2070,29 @@ static void build_mv(MatrixData& M, hipStream_t st) {
         }
       }
     }
+    // A leaf's near-field work (entries of its rows) varies by more than an
+    // order of magnitude: a leaf at a shallow level meets large clusters in
+    // its inadmissible blocks.  Leaves with more than twice the mean work
+    // are split into tasks of about that size that write partial sums, added
+    // per leaf in task order afterwards (deterministic); tasks run heaviest
+    // first.
+    int64_t task_entries = 0;
+    {
+      int64_t tot = 0, nlf = 0;
+      for (int32_t t = 0; t < tr.nc(); ++t) {
+        if (!tr.leaf(t)) continue;
+        ++nlf;
+        for (auto& pr : nl[t])
+          tot += tr.size[t] * (s == 0 ? tr.size[bt.near_s[pr.first]] : tr.size[bt.near_t[pr.first]]);
+      }
+      task_entries = std::max<int64_t>(2048, 2 * tot / std::max<int64_t>(1, nlf));
+    }
+    std::vector<std::pair<int64_t, LeafDev>> tasks;
+    std::vector<LeafDev> split;
+    int32_t slots = 0;
     for (int32_t t = 0; t < tr.nc(); ++t) {
       if (!tr.leaf(t)) continue;
+      if (tr.size[t] > 64) fail(DH2_EUNSUPPORTED, "leaf clusters with more than 64 points");
       LeafDev L{};
       L.row_off = tr.off[t];
       L.len = (int32_t)tr.size[t];
@@ -1983,25 +2102,88 @@ static void build_mv(MatrixData& M, hipStream_t st) {
       L.item_count = cnt;
       for (int32_t q = 1; q < cnt; ++q)
         if (S.P->ext2int[B.cs[s].first[t] + q] != L.item_first + q) fail(DH2_EDEVICE, "internal: leaf items not contiguous");
-      L.near_begin = (int64_t)refs.size();
-      for (auto& pr : nl[t]) refs.push_back(NearRefDev{pr.first, pr.second});
-      L.near_end = (int64_t)refs.size();
-      leaves.push_back(L);
+      L.slot = -1;
+      const int64_t r0 = (int64_t)refs.size();
+      int64_t total = 0;
+      std::vector<int64_t> wref;
+      for (auto& pr : nl[t]) {
+        refs.push_back(NearRefDev{pr.first, pr.second});
+        const int64_t b = pr.first;
+        wref.push_back((int64_t)L.len * (s == 0 ? tr.size[bt.near_s[b]] : tr.size[bt.near_t[b]]));
+        total += wref.back();
+      }
+      const int64_t r1 = (int64_t)refs.size();
+      if (total <= task_entries) {
+        L.near_begin = r0;
+        L.near_end = r1;
+        tasks.push_back({total, L});
+        continue;
+      }
+      const int64_t nt = (total + task_entries - 1) / task_entries;
+      const int64_t per = (total + nt - 1) / nt;
+      LeafDev R = L;
+      R.item_first = slots;
+      R.item_count = 0;
+      int64_t q = r0;
+      for (int64_t part = 0; q < r1; ++part) {
+        LeafDev T = L;
+        if (part > 0) T.item_count = 0;  // basis terms in the first task only
+        T.slot = slots++;
+        T.near_begin = q;
+        int64_t wsum = 0;
+        while (q < r1 && (wsum == 0 || wsum + wref[q - r0] <= per)) wsum += wref[q++ - r0];
+        T.near_end = q;
+        tasks.push_back({wsum, T});
+        ++R.item_count;
+      }
+      split.push_back(R);
     }
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+    for (const auto& tk : tasks) leaves.push_back(tk.second);
     V.d_leaves = upload(mem, leaves, st);
     V.d_nref = upload(mem, refs, st);
     V.nleaves = (int32_t)leaves.size();
+    V.d_split = split.empty() ? nullptr : upload(mem, split, st);
+    V.nsplit = (int32_t)split.size();
+    V.nslots = slots;
+    P->maxslots = std::max(P->maxslots, slots);
+  }
+  // the adjoint reads the near field through a transposed copy
+  {
+    int64_t tot = 0;
+    for (const NearDev& nb : M.nears) tot = std::max(tot, nb.off + nb.t_len * nb.s_len);
+    P->d_nearT = (double2*)mem.alloc(std::max<int64_t>(1, tot) * sizeof(double2));
   }
   P->d_nears = upload(mem, M.nears, st);
+  launch_near_transpose(P->d_nears, (int64_t)M.nears.size(), M.d_near, P->d_nearT, st);
+  launch_check("near-field transpose");
   std::vector<double2*> sp(M.S_ptr.begin(), M.S_ptr.end());
   P->d_Sptr = upload(mem, sp, st);
   P->d_Srows = upload(mem, M.S_rows, st);
   P->d_Scols = upload(mem, M.S_cols, st);
+  {
+    // the adjoint's coupling reads S_b^T (kc x kr), a copy made here
+    int64_t tot = 0;
+    for (int64_t b = 0; b < nadm; ++b) tot += (int64_t)M.S_rows[b] * M.S_cols[b];
+    double2* arena = (double2*)mem.alloc(std::max<int64_t>(1, tot) * sizeof(double2));
+    std::vector<double2*> tp(nadm);
+    int64_t o = 0;
+    for (int64_t b = 0; b < nadm; ++b) {
+      tp[b] = arena + o;
+      o += (int64_t)M.S_rows[b] * M.S_cols[b];
+    }
+    P->d_STptr = upload(mem, tp, st);
+    launch_coupling_transpose(P->d_Sptr, P->d_STptr, P->d_Srows, P->d_Scols, nadm, st);
+    launch_check("coupling transpose");
+  }
   int64_t n = tr.n;
   P->xp = (double2*)mem.alloc(n * kMvRhs * sizeof(double2));
   P->yp = (double2*)mem.alloc(n * kMvRhs * sizeof(double2));
   P->xh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * kMvRhs * sizeof(double2));
   P->yh = (double2*)mem.alloc(std::max<int64_t>(1, maxh) * kMvRhs * sizeof(double2));
+  P->part = (double2*)mem.alloc(std::max<int64_t>(1, (int64_t)P->maxslots * 64) * kMvRhs *
+                                sizeof(double2));
   P->maxh = maxh;
   M.mv = std::move(P);
 }
@@ -2024,13 +2206,17 @@ static void matvec_core(MatrixData& M, char op, int nr, const double2* x, double
   launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, w.xp, w.xh, nr, st);
   for (size_t q = 0; q < VA.d_fwd_lvl.size(); ++q)
     launch_fwd_inner(A.d_items, VA.d_fwd_lvl[q], VA.fwd_count[q], VA.d_hoff, w.xh, nr, st);
-  launch_coupling(Bs.d_items, Bs.nitems, VB.d_cbegin, VB.d_cblock, VB.d_cpartner, P.d_Sptr,
-                  P.d_Srows, P.d_Scols, VA.d_hoff, w.xh, VB.d_hoff, w.yh, adj, nr, st);
+  // op N: S_b (kt x ks); adjoint: S_b^T (ks x kt)
+  launch_coupling(Bs.d_items, Bs.nitems, VB.nheavy, VB.d_corder, VB.d_cbegin, VB.d_cblock,
+                  VB.d_cpartner,
+                  adj ? P.d_STptr : P.d_Sptr, adj ? P.d_Scols : P.d_Srows,
+                  adj ? P.d_Srows : P.d_Scols, VA.d_hoff, w.xh, VB.d_hoff, w.yh, adj, nr, st);
   for (size_t l = 0; l < VB.d_bl_items.size(); ++l)
     launch_bwd_inner(Bs.d_items, VB.d_bl_items[l], VB.bl_count[l], VB.d_bl_fbegin[l],
                      VB.d_bl_fitem[l], VB.d_bl_fson[l], VB.d_hoff, w.yh, nr, st);
-  launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near, VB.d_hoff,
-                  w.yh, w.xp, w.yp, adj, nr, st);
+  launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near,
+                  P.d_nearT, VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, st);
+  launch_leaf_sum(VB.d_split, VB.nsplit, w.part, w.yp, nr, st);
   launch_scatter_perm(w.yp, M.d_perm, n, y, st, nr);
   launch_check("matvec");
 }
@@ -2041,7 +2227,8 @@ void matvec(MatrixData& M, char op, int64_t nrhs, const double2* x, double2* y, 
   const int64_t n = M.blk->tree->tr.n;
   for (int64_t q = 0; q < nrhs; q += kMvRhs) {
     const int nr = (int)std::min<int64_t>(kMvRhs, nrhs - q);
-    matvec_core(M, op, nr, x + q * n, y + q * n, MatvecBufs{P.xp, P.yp, P.xh, P.yh}, st);
+    matvec_core(M, op, nr, x + q * n, y + q * n, MatvecBufs{P.xp, P.yp, P.xh, P.yh, P.part},
+                st);
   }
 }
 
@@ -2055,12 +2242,15 @@ void matvec_noalloc(MatrixData& M, char op, int64_t nrhs, const double2* x, doub
     fail(DH2_EINVAL, "the matrix has no matvec plan yet: call dh2_matvec on it once first");
   const int64_t n = M.blk->tree->tr.n;
   const int64_t maxh = std::max<int64_t>(1, M.mv->maxh);
-  // 256-byte aligned parts: xp, yp (n each), xh, yh (maxh each), per
-  // right-hand side of a pass; as many right-hand sides per pass as fit
+  const int64_t maxp = std::max<int64_t>(1, (int64_t)M.mv->maxslots * 64);
+  // 256-byte aligned parts: xp, yp (n each), xh, yh (maxh each), partial
+  // sums of split leaves (64 per slot), per right-hand side of a pass; as
+  // many right-hand sides per pass as fit
   auto part = [](int64_t cnt) { return ((size_t)cnt * sizeof(double2) + 255) / 256 * 256; };
+  auto total = [&](int r) { return 2 * part(n * r) + 2 * part(maxh * r) + part(maxp * r); };
   int nr = kMvRhs;
-  while (nr > 1 && 2 * part(n * nr) + 2 * part(maxh * nr) > noalloc_scratch_bytes()) --nr;
-  const size_t need = 2 * part(n * nr) + 2 * part(maxh * nr);
+  while (nr > 1 && total(nr) > noalloc_scratch_bytes()) --nr;
+  const size_t need = total(nr);
   if (need > noalloc_scratch_bytes())
     fail(DH2_EUNSUPPORTED, "the allocation-free product needs " + std::to_string(need) +
                                " bytes of scratch, more than the library's " +
@@ -2073,6 +2263,7 @@ void matvec_noalloc(MatrixData& M, char op, int64_t nrhs, const double2* x, doub
   w.yp = (double2*)(p + part(n * nr));
   w.xh = (double2*)(p + 2 * part(n * nr));
   w.yh = (double2*)(p + 2 * part(n * nr) + part(maxh * nr));
+  w.part = (double2*)(p + 2 * part(n * nr) + 2 * part(maxh * nr));
   for (int64_t q = 0; q < nrhs; q += nr) {
     const int m = (int)std::min<int64_t>(nr, nrhs - q);
     matvec_core(M, op, m, x + q * n, y + q * n, w, st);

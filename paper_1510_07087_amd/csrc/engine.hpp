@@ -71,6 +71,17 @@ struct TreeData {
 
 struct PlanCache;
 
+// Sizes that choose the batch count of a compression: the first level with
+// admissible blocks, the subtree group of every cluster (subtrees rooted one
+// level above it) and the column counts of the bases per level and group.
+struct SweepSizes {
+  int32_t lmin = 0;
+  int32_t ngroups = 0;
+  std::vector<int32_t> group;  // per cluster, -1 above the group level
+  std::vector<double> lvlN;    // columns per level (mean of both bases)
+  std::vector<double> grpN;    // columns per group (both bases)
+};
+
 struct BlocksData {
   std::shared_ptr<TreeData> tree;
   BlockTree bt;
@@ -79,6 +90,7 @@ struct BlocksData {
   // plan data of the compression for the last batch count used
   mutable std::mutex cache_mu;
   mutable std::shared_ptr<PlanCache> cache;
+  mutable std::shared_ptr<const SweepSizes> sizes;  // built by the first compression
 };
 
 // Plan-derived data of one basis for a given batch count (side 0: rows of G,

@@ -400,9 +400,31 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const ItemDev* items, const
 // k = #{sigma > eps}.
 // ---------------------------------------------------------------------------
 constexpr int kEigLds = 9216;  // largest X in double2 elements (144 KiB)
+constexpr int kFacLdsX = 4800;  // X of the first pass (75 KiB: two workgroups per CU)
 constexpr int kFacThreads = 256;
 // dynamic LDS of the non-leaf R-product (160 KiB per CU minus its static LDS)
 constexpr size_t kRprodLdsMax = 159 * 1024;
+
+// 1/sqrt(x) and 1/x (x > 0, normal): the hardware estimates refined by two
+// Newton steps with FMA residuals (each step squares the relative error)
+__device__ __forceinline__ double rsq_nr2(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+__device__ __forceinline__ double rcp_nr2(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+  }
+  return y;
+}
 
 __device__ __forceinline__ double wave_sum(double v, int width) {
   for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -524,12 +546,14 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
   }
   if (tid == 0) {
     s_p = p;
-    // remaining diagonal not captured by the factor
+    // the factorisation stopped at the column capacity while a remaining
+    // diagonal entry still exceeds tau (the cut the factor would have taken
+    // otherwise)
     double rest = 0.0;
     for (int i = 0; i < r; ++i)
-      if (!done[i]) rest += d[i];
+      if (!done[i]) rest = fmax(rest, d[i]);
     s_rot = 0;
-    if (p == pmax && rest > 0.1 * eps * eps) {
+    if (p == pmax && rest > tau) {
       // X in memory holds all r columns, so this cannot happen there; the
       // LDS-resident kernel marks the item (rank -1) for the host to factor it
       // again with X in memory
@@ -563,31 +587,59 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(ItemDev* items, const in
           int pa = pair, pb = pe - 1 - pair;
           int a = pa == 0 ? 0 : 1 + (pa - 1 + step) % (pe - 1);
           int b = pb == 0 ? 0 : 1 + (pb - 1 + step) % (pe - 1);
+          // squared column norms: summed in the first step of a sweep (its
+          // pairs cover every column), then carried through the rotations
+          // (|x'|^2 = |x|^2 - t |<x, y>|, |y'|^2 = |y|^2 + t |<x, y>|)
           double al = 0, be = 0, gr = 0, gi = 0;
-          for (int i = gl; i < r; i += g) {
-            double2 x = X[a * r + i], y = X[b * r + i];
-            al += x.x * x.x + x.y * x.y;
-            be += y.x * y.x + y.y * y.y;
-            gr += x.x * y.x + x.y * y.y;  // conj(x) * y
-            gi += x.x * y.y - x.y * y.x;
+          if (step == 0) {
+            for (int i = gl; i < r; i += g) {
+              double2 x = X[a * r + i], y = X[b * r + i];
+              al += x.x * x.x + x.y * x.y;
+              be += y.x * y.x + y.y * y.y;
+              gr += x.x * y.x + x.y * y.y;  // conj(x) * y
+              gi += x.x * y.y - x.y * y.x;
+            }
+            al = wave_sum(al, g);
+            be = wave_sum(be, g);
+          } else {
+            for (int i = gl; i < r; i += g) {
+              double2 x = X[a * r + i], y = X[b * r + i];
+              gr += x.x * y.x + x.y * y.y;
+              gi += x.x * y.y - x.y * y.x;
+            }
+            al = s_norm[a];
+            be = s_norm[b];
           }
-          al = wave_sum(al, g);
-          be = wave_sum(be, g);
           gr = wave_sum(gr, g);
           gi = wave_sum(gi, g);
-          double ag = sqrt(gr * gr + gi * gi);
-          if (ag > 1e-15 * sqrt(al * be) && ag > 1e-300) {
-            double tz = (be - al) / (2.0 * ag);
-            double t = (tz >= 0 ? 1.0 : -1.0) / (fabs(tz) + sqrt(1.0 + tz * tz));
-            double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-            double er = gr / ag, ei = -gi / ag;  // e^{-i phi}
+          const double g2 = gr * gr + gi * gi;  // |<x, y>|^2
+          // rotate unless |<x, y>| <= 1e-15 |x| |y|
+          if (g2 > 1e-30 * al * be && g2 > 1e-280) {
+            // rotation parameters from hardware reciprocal (square-root)
+            // estimates refined by two Newton steps each (to the last bits;
+            // c^2 + s^2 = 1 to rounding, so the rotation stays orthogonal)
+            const double iag = rsq_nr2(g2);  // 1 / |<x, y>|
+            double tz = (be - al) * 0.5 * iag;
+            const double h = fma(tz, tz, 1.0);
+            double t = rcp_nr2(fabs(tz) + h * rsq_nr2(h));
+            if (tz < 0) t = -t;
+            double c = rsq_nr2(fma(t, t, 1.0)), s = c * t;
+            double er = gr * iag, ei = -gi * iag;  // e^{-i phi}
             for (int i = gl; i < r; i += g) {
               double2 x = X[a * r + i], y = X[b * r + i];
               double2 ey = make_double2(er * y.x - ei * y.y, er * y.y + ei * y.x);
               X[a * r + i] = make_double2(c * x.x - s * ey.x, c * x.y - s * ey.y);
               X[b * r + i] = make_double2(s * x.x + c * ey.x, s * x.y + c * ey.y);
             }
+            const double tg = t * (g2 * iag);
+            al = fmax(0.0, al - tg);
+            be += tg;
             if (gl == 0) s_rot = 1;
+          }
+          // the pair's lanes are one wave: all have read the norms above
+          if (gl == 0) {
+            s_norm[a] = al;
+            s_norm[b] = be;
           }
         }
         __syncthreads();
@@ -1123,19 +1175,45 @@ __global__ void k_scatter_perm(const double2* yp, const int64_t* perm, int64_t n
 // sides (op: conj when conj_a), with U terms loaded ahead of their products
 // (U = 4 for one or two right-hand sides, fewer for more) so that several
 // loads are in flight.
+// Loads and stores through global (address space 1) pointers: a generic
+// (flat) access also counts against the LDS wait counter, so that waits for
+// LDS operands would also wait for memory traffic in flight.  Native vector
+// types carry the address space; the HIP vector types do not.
+typedef double gdv2 __attribute__((ext_vector_type(2)));
+typedef float gfv2 __attribute__((ext_vector_type(2)));
+typedef double gdv4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 ldg(const double2* p, int64_t i) {
+  const gdv2 v = ((const __attribute__((address_space(1))) gdv2*)p)[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ldg(const float2* p, int64_t i) {
+  const gfv2 v = ((const __attribute__((address_space(1))) gfv2*)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double4 ldg(const double4* p, int64_t i) {
+  const gdv4 v = ((const __attribute__((address_space(1))) gdv4*)p)[i];
+  return make_double4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stg(double2* p, int64_t i, double2 v) {
+  ((__attribute__((address_space(1))) gdv2*)p)[i] = gdv2{v.x, v.y};
+}
+__device__ __forceinline__ void stg(float2* p, int64_t i, float2 v) {
+  ((__attribute__((address_space(1))) gfv2*)p)[i] = gfv2{v.x, v.y};
+}
+
 template <int NR>
 __device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int64_t as,
                                         const double2* v, int64_t n, int nr, bool conj_a) {
-  constexpr int U = NR <= 2 ? 4 : (NR <= 4 ? 2 : 1);
+  constexpr int U = NR == 1 ? 8 : (NR == 2 ? 4 : (NR <= 4 ? 2 : 1));
   int64_t c = 0;
   for (; c + U <= n; c += U) {
     double2 av[U], xv[U][NR];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      av[u] = a[(c + u) * as];
+      av[u] = ldg(a, (c + u) * as);
 #pragma unroll
       for (int q = 0; q < NR; ++q)
-        if (q < nr) xv[u][q] = v[(c + u) * nr + q];
+        if (q < nr) xv[u][q] = ldg(v, (c + u) * nr + q);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -1148,11 +1226,12 @@ __device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int6
         }
   }
   for (; c < n; ++c) {
-    const double2 ac = a[c * as];
+    const double2 ac = ldg(a, c * as);
 #pragma unroll
     for (int q = 0; q < NR; ++q)
       if (q < nr) {
-        double2 t = conj_a ? cmulc(ac, v[c * nr + q]) : cmul(ac, v[c * nr + q]);
+        const double2 xq = ldg(v, c * nr + q);
+        double2 t = conj_a ? cmulc(ac, xq) : cmul(ac, xq);
         s[q].x += t.x;
         s[q].y += t.y;
       }
@@ -1201,11 +1280,19 @@ __global__ __launch_bounds__(128) void k_fwd_inner(const ItemDev* items, const i
 }
 
 // coupling: yh_i = sum over the item's blocks of S_b xh_partner (or S_b^* for
-// the adjoint, where S_b is kr x kc with the item on the column side).  One
-// wave per item, lane kk one coefficient; the partner's coefficients are
-// the same for all lanes.
-template <int NR>
+// the adjoint, where S_b is kr x kc with the item on the column side).  The
+// matrices come oriented with the item's coefficients as rows: S_b for op
+// N, the transposed copy S_b^T (kc x kr, column-major) for the adjoint, so
+// that both read consecutive rows across the lanes.  WPI waves per item
+// (1, or 4 for the items with the most blocks), items taken in the order
+// given (most work first): each wave is cut into 64 / kp slots of kp lanes
+// (kp the power of two >= k, at least 8), lane kk of a slot one coefficient;
+// the slots of the item's waves take its blocks in turn, and their sums are
+// added with shuffles, then across the waves through LDS, in a fixed order.
+// The partner's coefficients are the same for all lanes of a slot.
+template <int NR, int WPI>
 __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t nitems,
+                                                  const int32_t* order,
                                                   const int64_t* cbegin, const int32_t* cblock,
                                                   const int32_t* cpartner,
                                                   const double2* const* S_ptr,
@@ -1213,30 +1300,54 @@ __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t 
                                                   const int64_t* xh_off, const double2* xh,
                                                   const int64_t* yh_off, double2* yh,
                                                   int adjoint, int nr) {
-  int32_t i = (int32_t)blockIdx.x * 4 + wave_id();
-  if (i >= nitems) return;
+  __shared__ double2 part[WPI > 1 ? WPI : 1][NR][64];
+  const int w = wave_id();
+  const int32_t wi = WPI > 1 ? (int32_t)blockIdx.x : (int32_t)blockIdx.x * 4 + w;
+  if (wi >= nitems) return;
+  const int32_t i = order[wi];
   const int lane = threadIdx.x & 63;
   const int k = items[i].k;
+  const int kp = k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64));
+  const int nslot = 64 / kp, sl = lane / kp, kl = lane % kp;
+  const int first = (WPI > 1 ? w * nslot : 0) + sl, stride = WPI * nslot;
   for (int kk0 = 0; kk0 < k; kk0 += 64) {
-    const int kk = min(kk0 + lane, k - 1);
+    const int kk = min(kk0 + kl, k - 1);
     double2 s[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
-    for (int64_t c = cbegin[i]; c < cbegin[i + 1]; ++c) {
+    for (int64_t c = cbegin[i] + first; c < cbegin[i + 1]; c += stride) {
       const int32_t b = cblock[c];
       const double2* Sb = S_ptr[b];
-      const int kr = S_rows[b], kc = S_cols[b];
+      const int kr = S_rows[b], kc = S_cols[b];  // of the oriented matrix
       const double2* x = xh + xh_off[cpartner[c]] * nr;
-      // op N: sum_jj S[kk, jj] x[jj]; adjoint: sum_jj conj(S[jj, kk]) x[jj]
-      const int n = adjoint ? kr : kc;
-      const int64_t st = adjoint ? 1 : kr;
-      const double2* a0 = adjoint ? Sb + (int64_t)kk * kr : Sb + kk;
-      dot_rhs<NR>(s, a0, st, x, n, nr, adjoint != 0);
+      // op N: sum_jj S[kk, jj] x[jj]; adjoint: sum_jj conj(S^T[kk, jj]) x[jj]
+      dot_rhs<NR>(s, Sb + kk, kr, x, kc, nr, adjoint != 0);
     }
-    if (kk0 + lane < k)
+    for (int o = kp; o < 64; o <<= 1)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        s[q].x += __shfl_xor(s[q].x, o, 64);
+        s[q].y += __shfl_xor(s[q].y, o, 64);
+      }
+    if constexpr (WPI > 1) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) part[w][q][lane] = s[q];
+      __syncthreads();
+      if (w == 0) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+          for (int u = 1; u < WPI; ++u) {
+            s[q].x += part[u][q][lane].x;
+            s[q].y += part[u][q][lane].y;
+          }
+      }
+      __syncthreads();
+    }
+    if ((WPI == 1 || w == 0) && sl == 0 && kk0 + kl < k)
 #pragma unroll
       for (int q = 0; q < NR; ++q)
-        if (q < nr) yh[(yh_off[i] + kk0 + lane) * nr + q] = s[q];
+        if (q < nr) yh[(yh_off[i] + kk0 + kl) * nr + q] = s[q];
   }
 }
 
@@ -1267,58 +1378,105 @@ __global__ __launch_bounds__(128) void k_bwd_inner(const ItemDev* items, const i
 }
 
 // leaf rows: y|L = sum_c Q_Lc yh_Lc + near-field rows of L.  One workgroup
-// of four waves per leaf, lane j one row of the leaf (leaves have at most 64
-// rows): the waves take the leaf's basis terms and near-field blocks in
-// turn, and the partial sums are added through LDS in wave order.
+// of four waves per task (a leaf, or a part of a leaf's near-field blocks),
+// lane j one row of the leaf (leaves have at most 64 rows): the waves take
+// the task's basis terms and near-field blocks in turn, and the partial sums
+// are added through LDS in wave order.  The adjoint reads the transposed
+// copy of every near-field block (nearT, #s x #t column-major), so that both
+// products read consecutive rows across the lanes.
 template <int NR>
 __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const LeafDev* leaves,
                                                   const NearRefDev* nref, const NearDev* nears,
-                                                  const double2* nearv, const int64_t* yh_off,
-                                                  const double2* yh, const double2* xp,
-                                                  double2* yp, int adjoint, int nr) {
+                                                  const double2* nearv, const double2* nearT,
+                                                  const int64_t* yh_off, const double2* yh,
+                                                  const double2* xp, double2* yp,
+                                                  double2* partial, int adjoint, int nr) {
   __shared__ double2 part[4][NR][64];
   const LeafDev L = leaves[blockIdx.x];
   const int w = wave_id(), lane = threadIdx.x & 63;
-  for (int j0 = 0; j0 < L.len; j0 += 64) {
-    const int j = min(j0 + lane, L.len - 1);
-    double2 s[NR];
+  const int j = min(lane, L.len - 1);
+  double2 s[NR];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
-    for (int q = L.item_first + w; q < L.item_first + L.item_count; q += 4) {
-      const ItemDev& it = items[q];
-      dot_rhs<NR>(s, it.Q + (int64_t)j * it.k, 1, yh + yh_off[q] * nr, it.k, nr, false);
-    }
-    for (int64_t q = L.near_begin + w; q < L.near_end; q += 4) {
-      const NearRefDev ref = nref[q];
-      const NearDev nb = nears[ref.b];
-      const double2* B = nearv + nb.off;
-      // op N: sum_c B[row, c] x[s_off + c]; adjoint: sum_c conj(B[c, row])
-      // x[t_off + c], with row = ref.row0 + j
-      const int64_t row = ref.row0 + j;
-      if (!adjoint)
-        dot_rhs<NR>(s, B + row, nb.t_len, xp + nb.s_off * nr, nb.s_len, nr, false);
-      else
-        dot_rhs<NR>(s, B + row * nb.t_len, 1, xp + nb.t_off * nr, nb.t_len, nr, true);
-    }
+  for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
+  for (int q = L.item_first + w; q < L.item_first + L.item_count; q += 4) {
+    const ItemDev& it = items[q];
+    dot_rhs<NR>(s, it.Q + (int64_t)j * it.k, 1, yh + yh_off[q] * nr, it.k, nr, false);
+  }
+  for (int64_t q = L.near_begin + w; q < L.near_end; q += 4) {
+    const NearRefDev ref = nref[q];
+    const NearDev nb = nears[ref.b];
+    // op N: sum_c B[row, c] x[s_off + c]; adjoint: sum_c conj(B[c, row])
+    // x[t_off + c] = sum_c conj(B^T[row, c]) x[t_off + c], with row = ref.row0 + j
+    const int64_t row = ref.row0 + j;
+    if (!adjoint)
+      dot_rhs<NR>(s, nearv + nb.off + row, nb.t_len, xp + nb.s_off * nr, nb.s_len, nr, false);
+    else
+      dot_rhs<NR>(s, nearT + nb.off + row, nb.s_len, xp + nb.t_off * nr, nb.t_len, nr, true);
+  }
 #pragma unroll
-    for (int q = 0; q < NR; ++q) part[w][q][lane] = s[q];
-    __syncthreads();
-    if (w == 0 && j0 + lane < L.len) {
+  for (int q = 0; q < NR; ++q) part[w][q][lane] = s[q];
+  __syncthreads();
+  if (w == 0 && lane < L.len) {
+    double2* out = L.slot < 0 ? yp + (L.row_off + lane) * nr
+                              : partial + ((int64_t)L.slot * 64 + lane) * nr;
 #pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        if (q < nr) {
-          double2 t = part[0][q][lane];
+    for (int q = 0; q < NR; ++q) {
+      if (q < nr) {
+        double2 t = part[0][q][lane];
 #pragma unroll
-          for (int u = 1; u < 4; ++u) {
-            t.x += part[u][q][lane].x;
-            t.y += part[u][q][lane].y;
-          }
-          yp[(L.row_off + j0 + lane) * nr + q] = t;
+        for (int u = 1; u < 4; ++u) {
+          t.x += part[u][q][lane].x;
+          t.y += part[u][q][lane].y;
         }
+        out[q] = t;
       }
     }
-    __syncthreads();
   }
+}
+
+// rows of the leaves whose work was split: the partial sums of their slots
+// added in slot order (one wave per leaf)
+template <int NR>
+__global__ __launch_bounds__(64) void k_leaf_sum(const LeafDev* leaves, const double2* partial,
+                                                 double2* yp, int nr) {
+  const LeafDev L = leaves[blockIdx.x];
+  const int lane = threadIdx.x;
+  if (lane >= L.len) return;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    if (q < nr) {
+      double2 t = make_double2(0.0, 0.0);
+      for (int sl = L.item_first; sl < L.item_first + L.item_count; ++sl) {
+        const double2 v = partial[((int64_t)sl * 64 + lane) * nr + q];
+        t.x += v.x;
+        t.y += v.y;
+      }
+      yp[(L.row_off + lane) * nr + q] = t;
+    }
+  }
+}
+
+// transposed copy of the near-field blocks for the adjoint (one workgroup
+// per block, tiles of 64 rows x 32 columns through LDS)
+__global__ __launch_bounds__(256) void k_near_transpose(const NearDev* nears, const double2* B,
+                                                        double2* BT) {
+  __shared__ double2 tile[32][65];
+  const NearDev nb = nears[blockIdx.x];
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;  // loads: 64 rows x 4
+  const int sx = threadIdx.x & 31, sy = threadIdx.x >> 5;  // stores: 32 columns x 8
+  for (int64_t i0 = 0; i0 < nb.t_len; i0 += 64)
+    for (int64_t j0 = 0; j0 < nb.s_len; j0 += 32) {
+      for (int jj = ly; jj < 32; jj += 4) {
+        const int64_t i = i0 + lx, j = j0 + jj;
+        if (i < nb.t_len && j < nb.s_len) tile[jj][lx] = B[nb.off + i + j * nb.t_len];
+      }
+      __syncthreads();
+      for (int ii = sy; ii < 64; ii += 8) {
+        const int64_t j = j0 + sx, i = i0 + ii;
+        if (i < nb.t_len && j < nb.s_len) BT[nb.off + j + i * nb.s_len] = tile[sx][ii];
+      }
+      __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1731,7 +1889,7 @@ struct RAcc<false> {
   }
   __device__ __forceinline__ int row(int lane, int v) const { return f64_row(lane, v); }
   __device__ __forceinline__ void store(void* R, int64_t idx, int v, double sc = 1.0) const {
-    reinterpret_cast<double2*>(R)[idx] = make_double2(re[v] * sc, im[v] * sc);
+    stg(reinterpret_cast<double2*>(R), idx, make_double2(re[v] * sc, im[v] * sc));
   }
 };
 template <>
@@ -1746,7 +1904,27 @@ struct RAcc<true> {
   __device__ __forceinline__ int row(int lane, int v) const { return f32_row(lane, v); }
   __device__ __forceinline__ void store(void* R, int64_t idx, int v, double sc = 1.0) const {
     float f = (float)sc;
-    reinterpret_cast<float2*>(R)[idx] = make_float2(re[v] * f, im[v] * f);
+    stg(reinterpret_cast<float2*>(R), idx, make_float2(re[v] * f, im[v] * f));
+  }
+};
+
+// Column j of R^T: inherited columns in the level's arena, own-block
+// columns (row basis) in the arena kept for the projection.  The item's
+// fields are taken into registers once (the stores could alias the item
+// array, so reading them at every store would reload them).
+template <bool MX>
+struct RDst {
+  void* R;
+  void* Rown;
+  int64_t ninh;
+  int k;
+  __device__ __forceinline__ explicit RDst(const ItemDev& it)
+      : R(it.R), Rown(it.Rown), ninh(it.ninh), k(it.k) {}
+  __device__ __forceinline__ void* col(int64_t j) const {
+    using E = typename std::conditional<MX, float2, double2>::type;
+    return (Rown != nullptr && j >= ninh)
+               ? static_cast<void*>(reinterpret_cast<E*>(Rown) + (j - ninh) * k)
+               : static_cast<void*>(reinterpret_cast<E*>(R) + j * k);
   }
 };
 
@@ -1771,38 +1949,48 @@ __device__ __forceinline__ void rmax_flush(const ItemDev& it, const unsigned* s_
     if (s_rmax[kk]) atomicMax(reinterpret_cast<unsigned*>(it.rmax) + kk, s_rmax[kk]);
 }
 
-// R^T of a non-leaf block row, one workgroup per unit (column range): the
-// four waves share Q_hat (in the compute precision, rows padded with zeros to
-// r + 8) in LDS and take 16-column groups in turn.
-// R^T[j][kk] = zeta sum_rho [R_t1c'; R_t2c'][rho][j] conj(Q_hat[rho][kk]).
-// Row rho of the stacked sons' R is one load from the son that holds it.
-// The sons' values are loaded kRing - 1 k-steps ahead and Q_hat one step
+// The rows of the product's operand: rows [0, k1) from P1 (column j at
+// P1[j k1]) and rows [k1, r) from P2 (column j at P2[j k2]), both starting at
+// column c0 (the sons' R of a non-leaf item).
+struct RowsSrc {
+  const void* P1;
+  const void* P2;
+  int k1, k2;
+  int64_t c0;
+};
+
+// R^T of a block row read from memory, one workgroup per unit (column
+// range): the four waves share Q_hat (in the compute precision, rows padded
+// with zeros to r + 8) in LDS and take 16-column groups in turn.
+// Non-leaf: R^T[j][kk] = zeta sum_rho [R_t1c'; R_t2c'][rho][j] conj(Q_hat[rho][kk]).
+// Row rho of the operand is one load from the part that holds it.
+// The operand values are loaded kRing - 1 k-steps ahead and Q_hat one step
 // ahead, in rings of kRing register sets that are unrolled so that no loaded
 // register is copied.
 template <bool MX, int KT>
-__device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemDev& s2,
-                               const UnitDev& u, double zeta, const ROp<MX>* Qs,
-                               unsigned* s_rmax, int kc0 = 0) {
+__device__ void rprod_rows_wg(const ItemDev& it, const RowsSrc& src, const UnitDev& u,
+                              double zeta, const ROp<MX>* Qs, unsigned* s_rmax, int kc0 = 0) {
   using OT = ROp<MX>;
   using S = typename std::conditional<MX, float, double>::type;
   typedef S E2 __attribute__((ext_vector_type(2)));
   using GP = const __attribute__((address_space(1))) E2*;
   constexpr int kRing = 5;
   int w = wave_id(), lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
-  const int r = it.r, k = it.k, k1 = s1.k;
+  const int r = it.r, k = it.k, k1 = src.k1, k2 = src.k2;
   const int nks = (r + 3) / 4;
   constexpr int ldq = 16 * KT;
   const int ncols = (int)u.ncols;
-  const int64_t c0 = it.col_off + u.col_begin;
-  const OT* R1 = reinterpret_cast<const OT*>(s1.R) + c0 * k1;  // column j at R1[j * k1]
-  const OT* R2 = reinterpret_cast<const OT*>(s2.R) + c0 * s2.k;
+  const int64_t c0 = src.c0;
+  const OT* R1 = reinterpret_cast<const OT*>(src.P1) + c0 * k1;  // column j at R1[j * k1]
+  const OT* R2 = reinterpret_cast<const OT*>(src.P2) + c0 * k2;
+  const RDst<MX> dst(it);
   for (int j0 = 16 * w; j0 < ncols; j0 += 64) {
     // one load per element: row rho of [R1; R2] in column j; columns past
     // the unit and rows past r read a valid element instead (their products
     // land in columns that are not stored, or meet zero rows of Q_hat)
     const int jc = min(j0 + row, ncols - 1);
     const OT* c1 = R1 + (int64_t)jc * k1;
-    const OT* c2 = R2 + (int64_t)jc * s2.k - k1;
+    const OT* c2 = R2 + (int64_t)jc * k2 - k1;
     auto lda = [&](int rho, OT& a) {
       const int rc = min(rho, r - 1);
       E2 v = ((GP)(rc < k1 ? c1 + rc : c2 + rc))[0];
@@ -1855,7 +2043,7 @@ __device__ void rprod_inner_wg(const ItemDev& it, const ItemDev& s1, const ItemD
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int64_t jv = j0 + acc[t].row(lane, v);
-        if (jv < ncols && kk < k) acc[t].store(it.R, (u.col_begin + jv) * k + kk, v, zeta);
+        if (jv < ncols && kk < k) acc[t].store(dst.col(u.col_begin + jv), kk, v, zeta);
       }
       if constexpr (MX) {
         // the stored values are the accumulators scaled by zeta in FP32
@@ -1891,7 +2079,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX && KT <=
   }
   for (int kk = threadIdx.x; kk < kMaxR; kk += 256) s_rmax[kk] = 0u;
   __syncthreads();
-  rprod_inner_wg<MX, KT>(it, items[it.son[0]], items[it.son[1]], u, zeta, Qs, s_rmax);
+  const ItemDev& s1 = items[it.son[0]];
+  const ItemDev& s2 = items[it.son[1]];
+  const RowsSrc src{s1.R, s2.R, s1.k, s2.k, it.col_off + u.col_begin};
+  rprod_rows_wg<MX, KT>(it, src, u, zeta, Qs, s_rmax);
   if constexpr (MX) {
     __syncthreads();
     rmax_flush(it, s_rmax);
@@ -1912,8 +2103,10 @@ __global__ __launch_bounds__(256) void k_rprod_inner_big(const ItemDev* items,
   if (it.k == 0) return;
   for (int kk = threadIdx.x; kk < kMaxRBig; kk += 256) s_rmax[kk] = 0u;
   __syncthreads();
-  rprod_inner_wg<MX, 4>(it, items[it.son[0]], items[it.son[1]], u, zeta, qchunk[blockIdx.x],
-                        s_rmax, 64 * u.a0);
+  const ItemDev& s1 = items[it.son[0]];
+  const ItemDev& s2 = items[it.son[1]];
+  const RowsSrc src{s1.R, s2.R, s1.k, s2.k, it.col_off + u.col_begin};
+  rprod_rows_wg<MX, 4>(it, src, u, zeta, qchunk[blockIdx.x], s_rmax, 64 * u.a0);
   if constexpr (MX) {
     __syncthreads();
     rmax_flush(it, s_rmax);
@@ -1946,11 +2139,12 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
   int w = wave_id(), lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   int r = it.r, k = it.k;
   int nks = (r + 3) / 4;
+  const RDst<MX> dst(it);
+  const double4* const cols = it.cols;
   for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
     int64_t j = u.col_begin + j0 + row;
-    double4 cc = j0 + row < u.ncols ? it.cols[j]
-                                    : (MX && SRC == SRC_HELMHOLTZ
-                                           ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0));
+    double4 cc = MX && SRC == SRC_HELMHOLTZ ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0);
+    if (j0 + row < u.ncols) cc = ldg(cols, j);
     RAcc<MX> acc[KT];
     if constexpr (MX && SRC == SRC_HELMHOLTZ) {
       // the lane's entries of all k-steps first (independent chains), then
@@ -1989,7 +2183,7 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int64_t jl = j0 + acc[t].row(lane, v);
-        if (jl < u.ncols && kk < k) acc[t].store(it.R, (u.col_begin + jl) * k + kk, v);
+        if (jl < u.ncols && kk < k) acc[t].store(dst.col(u.col_begin + jl), kk, v);
       }
       rmax_tile<MX>(acc[t], j0, u.ncols, kk, k, s_rmax);
     }
@@ -2127,26 +2321,11 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
       if (tid < 64) {
         int64_t j = (int64_t)c * 64 + tid;
         // double layer: the column data hold positions, padding reads point 0
-        cold[buf * 64 + tid] = (c < nch && j < ncols)
-                                   ? it.cols[u.col_begin + j]
-                                   : (KIND == 0 ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0));
+        double4 v = KIND == 0 ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0);
+        if (c < nch && j < ncols) v = ldg(it.cols, u.col_begin + j);
+        cold[buf * 64 + tid] = v;
       }
     }
-  };
-  // source of the non-leaf rows: row rho of [R_t1c'; R_t2c'] (zeta applied to the Gram)
-  auto inner_src = [&](int rho, int& ld) -> const float2* {
-    const ItemDev& s1 = items[it.son[0]];
-    const ItemDev& s2 = items[it.son[1]];
-    ld = 1;
-    if (rho < s1.k) {
-      ld = s1.k;
-      return reinterpret_cast<const float2*>(s1.R) + rho;
-    }
-    if (rho < r) {
-      ld = s2.k;
-      return reinterpret_cast<const float2*>(s2.R) + (rho - s1.k);
-    }
-    return nullptr;
   };
   __syncthreads();
   if constexpr (KIND == 2) {
@@ -2240,23 +2419,35 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
   // iteration before they are sliced
   // combos of 4 columns: cb = ((T * 4 + gg) * 4 + pp) * 16 + i, columns
   // 16 gg + 4 pp .. + 3 of the chunk for row i of tile T
+  // The loads of a combo are issued without branches: rows past r read row
+  // r - 1 and columns past the unit its last column (all inside the sons'
+  // R), and those values are then replaced by zeros.  Combos past the unit's
+  // tiles (whole waves, since ntile * 256 is a multiple of 64) load nothing.
   float2 raw[2][4];
   auto load_raw = [&](int c) {
+    if (c >= nch) return;
+    const ItemDev& s1 = items[it.son[0]];
+    const ItemDev& s2 = items[it.son[1]];
+    const int k1 = s1.k;
+    const int64_t c0 = it.col_off + u.col_begin;
 #pragma unroll
     for (int h2 = 0; h2 < 2; ++h2) {
-      int cb = tid + kI8Threads * h2;
+      const int cb = tid + kI8Threads * h2;
+      if (cb >= ntile * 256) continue;
+      const int i = cb & 15, pp = (cb >> 4) & 3, gg = (cb >> 6) & 3, T = cb >> 8;
+      const int rho = row0(T) + i;
+      const bool rowok = rho < r;
+      const int rc = min(rho, r - 1);
+      const bool first = rc < k1;
+      const float2* src = first ? reinterpret_cast<const float2*>(s1.R) + rc
+                                : reinterpret_cast<const float2*>(s2.R) + (rc - k1);
+      const int64_t ld = first ? k1 : s2.k;
+      const int64_t j0 = (int64_t)c * 64 + 16 * gg + 4 * pp;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) raw[h2][q] = make_float2(0.0f, 0.0f);
-      if (cb < ntile * 256 && c < nch) {
-        int i = cb & 15, pp = (cb >> 4) & 3, gg = (cb >> 6) & 3, T = cb >> 8;
-        int ld;
-        const float2* src = inner_src(row0(T) + i, ld);
-        int64_t j0 = (int64_t)c * 64 + 16 * gg + 4 * pp;
-        if (src) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (j0 + q < ncols) raw[h2][q] = src[(it.col_off + u.col_begin + j0 + q) * ld];
-        }
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = min(j0 + q, ncols - 1);
+        const float2 v = ldg(src, (c0 + j) * ld);
+        raw[h2][q] = rowok && j0 + q < ncols ? v : make_float2(0.0f, 0.0f);
       }
     }
   };
@@ -2324,23 +2515,41 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
     cA = (type == 1 || type == 2) ? 1 : 0;
     cB = (type == 1 || type == 3) ? 1 : 0;
   };
+  // LDS offsets of the wave's products, fixed over the chunks and the same
+  // for all lanes of the wave: operand A of product s at offA[s] + 1024 p
+  // (slice p) + 16 lane, operand B at offB[s] + 1024 q + 16 lane.  Taken
+  // once for the non-leaf rows; the generated rows need those registers
+  // for the entries and take them per chunk.
+  int offA[kI8ProdPerWave], offB[kI8ProdPerWave];
+  auto product_offsets = [&](int s) {
+    offA[s] = offB[s] = 0;
+    const int q = w + kI8Waves * s;
+    if (q < nprod) {
+      int TA, TB, cA, cB;
+      tiles_of(q, TA, TB, cA, cB);
+      offA[s] = __builtin_amdgcn_readfirstlane(i8_off(TA, cA, 0, 0, 0));
+      offB[s] = __builtin_amdgcn_readfirstlane(i8_off(TB, cB, 0, 0, 0));
+    }
+  };
+  if constexpr (KIND == 1) {
+#pragma unroll
+    for (int s = 0; s < kI8ProdPerWave; ++s) product_offsets(s);
+  }
   auto consume = [&](int buf) {
-    const char* S = slices + buf * kI8Buf;
-    int gg = lane >> 4, i = lane & 15;
+    const char* S = slices + buf * kI8Buf + 16 * lane;
 #pragma unroll
     for (int s = 0; s < kI8ProdPerWave; ++s) {
       int q = w + kI8Waves * s;
       if (q < nprod) {
-        int TA, TB, cA, cB;
-        tiles_of(q, TA, TB, cA, cB);
+        if constexpr (KIND != 1) product_offsets(s);
         // slice pairs (p, q) with p + q <= 5 (0-based) into level p + q
         ivec4 a[4];
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-          a[p] = *reinterpret_cast<const ivec4*>(S + i8_off(TA, cA, p, gg, i));
+          a[p] = *reinterpret_cast<const ivec4*>(S + offA[s] + 1024 * p);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          ivec4 b = *reinterpret_cast<const ivec4*>(S + i8_off(TB, cB, q, gg, i));
+          ivec4 b = *reinterpret_cast<const ivec4*>(S + offB[s] + 1024 * q);
 #pragma unroll
           for (int p = 0; p < 4; ++p)
             if (p + q <= 5) acc[s][p + q] = mfma_i8(a[p], b, acc[s][p + q]);
@@ -2485,7 +2694,7 @@ void launch_ranks(const ItemDev* items, int32_t n, int32_t* out, hipStream_t st)
 }
 
 void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rmax, double eps,
-                   int max_sweeps, int32_t* status, hipStream_t st) {
+                   int max_sweeps, int32_t* status, hipStream_t st, bool wide) {
   if (nl == 0) return;
   static std::once_flag attr;
   std::call_once(attr, [] {
@@ -2493,8 +2702,13 @@ void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rm
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(kEigLds * sizeof(double2)));
   });
-  // X needs r columns plus one for the even pairing
-  int cap = std::min(kEigLds, std::max(2, rmax * (rmax + 1)));
+  // X needs p columns (the numerical rank of the Gram matrix above the cut),
+  // plus one for the even pairing.  First pass: X within kFacLdsX elements
+  // (two workgroups per CU) even where that holds fewer than r + 1 columns;
+  // a factor that needs more is marked and factored again with room for all
+  // columns (wide: up to kEigLds, one workgroup per CU)
+  const int full = std::max(2, rmax * (rmax + 1));
+  int cap = wide ? std::min(kEigLds, full) : std::min(kFacLdsX, full);
   hipLaunchKernelGGL((k_factor<kMaxR, false>), dim3(nl), dim3(kFacThreads),
                      (size_t)cap * sizeof(double2), st, items, litems, eps, max_sweeps, cap,
                      status, nullptr);
@@ -2636,18 +2850,6 @@ void launch_rprod_inner_big(bool mixed, const ItemDev* items, const UnitDev* uni
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st) {
   if (ntasks == 0) return;
   hipLaunchKernelGGL(k_expand, dim3((unsigned)ntasks), dim3(256), 0, st, tasks);
-}
-
-__global__ __launch_bounds__(256) void k_copy_bytes(const CopyDev* tasks) {
-  const CopyDev t = tasks[blockIdx.x];
-  const uint64_t* s = reinterpret_cast<const uint64_t*>(t.src);
-  uint64_t* d = reinterpret_cast<uint64_t*>(t.dst);
-  for (int64_t e = threadIdx.x; e < t.bytes / 8; e += 256) d[e] = s[e];
-}
-
-void launch_copy_bytes(const CopyDev* tasks, int64_t ntasks, hipStream_t st) {
-  if (ntasks == 0) return;
-  hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)ntasks), dim3(256), 0, st, tasks);
 }
 
 void launch_cvt(const CvtDev* tasks, int64_t ntasks, hipStream_t st) {
@@ -2822,15 +3024,46 @@ void launch_fwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
   DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_fwd_inner<NR>, dim3(nl), dim3(128), 0, st, items,
                                          litems, xh_off, xh, nr));
 }
-void launch_coupling(const ItemDev* items, int32_t nitems, const int64_t* cbegin,
-                     const int32_t* cblock, const int32_t* cpartner, const double2* const* S_ptr,
+// S_b^T of every admissible block (one workgroup per block)
+__global__ __launch_bounds__(256) void k_coupling_transpose(const double2* const* S,
+                                                            double2* const* ST,
+                                                            const int32_t* rows,
+                                                            const int32_t* cols) {
+  const int b = blockIdx.x;
+  const double2* A = S[b];
+  double2* T = ST[b];
+  const int kr = rows[b], kc = cols[b];
+  for (int e = threadIdx.x; e < kr * kc; e += 256) {
+    const int i = e % kr, j = e / kr;
+    T[j + (int64_t)i * kc] = A[e];
+  }
+}
+
+void launch_coupling_transpose(const double2* const* S, double2* const* ST, const int32_t* rows,
+                               const int32_t* cols, int64_t nblocks, hipStream_t st) {
+  if (nblocks == 0) return;
+  hipLaunchKernelGGL(k_coupling_transpose, dim3((unsigned)nblocks), dim3(256), 0, st, S, ST, rows,
+                     cols);
+}
+
+void launch_coupling(const ItemDev* items, int32_t nitems, int32_t nheavy,
+                     const int32_t* order, const int64_t* cbegin, const int32_t* cblock,
+                     const int32_t* cpartner, const double2* const* S_ptr,
                      const int32_t* S_rows, const int32_t* S_cols, const int64_t* xh_off,
                      const double2* xh, const int64_t* yh_off, double2* yh, int adjoint, int nr,
                      hipStream_t st) {
   if (nitems == 0) return;
-  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_coupling<NR>, dim3((nitems + 3) / 4), dim3(256), 0, st,
-                                         items, nitems, cbegin, cblock, cpartner, S_ptr, S_rows,
-                                         S_cols, xh_off, xh, yh_off, yh, adjoint, nr));
+  // order[0, nheavy): one workgroup per item; the rest one wave per item
+  if (nheavy > 0)
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_coupling<NR, 4>), dim3(nheavy), dim3(256), 0, st,
+                                           items, nheavy, order, cbegin, cblock, cpartner, S_ptr,
+                                           S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint, nr));
+  const int32_t rest = nitems - nheavy;
+  if (rest > 0)
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_coupling<NR, 1>), dim3((rest + 3) / 4), dim3(256), 0,
+                                           st, items, rest, order + nheavy, cbegin, cblock,
+                                           cpartner, S_ptr, S_rows, S_cols, xh_off, xh, yh_off, yh,
+                                           adjoint, nr));
 }
 void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* fbegin, const int32_t* fitem, const int32_t* fsonidx,
@@ -2841,12 +3074,26 @@ void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
 }
 void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleaves,
                      const NearRefDev* nref, const NearDev* nears, const double2* nearv,
-                     const int64_t* yh_off, const double2* yh, const double2* xp, double2* yp,
-                     int adjoint, int nr, hipStream_t st) {
+                     const double2* nearT, const int64_t* yh_off, const double2* yh,
+                     const double2* xp, double2* yp, double2* partial, int adjoint, int nr,
+                     hipStream_t st) {
   if (nleaves == 0) return;
   DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_bwd_leaf<NR>, dim3(nleaves), dim3(256), 0, st, items,
-                                         leaves, nref, nears, nearv, yh_off, yh, xp, yp, adjoint,
-                                         nr));
+                                         leaves, nref, nears, nearv, nearT, yh_off, yh, xp, yp,
+                                         partial, adjoint, nr));
+}
+
+void launch_leaf_sum(const LeafDev* leaves, int32_t nleaves, const double2* partial, double2* yp,
+                     int nr, hipStream_t st) {
+  if (nleaves == 0) return;
+  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_leaf_sum<NR>, dim3(nleaves), dim3(64), 0, st, leaves,
+                                         partial, yp, nr));
+}
+
+void launch_near_transpose(const NearDev* nears, int64_t nblocks, const double2* B, double2* BT,
+                           hipStream_t st) {
+  if (nblocks == 0) return;
+  hipLaunchKernelGGL(k_near_transpose, dim3((unsigned)nblocks), dim3(256), 0, st, nears, B, BT);
 }
 void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
                    const double2* xp, int adjoint, double2* out, hipStream_t st) {

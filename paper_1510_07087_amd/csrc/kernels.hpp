@@ -28,7 +28,7 @@ void launch_gram_reduce(const ItemDev* items, const int32_t* litems, int32_t nl,
 // factorisations)
 void launch_ranks(const ItemDev* items, int32_t n, int32_t* out, hipStream_t st);
 void launch_factor(ItemDev* items, const int32_t* litems, int32_t nl, int32_t rmax, double eps,
-                   int max_sweeps, int32_t* status, hipStream_t st);
+                   int max_sweeps, int32_t* status, hipStream_t st, bool wide = false);
 // factors with r up to kMaxRBig, X of the q-th listed item at xptr[q]
 // (r (r + 1) complex elements)
 void launch_factor_big(ItemDev* items, const int32_t* litems, int32_t nl, double eps,
@@ -62,7 +62,6 @@ void launch_rprod_inner_big(bool mixed, const ItemDev* items, const UnitDev* uni
 void launch_expand(const ExpandDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_cvt(const CvtDev* tasks, int64_t ntasks, hipStream_t st);
 // one workgroup per task, 8-byte words
-void launch_copy_bytes(const CopyDev* tasks, int64_t ntasks, hipStream_t st);
 void launch_copy_c(const double2* src, int64_t src_off, double2* dst, int64_t dst_off,
                    int64_t count, hipStream_t st);
 void launch_project(bool mixed, const ProjDev* tasks, int64_t ntasks, const double* omega,
@@ -96,8 +95,11 @@ void launch_fwd_leaf(const ItemDev* items, const int32_t* litems, int32_t nl,
                      hipStream_t st);
 void launch_fwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* xh_off, double2* xh, int nr, hipStream_t st);
-void launch_coupling(const ItemDev* items, int32_t nitems, const int64_t* cbegin,
-                     const int32_t* cblock, const int32_t* cpartner, const double2* const* S_ptr,
+void launch_coupling_transpose(const double2* const* S, double2* const* ST, const int32_t* rows,
+                               const int32_t* cols, int64_t nblocks, hipStream_t st);
+void launch_coupling(const ItemDev* items, int32_t nitems, int32_t nheavy,
+                     const int32_t* order, const int64_t* cbegin, const int32_t* cblock,
+                     const int32_t* cpartner, const double2* const* S_ptr,
                      const int32_t* S_rows, const int32_t* S_cols, const int64_t* xh_off,
                      const double2* xh, const int64_t* yh_off, double2* yh, int adjoint, int nr,
                      hipStream_t st);
@@ -106,8 +108,13 @@ void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* yh_off, double2* yh, int nr, hipStream_t st);
 void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleaves,
                      const NearRefDev* nref, const NearDev* nears, const double2* nearv,
-                     const int64_t* yh_off, const double2* yh, const double2* xp, double2* yp,
-                     int adjoint, int nr, hipStream_t st);
+                     const double2* nearT, const int64_t* yh_off, const double2* yh,
+                     const double2* xp, double2* yp, double2* partial, int adjoint, int nr,
+                     hipStream_t st);
+void launch_leaf_sum(const LeafDev* leaves, int32_t nleaves, const double2* partial, double2* yp,
+                     int nr, hipStream_t st);
+void launch_near_transpose(const NearDev* nears, int64_t nblocks, const double2* B, double2* BT,
+                           hipStream_t st);
 void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
                    const double2* xp, int adjoint, double2* out, hipStream_t st);
 
