@@ -75,7 +75,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(dh2, torch, blocks, w, eps, leaf, form, steps, warmup, groups):
+def run_form(dh2, torch, blocks, w, eps, leaf, form, steps, warmup, groups, normals=None):
     prec = dh2.FP64 if form == "fp64" else dh2.MIXED
     o = dh2.opts(leaf_size=leaf, precision=prec, groups=groups)
     times, st, m = [], None, None
@@ -83,7 +83,10 @@ def run_form(dh2, torch, blocks, w, eps, leaf, form, steps, warmup, groups):
         m = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        m = dh2.compress_helmholtz(blocks, w, eps, o)
+        if normals is None:
+            m = dh2.compress_helmholtz(blocks, w, eps, o)
+        else:
+            m = dh2.compress_helmholtz_dlp(blocks, w, normals, eps, o)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = dh2.stats(m)
@@ -334,6 +337,10 @@ def main():
                     help="HBM bytes per launch of the roofline kernel from the counter runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter scale calibration)")
+    ap.add_argument("--source", choices=("slp", "dlp"), default="slp",
+                    help="slp (default): the single-layer matrix of the workload; dlp: the "
+                         "double-layer matrix on the same points (sphere and ellipsoid "
+                         "workloads), timed as a separate line")
     ap.add_argument("--mode", choices=("compress", "matvec"), default="compress",
                     help="compress (default): the compression step; matvec: y = G~x and "
                          "y = G~^*x with the compressed representation of the first form")
@@ -375,10 +382,18 @@ def main():
     if args.mode == "matvec":
         run_matvec(args, dh2, torch, synth, blocks, w, eps, leaf, kappa, n, forms[0])
         return
+    normals = None
+    if args.source == "dlp":
+        if args.workload.startswith("sphere"):
+            normals = synth.sphere_normals(p)
+        elif args.workload.startswith("ellip"):
+            normals = synth.ellipsoid_normals(n)
+        else:
+            raise SystemExit("--source dlp needs a sphere or ellipsoid workload")
     res = {}
     for form in forms:
         m, st, times = run_form(dh2, torch, blocks, w, eps, leaf, form, args.steps, args.warmup,
-                                args.groups)
+                                args.groups, normals)
         rows = np.random.default_rng(5).choice(n, 16, replace=False)
         x = torch.from_numpy(synth.complex_gaussian(n, 6)).to("cuda")
         _, _, rows_rel = dh2.rows_check(m, rows, x)
@@ -400,8 +415,13 @@ def main():
     nl = max(1, st["n_gram_leaf"])
     # counter figures of the committed profile of this workload and form
     # (empty when the kernels changed since they were taken)
-    fig = profile_figures(f"compress_{args.workload}_{head}")
-    if head == "mixed":
+    dlp = args.source == "dlp"
+    fig = {} if dlp else profile_figures(f"compress_{args.workload}_{head}")
+    if head == "mixed" and dlp:
+        kern = "k_gram_i8<2> (double-layer leaf Gram matrices, exact int8 slices on int8 MFMA)"
+        peak, unit, key = PEAK_INT8_MFMA, "TOP/s", "k_gram_i8_2"
+        extra = {"int8_ops_per_flop": st["ops_gram_leaf_i8"] / max(1.0, st["flops_gram_leaf"])}
+    elif head == "mixed":
         # dominant kernel: the int8-sliced leaf Gram (k_gram_i8<0>); its work is
         # the reduction's algorithmic 8 r^2 N real flops, against the peak of the
         # MFMA it runs on (int8); the emulation's own int8 operations per flop
@@ -448,6 +468,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "kappa": kappa, "leaf_size": leaf,
                    "eps": eps, "eta1": 20.0, "eta2": 5.0, "zeta": 2.0 / 3.0, "form": head,
+                   "matrix": "double layer" if dlp else "single layer",
                    "entries": "generated on the fly"},
         "roofline": {"bound": "mfma", "kernel": kern,
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
@@ -476,7 +497,7 @@ def main():
     }
     if "mixed" in res and "fp64" in res:
         out["speedup_mixed_vs_fp64"] = res["fp64"]["s"] / res["mixed"]["s"]
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not dlp:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget, st["k_max"], n)
     print(json.dumps(out), flush=True)
 

@@ -737,14 +737,17 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
           leaf_ids.push_back(i);
           sum_leafN += S.items[i].N;
         }
-      double4* colbuf = sum_leafN ? (double4*)mem.alloc(sum_leafN * sizeof(double4)) : nullptr;
+      // mixed double layer: positions and factors, then the N column normals
+      const int64_t cmul = mixed && M.src == SRC_DLP ? 2 : 1;
+      double4* colbuf =
+          sum_leafN ? (double4*)mem.alloc(cmul * sum_leafN * sizeof(double4)) : nullptr;
       {
         int64_t o = 0;
         for (int32_t i = lo; i < hi; ++i) {
           S.items[i].cols = nullptr;
           if (S.items[i].leaf && S.items[i].N > 0) {
             S.items[i].cols = colbuf + o;
-            o += S.items[i].N;
+            o += cmul * S.items[i].N;
           }
         }
       }
@@ -766,7 +769,8 @@ static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepS
       }
       copy_to(mem, S.d_items + lo, S.items.data() + lo, n, st);
       int32_t* d_leaf_ids = upload(mem, leaf_ids, st);
-      launch_leaf_cols(M.src, g, S.d_items, d_leaf_ids, (int32_t)leaf_ids.size(), S.d_ents, s, st);
+      launch_leaf_cols(M.src, g, S.d_items, d_leaf_ids, (int32_t)leaf_ids.size(), S.d_ents, s,
+                       mixed, st);
       launch_check("leaf columns");
       tr_.mark("arenas", s, b, lv);
       // Gram units: leaf items first, then non-leaf items

@@ -1525,11 +1525,14 @@ __device__ __forceinline__ void wave_sync() {
 // one workgroup per item walks its column-set entries.  Column j of the
 // weighted block row carries (x, y, z, factor): Helmholtz factor =
 // scale * (side 0 ? w_j : 1) / (4 pi), scale = 1 / (omega_b zeta^d); dense:
-// the original index in x and factor = scale.
+// the original index in x and factor = scale.  Double layer, mixed form
+// (pos_dlp): (x, y, z, factor) as for the single layer, followed after the
+// item's N columns by the unit normals (nx, ny, nz, 0); FP64 form: the
+// position in x and factor = scale.
 template <int SRC>
 __global__ __launch_bounds__(256) void k_leaf_cols(GeomDev g, const ItemDev* items,
                                                    const int32_t* litems, const EntDev* ents,
-                                                   int side) {
+                                                   int side, int pos_dlp) {
   const ItemDev& it = items[litems[blockIdx.x]];
   double4* out = it.cols;
   // the four waves take the column-set entries in turn, so that the loads
@@ -1540,9 +1543,13 @@ __global__ __launch_bounds__(256) void k_leaf_cols(GeomDev g, const ItemDev* ite
     for (int64_t q = lane; q < en.len; q += 64) {
       int64_t pos = en.pos + q;
       double4 v;
-      if constexpr (SRC == SRC_HELMHOLTZ) {
+      if (SRC == SRC_HELMHOLTZ || (SRC == SRC_DLP && pos_dlp)) {
         const double* p = g.pts + 4 * pos;
         v = make_double4(p[0], p[1], p[2], en.scale * (side == 0 ? p[3] : 1.0) * kInv4Pi);
+        if (SRC == SRC_DLP) {
+          const double* nv = g.nrm + 4 * pos;
+          out[it.N + en.col_start + q] = make_double4(nv[0], nv[1], nv[2], 0.0);
+        }
       } else {
         // dense: original index; double layer: position
         const int64_t id = SRC == SRC_DLP ? pos : g.perm[pos];
@@ -1585,7 +1592,16 @@ __device__ __forceinline__ RowData row_data(const GeomDev& g, const ItemDev& it,
   return r;
 }
 
-// entry of the weighted block row from staged row and column data
+// unit normal of row rho (double layer; 0 for padding rows)
+__device__ __forceinline__ double4 row_normal(const GeomDev& g, const ItemDev& it, int rho) {
+  double4 n = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (rho < it.m) {
+    const double* v = g.nrm + 4 * (it.row_off + rho);
+    n = make_double4(v[0], v[1], v[2], 0.0);
+  }
+  return n;
+}
+
 // Entry of the weighted block row from staged row and column data.  No
 // branch: padding rows and columns carry factor 0 (the distance is clamped so
 // that 0 * 1/r stays 0), which lets the compiler interleave several entries.
@@ -1637,6 +1653,32 @@ __device__ __forceinline__ float2 gen_entry_mx(const GeomDev& g, const RowData& 
   sincos_mixed(g.kappa * (r2 * ri), sn, cs);
   float a = (float)rw.f * (float)cc.w * (float)ri;
   return make_float2(a * cs, side == 0 ? a * sn : -a * sn);
+}
+
+// Mixed form, double layer: w_q (1 - i kappa r) exp(i kappa r) <x_p - x_q,
+// n_q> / (4 pi r^3) with q the column point (side 0) or the row point (side
+// 1, conjugated); the distance, <x_p - x_q, n_q> and the phase reduction in
+// FP64, sin, cos and the amplitude in FP32.  rn, cn: the row's and the
+// column's unit normals.  Padding rows and columns have factor and normal 0
+// and sit far apart, so the entry is 0 without a clamp.
+__device__ __forceinline__ float2 gen_entry_dlp_mx(const GeomDev& g, const RowData& rw,
+                                                   double4 rn, double4 cc, double4 cn,
+                                                   int side) {
+  double dx = rw.x - cc.x, dy = rw.y - cc.y, dz = rw.z - cc.z;
+  double r2 = dx * dx + dy * dy + dz * dz;
+  double r0 = __builtin_amdgcn_rsq(r2);
+  double e = fma(-r2 * r0, r0, 1.0);
+  double ri = fma(0.5 * r0, e, r0);
+  double kr = g.kappa * (r2 * ri);
+  // <x_p - x_q, n_q>: side 0 (row point p, column point q) or side 1 (row q)
+  double dot = side == 0 ? dx * cn.x + dy * cn.y + dz * cn.z
+                         : -(dx * rn.x + dy * rn.y + dz * rn.z);
+  float sn, cs;
+  sincos_mixed(kr, sn, cs);
+  float a = (float)(rw.f * cc.w * dot * (ri * ri * ri));
+  float k = (float)kr;
+  float re = a * fmaf(k, sn, cs), im = a * fmaf(-k, cs, sn);
+  return make_float2(re, side == 0 ? im : -im);
 }
 
 // Gram of a leaf block row, one unit per wave, all lower tile pairs.  The
@@ -2135,7 +2177,9 @@ __global__ __launch_bounds__(256) void k_pack_q(const ItemDev* items, const int3
 template <int SRC, bool MX, int KT>
 __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDev* ents, int side,
                                 const UnitDev& u, const ROp<MX>* Qs, const RowData* rows,
-                                unsigned* s_rmax) {
+                                const double4* rown, unsigned* s_rmax) {
+  // mixed form with generated entries: register-staged FP32 generators
+  constexpr bool kGen = MX && (SRC == SRC_HELMHOLTZ || SRC == SRC_DLP);
   int w = wave_id(), lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
   int r = it.r, k = it.k;
   int nks = (r + 3) / 4;
@@ -2143,16 +2187,25 @@ __device__ void rprod_leaf_wave(const GeomDev& g, const ItemDev& it, const EntDe
   const double4* const cols = it.cols;
   for (int64_t j0 = 16 * w; j0 < u.ncols; j0 += 64) {
     int64_t j = u.col_begin + j0 + row;
-    double4 cc = MX && SRC == SRC_HELMHOLTZ ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0);
-    if (j0 + row < u.ncols) cc = ldg(cols, j);
+    double4 cc = kGen ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0);
+    double4 cn = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (j0 + row < u.ncols) {
+      cc = ldg(cols, j);
+      if constexpr (kGen && SRC == SRC_DLP) cn = ldg(cols, it.N + j);
+    }
     RAcc<MX> acc[KT];
-    if constexpr (MX && SRC == SRC_HELMHOLTZ) {
+    if constexpr (kGen) {
       // the lane's entries of all k-steps first (independent chains), then
       // the MFMAs (leaf block rows have at most 64 rows: 16 k-steps)
       float2 e[16];
 #pragma unroll
       for (int ks = 0; ks < 16; ++ks)
-        if (ks < nks) e[ks] = gen_entry_mx(g, rows[4 * ks + kq], cc, side);
+        if (ks < nks) {
+          if constexpr (SRC == SRC_HELMHOLTZ)
+            e[ks] = gen_entry_mx(g, rows[4 * ks + kq], cc, side);
+          else
+            e[ks] = gen_entry_dlp_mx(g, rows[4 * ks + kq], rown[4 * ks + kq], cc, cn, side);
+        }
 #pragma unroll
       for (int ks = 0; ks < 16; ++ks) {
         if (ks < nks) {
@@ -2196,6 +2249,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX ? 4 : 1)
                                                       int side) {
   __shared__ ROp<MX> Qs[68 * 64];   // (r + 4) x (16 KT), zero padded rows past r
   __shared__ RowData rows[64 + 8];
+  // mixed double layer: the rows' unit normals
+  constexpr bool kDlpMx = MX && SRC == SRC_DLP;
+  __shared__ double4 rown[kDlpMx ? 64 + 8 : 1];
   __shared__ unsigned s_rmax[64];
   const UnitDev u = units[blockIdx.x];
   const ItemDev& it = items[u.item];
@@ -2207,14 +2263,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MX ? 4 : 1)
     int i = e / ldq, kk = e - i * ldq;
     Qs[e] = rop<MX>((i < r && kk < k) ? it.Q[(int64_t)i * k + kk] : make_double2(0.0, 0.0));
   }
-  for (int i = threadIdx.x; i < 72; i += 256) rows[i] = row_data<SRC>(g, it, i, side, MX);
+  for (int i = threadIdx.x; i < 72; i += 256) {
+    // the mixed double layer stages positions like the single layer
+    rows[i] = row_data<kDlpMx ? SRC_HELMHOLTZ : SRC>(g, it, i, side, MX);
+    if constexpr (kDlpMx) rown[i] = row_normal(g, it, i);
+  }
   for (int kk = threadIdx.x; kk < 64; kk += 256) s_rmax[kk] = 0u;
   __syncthreads();
   switch (kt) {
-    case 1: rprod_leaf_wave<SRC, MX, 1>(g, it, ents, side, u, Qs, rows, s_rmax); break;
-    case 2: rprod_leaf_wave<SRC, MX, 2>(g, it, ents, side, u, Qs, rows, s_rmax); break;
-    case 3: rprod_leaf_wave<SRC, MX, 3>(g, it, ents, side, u, Qs, rows, s_rmax); break;
-    default: rprod_leaf_wave<SRC, MX, 4>(g, it, ents, side, u, Qs, rows, s_rmax); break;
+    case 1: rprod_leaf_wave<SRC, MX, 1>(g, it, ents, side, u, Qs, rows, rown, s_rmax); break;
+    case 2: rprod_leaf_wave<SRC, MX, 2>(g, it, ents, side, u, Qs, rows, rown, s_rmax); break;
+    case 3: rprod_leaf_wave<SRC, MX, 3>(g, it, ents, side, u, Qs, rows, rown, s_rmax); break;
+    default: rprod_leaf_wave<SRC, MX, 4>(g, it, ents, side, u, Qs, rows, rown, s_rmax); break;
   }
   if constexpr (MX) {
     __syncthreads();
@@ -2250,8 +2310,8 @@ constexpr int kI8Waves = kI8Threads / 64;
 constexpr int kI8ProdPerWave = 3;                     // 40 real tile products over 16 waves
 constexpr int kI8Slab = 1024;                         // one slice of one tile: 16 rows x 64 B
 constexpr int kI8Buf = kI8Tiles * 2 * 4 * kI8Slab;    // tiles x components x slices
-constexpr size_t kI8Lds = 2 * (size_t)kI8Buf + 3 * 64 * sizeof(double4) +
-                          kI8Tiles * 16 * (sizeof(RowData) + 2 * sizeof(int));
+constexpr size_t kI8Lds = 2 * (size_t)kI8Buf + 6 * 64 * sizeof(double4) +
+                          kI8Tiles * 16 * (sizeof(RowData) + sizeof(double4) + 2 * sizeof(int));
 
 __device__ __forceinline__ int i8_off(int T, int comp, int p, int g, int i) {
   return ((((T * 2 + comp) * 4 + p) * 4 + g) * 16 + i) * 16;
@@ -2292,8 +2352,10 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
   extern __shared__ __align__(16) char lds[];
   char* slices = lds;
   double4* cold = reinterpret_cast<double4*>(lds + 2 * kI8Buf);  // 3 x 64 columns
-  RowData* rowd = reinterpret_cast<RowData*>(cold + 3 * 64);
-  int* rexp = reinterpret_cast<int*>(rowd + kI8Tiles * 16);
+  double4* coldn = cold + 3 * 64;  // double layer: their normals
+  RowData* rowd = reinterpret_cast<RowData*>(coldn + 3 * 64);
+  double4* rown = reinterpret_cast<double4*>(rowd + kI8Tiles * 16);  // double layer: row normals
+  int* rexp = reinterpret_cast<int*>(rown + kI8Tiles * 16);
   unsigned* rmaxb = reinterpret_cast<unsigned*>(rexp + kI8Tiles * 16);
 
   const UnitDev u = units[blockIdx.x];
@@ -2312,18 +2374,23 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
   // ---- row data and row bounds ----
   for (int e = tid; e < ntile * 16; e += kI8Threads) {
     rmaxb[e] = 0u;
-    if constexpr (KIND != 1)
-      rowd[e] = row_data<KIND == 2 ? SRC_DLP : SRC_HELMHOLTZ>(g, it, row0(e >> 4) + (e & 15), side,
-                                                             true);
+    if constexpr (KIND != 1) {
+      // positions and row factors (the double layer's too), padding far away
+      rowd[e] = row_data<SRC_HELMHOLTZ>(g, it, row0(e >> 4) + (e & 15), side, true);
+      if constexpr (KIND == 2) rown[e] = row_normal(g, it, row0(e >> 4) + (e & 15));
+    }
   }
   auto stage_cols = [&](int c, int buf) {
     if constexpr (KIND != 1) {
       if (tid < 64) {
         int64_t j = (int64_t)c * 64 + tid;
-        // double layer: the column data hold positions, padding reads point 0
-        double4 v = KIND == 0 ? pad_col() : make_double4(0.0, 0.0, 0.0, 0.0);
-        if (c < nch && j < ncols) v = ldg(it.cols, u.col_begin + j);
+        double4 v = pad_col(), vn = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (c < nch && j < ncols) {
+          v = ldg(it.cols, u.col_begin + j);
+          if constexpr (KIND == 2) vn = ldg(it.cols, it.N + u.col_begin + j);
+        }
         cold[buf * 64 + tid] = v;
+        if constexpr (KIND == 2) coldn[buf * 64 + tid] = vn;
       }
     }
   };
@@ -2337,13 +2404,15 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
     if (tid < stride * nrow) {
       const int rl = tid % nrow;
       const RowData rw = rowd[rl];
-      double mx = 0.0;
+      const double4 rn = rown[rl];
+      float mx = 0.0f;
       if (rw.f != 0.0)
         for (int64_t j = tid / nrow; j < ncols; j += stride) {
-          const double2 v = gen_entry<SRC_DLP, false>(g, rw, it.cols[u.col_begin + j], side);
-          mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+          const float2 v = gen_entry_dlp_mx(g, rw, rn, ldg(it.cols, u.col_begin + j),
+                                            ldg(it.cols, it.N + u.col_begin + j), side);
+          mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
         }
-      if (mx > 0.0) atomicMax(&rmaxb[rl], __float_as_uint((float)mx));
+      if (mx > 0.0f) atomicMax(&rmaxb[rl], __float_as_uint(mx));
     }
   } else if constexpr (KIND == 0) {
     // leaf rows: |entry| <= |f_i| scale_e wfac_e / (4 pi dist(x_i, box of s_e)) over
@@ -2470,8 +2539,8 @@ __global__ __launch_bounds__(kI8Threads) void k_gram_i8(GeomDev g, const ItemDev
             if constexpr (KIND == 0) {
               v = gen_entry_mx(g, rw, cc[q], side);
             } else {
-              const double2 d = gen_entry<SRC_DLP, false>(g, rw, cc[q], side);
-              v = make_float2((float)d.x, (float)d.y);
+              v = gen_entry_dlp_mx(g, rw, rown[T * 16 + i], cc[q],
+                                   coldn[(c % 3) * 64 + 16 * gg + 4 * pp + q], side);
             }
             vr[q] = v.x;
             vi[q] = v.y;
@@ -2723,17 +2792,17 @@ void launch_factor_big(ItemDev* items, const int32_t* litems, int32_t nl, double
 }
 
 void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int32_t* litems,
-                      int32_t nl, const EntDev* ents, int side, hipStream_t st) {
+                      int32_t nl, const EntDev* ents, int side, bool mixed, hipStream_t st) {
   if (nl == 0) return;
   if (src == SRC_HELMHOLTZ)
     hipLaunchKernelGGL(k_leaf_cols<SRC_HELMHOLTZ>, dim3(nl), dim3(256), 0, st, g, items, litems,
-                       ents, side);
+                       ents, side, 0);
   else if (src == SRC_DLP)
     hipLaunchKernelGGL(k_leaf_cols<SRC_DLP>, dim3(nl), dim3(256), 0, st, g, items, litems, ents,
-                       side);
+                       side, mixed ? 1 : 0);
   else
     hipLaunchKernelGGL(k_leaf_cols<SRC_DENSE>, dim3(nl), dim3(256), 0, st, g, items, litems, ents,
-                       side);
+                       side, 0);
 }
 
 void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,

@@ -35,7 +35,7 @@ void launch_factor_big(ItemDev* items, const int32_t* litems, int32_t nl, double
                        int max_sweeps, int32_t* status, double2* const* xptr, hipStream_t st);
 // Column data (x, y, z, factor) of the listed leaf items into their it.cols.
 void launch_leaf_cols(int src, const GeomDev& g, const ItemDev* items, const int32_t* litems,
-                      int32_t nl, const EntDev* ents, int side, hipStream_t st);
+                      int32_t nl, const EntDev* ents, int side, bool mixed, hipStream_t st);
 // Mixed form: Gram units of one workgroup each on int8 MFMA (leaf block rows
 // generated, non-leaf block rows from the sons' FP32 R).
 void launch_gram_i8(bool inner, const GeomDev& g, const ItemDev* items, const EntDev* ents,

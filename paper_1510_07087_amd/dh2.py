@@ -267,7 +267,7 @@ def compress_helmholtz(b: Blocks, w, eps: float, o: Opts, stream=None) -> Matrix
 
 def compress_helmholtz_dlp(b: Blocks, w, normals, eps: float, o: Opts, stream=None) -> Matrix:
     """Double-layer operator generated from points, weights and unit normals
-    (n x 3, original order); FP64 form."""
+    (n x 3, original order); either form (o.precision)."""
     wa = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
     na = np.ascontiguousarray(normals, dtype=np.float64)
     h = C.c_void_p()
