@@ -1519,7 +1519,7 @@ static std::shared_ptr<const SweepSizes> sweep_sizes(const BlocksData& B) {
 
 std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, const void* G,
                                      int64_t ld, const double* w, double eps, const dh2_opts& o,
-                                     hipStream_t st, const double* nrm) {
+                                     hipStream_t st, const double* nrm, bool concurrent) {
   auto Mp = std::make_unique<MatrixData>();
   MatrixData& M = *Mp;
   M.blk = blk;
@@ -1625,7 +1625,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   // cap is set (then one after the other, so that the cap stays exact).
   // Running together they hold the R matrices of both sides: the batch
   // count leaves room for that.
-  M.concurrent = o.max_device_bytes == 0;
+  M.concurrent = concurrent && o.max_device_bytes == 0;
   const double need = M.concurrent ? 2.0 * peak : peak;
   int32_t nb = o.groups > 0 ? o.groups : (int32_t)std::ceil(need / std::max(1.0, budget));
   nb = std::max(1, std::min(nb, std::max(1, ngroups)));
@@ -1899,6 +1899,10 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
 // (default priority), take instances in turn; concurrent kernels of several
 // instances fill the device where one small instance would not.  All work
 // is ordered after the caller's stream and complete on return.
+// instances of a batch run their two sweeps one after the other: the
+// instances on several streams already fill the device
+constexpr bool kBatchConcurrent = false;
+
 std::vector<std::unique_ptr<MatrixData>> compress_batch(
     const std::vector<std::shared_ptr<BlocksData>>& blks, const std::vector<const double*>& w,
     double eps, const dh2_opts& o, hipStream_t st, int nstreams) {
@@ -1927,7 +1931,8 @@ std::vector<std::unique_ptr<MatrixData>> compress_batch(
       for (;;) {
         int i = next.fetch_add(1);
         if (i >= n || failed.load()) break;
-        out[i] = compress(blks[i], SRC_HELMHOLTZ, nullptr, 0, w[i], eps, o, s);
+        out[i] = compress(blks[i], SRC_HELMHOLTZ, nullptr, 0, w[i], eps, o, s, nullptr,
+                          kBatchConcurrent);
       }
     } catch (const Error& e) {
       record(e.code, e.msg);

@@ -180,10 +180,12 @@ struct MatrixData {
 
 std::shared_ptr<TreeData> make_tree(const double* pts, int64_t n, double kappa, const dh2_opts& o);
 std::shared_ptr<BlocksData> make_blocks(std::shared_ptr<TreeData> t, const dh2_opts& o);
-// nrm: host n x 3 unit normals in the original order (SRC_DLP only)
+// nrm: host n x 3 unit normals in the original order (SRC_DLP only);
+// concurrent: the two sweeps may run at once (without a memory cap)
 std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> b, int src, const void* G,
                                      int64_t ld, const double* w, double eps, const dh2_opts& o,
-                                     hipStream_t st, const double* nrm = nullptr);
+                                     hipStream_t st, const double* nrm = nullptr,
+                                     bool concurrent = true);
 std::vector<std::unique_ptr<MatrixData>> compress_batch(
     const std::vector<std::shared_ptr<BlocksData>>& blks, const std::vector<const double*>& w,
     double eps, const dh2_opts& o, hipStream_t st, int nstreams);
