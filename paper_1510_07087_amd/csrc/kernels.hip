@@ -1283,16 +1283,17 @@ __global__ __launch_bounds__(128) void k_fwd_inner(const ItemDev* items, const i
 // the adjoint, where S_b is kr x kc with the item on the column side).  The
 // matrices come oriented with the item's coefficients as rows: S_b for op
 // N, the transposed copy S_b^T (kc x kr, column-major) for the adjoint, so
-// that both read consecutive rows across the lanes.  WPI waves per item
-// (1, or 4 for the items with the most blocks), items taken in the order
-// given (most work first): each wave is cut into 64 / kp slots of kp lanes
-// (kp the power of two >= k, at least 8), lane kk of a slot one coefficient;
-// the slots of the item's waves take its blocks in turn, and their sums are
-// added with shuffles, then across the waves through LDS, in a fixed order.
-// The partner's coefficients are the same for all lanes of a slot.
-template <int NR, int WPI>
+// that both read consecutive rows across the lanes.  Items are taken in the
+// order given (most work first): the first nheavy workgroups take one item
+// each with their four waves, the others four items, one per wave.  Each
+// wave is cut into 64 / kp slots of kp lanes (kp the power of two >= k, at
+// least 8), lane kk of a slot one coefficient; the slots of the item's waves
+// take its blocks in turn, and their sums are added with shuffles, then
+// across the waves through LDS, in a fixed order.  The partner's
+// coefficients are the same for all lanes of a slot.
+template <int NR>
 __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t nitems,
-                                                  const int32_t* order,
+                                                  int32_t nheavy, const int32_t* order,
                                                   const int64_t* cbegin, const int32_t* cblock,
                                                   const int32_t* cpartner,
                                                   const double2* const* S_ptr,
@@ -1300,16 +1301,18 @@ __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t 
                                                   const int64_t* xh_off, const double2* xh,
                                                   const int64_t* yh_off, double2* yh,
                                                   int adjoint, int nr) {
-  __shared__ double2 part[WPI > 1 ? WPI : 1][NR][64];
+  __shared__ double2 part[4][NR][64];
   const int w = wave_id();
-  const int32_t wi = WPI > 1 ? (int32_t)blockIdx.x : (int32_t)blockIdx.x * 4 + w;
-  if (wi >= nitems) return;
+  const bool heavy = (int32_t)blockIdx.x < nheavy;  // the same for the whole workgroup
+  const int32_t wi = heavy ? (int32_t)blockIdx.x
+                           : nheavy + ((int32_t)blockIdx.x - nheavy) * 4 + w;
+  if (wi >= nitems) return;  // light workgroups only: heavy ones have an item
   const int32_t i = order[wi];
   const int lane = threadIdx.x & 63;
   const int k = items[i].k;
   const int kp = k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 32 ? 32 : 64));
   const int nslot = 64 / kp, sl = lane / kp, kl = lane % kp;
-  const int first = (WPI > 1 ? w * nslot : 0) + sl, stride = WPI * nslot;
+  const int first = (heavy ? w * nslot : 0) + sl, stride = (heavy ? 4 : 1) * nslot;
   for (int kk0 = 0; kk0 < k; kk0 += 64) {
     const int kk = min(kk0 + kl, k - 1);
     double2 s[NR];
@@ -1329,7 +1332,7 @@ __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t 
         s[q].x += __shfl_xor(s[q].x, o, 64);
         s[q].y += __shfl_xor(s[q].y, o, 64);
       }
-    if constexpr (WPI > 1) {
+    if (heavy) {
 #pragma unroll
       for (int q = 0; q < NR; ++q) part[w][q][lane] = s[q];
       __syncthreads();
@@ -1337,14 +1340,14 @@ __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t 
 #pragma unroll
         for (int q = 0; q < NR; ++q)
 #pragma unroll
-          for (int u = 1; u < WPI; ++u) {
+          for (int u = 1; u < 4; ++u) {
             s[q].x += part[u][q][lane].x;
             s[q].y += part[u][q][lane].y;
           }
       }
       __syncthreads();
     }
-    if ((WPI == 1 || w == 0) && sl == 0 && kk0 + kl < k)
+    if ((!heavy || w == 0) && sl == 0 && kk0 + kl < k)
 #pragma unroll
       for (int q = 0; q < NR; ++q)
         if (q < nr) yh[(yh_off[i] + kk0 + kl) * nr + q] = s[q];
@@ -3122,17 +3125,11 @@ void launch_coupling(const ItemDev* items, int32_t nitems, int32_t nheavy,
                      const double2* xh, const int64_t* yh_off, double2* yh, int adjoint, int nr,
                      hipStream_t st) {
   if (nitems == 0) return;
-  // order[0, nheavy): one workgroup per item; the rest one wave per item
-  if (nheavy > 0)
-    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_coupling<NR, 4>), dim3(nheavy), dim3(256), 0, st,
-                                           items, nheavy, order, cbegin, cblock, cpartner, S_ptr,
-                                           S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint, nr));
-  const int32_t rest = nitems - nheavy;
-  if (rest > 0)
-    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_coupling<NR, 1>), dim3((rest + 3) / 4), dim3(256), 0,
-                                           st, items, rest, order + nheavy, cbegin, cblock,
-                                           cpartner, S_ptr, S_rows, S_cols, xh_off, xh, yh_off, yh,
-                                           adjoint, nr));
+  // one launch: workgroups [0, nheavy) one item each, then four items each
+  const int32_t nwg = nheavy + (nitems - nheavy + 3) / 4;
+  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_coupling<NR>, dim3(nwg), dim3(256), 0, st, items,
+                                         nitems, nheavy, order, cbegin, cblock, cpartner, S_ptr,
+                                         S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint, nr));
 }
 void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* fbegin, const int32_t* fitem, const int32_t* fsonidx,
