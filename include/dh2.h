@@ -253,7 +253,14 @@ void dh2_release_cached_memory(void);
  * transformation, coupling, backward transformation, near field).
  *   op   : 'N' for y = G~ x, 'C' for y = G~^* x.
  *   x, y : device, n x nrhs complex128, column-major (ld = n), ORIGINAL order.
- *          y is overwritten.                                                */
+ *          y is overwritten.
+ * The near-field rows run on a second stream that the matrix owns, forked
+ * from and joined back into `stream` with events, so that y is complete
+ * when `stream` reaches this point.  The first call on a matrix builds the
+ * product's index lists and transposed copies of the near field and of the
+ * coupling matrices (for the adjoint; about as much memory again as those
+ * parts of the representation).  Products on one matrix share its work
+ * vectors: calls from several host threads must be serialised.          */
 dh2_status dh2_matvec(dh2_matrix m, char op, int64_t nrhs, const void* x,
                       void* y, void* stream);
 
@@ -270,7 +277,7 @@ dh2_status dh2_matvec(dh2_matrix m, char op, int64_t nrhs, const void* x,
  *     points at the benchmark's ranks).
  *   - The product's index lists are built by the first dh2_matvec on the
  *     matrix; before that this call returns DH2_EINVAL.
- *   - The work is only enqueued on `stream` (no wait); y is complete when the
+ *   - The work is only enqueued (no wait), as for dh2_matvec; y is complete when the
  *     stream reaches this point.  Calls that overlap on one device share the
  *     array and race: serialise them on one stream.                        */
 dh2_status dh2_matvec_noalloc(dh2_matrix m, char op, int64_t nrhs, const void* x,

@@ -407,6 +407,9 @@ struct SideMV {
   LeafDev* d_split = nullptr;
   int32_t nsplit = 0;
   int32_t nslots = 0;
+  // basis terms of every leaf (added to the near-field rows afterwards)
+  LeafDev* d_basis = nullptr;
+  int32_t nbasis = 0;
 };
 
 struct MatvecPlan {
@@ -424,6 +427,17 @@ struct MatvecPlan {
   int64_t maxh = 0;       // coefficients of the larger side
   int32_t maxslots = 0;   // partial slots of the larger side
   double2* d_nearT = nullptr;  // near-field blocks transposed (#s x #t column-major)
+  // the near-field rows run on a second stream beside the basis chain
+  hipStream_t side = nullptr;
+  hipEvent_t ev_x = nullptr, ev_near = nullptr;
+  ~MatvecPlan() {
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    if (ev_x) (void)hipEventDestroy(ev_x);
+    if (ev_near) (void)hipEventDestroy(ev_near);
+  }
 };
 
 // right-hand sides per pass of the matrix-vector product kernels
@@ -2097,7 +2111,7 @@ static void build_mv(MatrixData& M, hipStream_t st) {
       task_entries = std::max<int64_t>(2048, 2 * tot / std::max<int64_t>(1, nlf));
     }
     std::vector<std::pair<int64_t, LeafDev>> tasks;
-    std::vector<LeafDev> split;
+    std::vector<LeafDev> split, basis;
     int32_t slots = 0;
     for (int32_t t = 0; t < tr.nc(); ++t) {
       if (!tr.leaf(t)) continue;
@@ -2112,6 +2126,14 @@ static void build_mv(MatrixData& M, hipStream_t st) {
       for (int32_t q = 1; q < cnt; ++q)
         if (S.P->ext2int[B.cs[s].first[t] + q] != L.item_first + q) fail(DH2_EDEVICE, "internal: leaf items not contiguous");
       L.slot = -1;
+      // the basis terms go into a task list of their own; the near-field
+      // tasks carry none
+      {
+        LeafDev Bt = L;
+        Bt.near_begin = Bt.near_end = 0;
+        basis.push_back(Bt);
+      }
+      L.item_count = 0;
       const int64_t r0 = (int64_t)refs.size();
       int64_t total = 0;
       std::vector<int64_t> wref;
@@ -2136,7 +2158,6 @@ static void build_mv(MatrixData& M, hipStream_t st) {
       int64_t q = r0;
       for (int64_t part = 0; q < r1; ++part) {
         LeafDev T = L;
-        if (part > 0) T.item_count = 0;  // basis terms in the first task only
         T.slot = slots++;
         T.near_begin = q;
         int64_t wsum = 0;
@@ -2155,6 +2176,8 @@ static void build_mv(MatrixData& M, hipStream_t st) {
     V.nleaves = (int32_t)leaves.size();
     V.d_split = split.empty() ? nullptr : upload(mem, split, st);
     V.nsplit = (int32_t)split.size();
+    V.d_basis = upload(mem, basis, st);
+    V.nbasis = (int32_t)basis.size();
     V.nslots = slots;
     P->maxslots = std::max(P->maxslots, slots);
   }
@@ -2165,6 +2188,9 @@ static void build_mv(MatrixData& M, hipStream_t st) {
     P->d_nearT = (double2*)mem.alloc(std::max<int64_t>(1, tot) * sizeof(double2));
   }
   P->d_nears = upload(mem, M.nears, st);
+  hip_check(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "stream create");
+  hip_check(hipEventCreateWithFlags(&P->ev_x, hipEventDisableTiming), "event");
+  hip_check(hipEventCreateWithFlags(&P->ev_near, hipEventDisableTiming), "event");
   launch_near_transpose(P->d_nears, (int64_t)M.nears.size(), M.d_near, P->d_nearT, st);
   launch_check("near-field transpose");
   std::vector<double2*> sp(M.S_ptr.begin(), M.S_ptr.end());
@@ -2212,6 +2238,14 @@ static void matvec_core(MatrixData& M, char op, int nr, const double2* x, double
   SideMV& VA = P.s[src_side];
   SideMV& VB = P.s[dst_side];
   launch_gather_perm(x, M.d_perm, n, w.xp, st, nr);
+  // the near-field rows (about half of the representation's bytes) on the
+  // second stream, beside the chain of small basis kernels
+  hip_check(hipEventRecord(P.ev_x, st), "event record");
+  hip_check(hipStreamWaitEvent(P.side, P.ev_x, 0), "stream wait");
+  launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near,
+                  P.d_nearT, VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 0, P.side);
+  launch_leaf_sum(VB.d_split, VB.nsplit, w.part, w.yp, nr, P.side);
+  hip_check(hipEventRecord(P.ev_near, P.side), "event record");
   launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, w.xp, w.xh, nr, st);
   for (size_t q = 0; q < VA.d_fwd_lvl.size(); ++q)
     launch_fwd_inner(A.d_items, VA.d_fwd_lvl[q], VA.fwd_count[q], VA.d_hoff, w.xh, nr, st);
@@ -2223,9 +2257,10 @@ static void matvec_core(MatrixData& M, char op, int nr, const double2* x, double
   for (size_t l = 0; l < VB.d_bl_items.size(); ++l)
     launch_bwd_inner(Bs.d_items, VB.d_bl_items[l], VB.bl_count[l], VB.d_bl_fbegin[l],
                      VB.d_bl_fitem[l], VB.d_bl_fson[l], VB.d_hoff, w.yh, nr, st);
-  launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near,
-                  P.d_nearT, VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, st);
-  launch_leaf_sum(VB.d_split, VB.nsplit, w.part, w.yp, nr, st);
+  // basis terms added to the near-field rows
+  hip_check(hipStreamWaitEvent(st, P.ev_near, 0), "stream wait");
+  launch_bwd_leaf(Bs.d_items, VB.d_basis, VB.nbasis, VB.d_nref, P.d_nears, M.d_near, P.d_nearT,
+                  VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 1, st);
   launch_scatter_perm(w.yp, M.d_perm, n, y, st, nr);
   launch_check("matvec");
 }

@@ -1381,7 +1381,8 @@ __global__ __launch_bounds__(128) void k_bwd_inner(const ItemDev* items, const i
 }
 
 // leaf rows: y|L = sum_c Q_Lc yh_Lc + near-field rows of L.  One workgroup
-// of four waves per task (a leaf, or a part of a leaf's near-field blocks),
+// of four waves per task (the basis terms of a leaf, added to the rows
+// already written (accumulate), or a leaf's near-field blocks, or a part of them),
 // lane j one row of the leaf (leaves have at most 64 rows): the waves take
 // the task's basis terms and near-field blocks in turn, and the partial sums
 // are added through LDS in wave order.  The adjoint reads the transposed
@@ -1393,7 +1394,8 @@ __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const Le
                                                   const double2* nearv, const double2* nearT,
                                                   const int64_t* yh_off, const double2* yh,
                                                   const double2* xp, double2* yp,
-                                                  double2* partial, int adjoint, int nr) {
+                                                  double2* partial, int adjoint, int nr,
+                                                  int accumulate) {
   __shared__ double2 part[4][NR][64];
   const LeafDev L = leaves[blockIdx.x];
   const int w = wave_id(), lane = threadIdx.x & 63;
@@ -1430,6 +1432,11 @@ __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const Le
         for (int u = 1; u < 4; ++u) {
           t.x += part[u][q][lane].x;
           t.y += part[u][q][lane].y;
+        }
+        if (accumulate) {
+          const double2 o = out[q];
+          t.x += o.x;
+          t.y += o.y;
         }
         out[q] = t;
       }
@@ -3142,11 +3149,11 @@ void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleave
                      const NearRefDev* nref, const NearDev* nears, const double2* nearv,
                      const double2* nearT, const int64_t* yh_off, const double2* yh,
                      const double2* xp, double2* yp, double2* partial, int adjoint, int nr,
-                     hipStream_t st) {
+                     int accumulate, hipStream_t st) {
   if (nleaves == 0) return;
   DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_bwd_leaf<NR>, dim3(nleaves), dim3(256), 0, st, items,
                                          leaves, nref, nears, nearv, nearT, yh_off, yh, xp, yp,
-                                         partial, adjoint, nr));
+                                         partial, adjoint, nr, accumulate));
 }
 
 void launch_leaf_sum(const LeafDev* leaves, int32_t nleaves, const double2* partial, double2* yp,
