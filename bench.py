@@ -303,6 +303,10 @@ def run_matvec(args, dh2, torch, synth, blocks, w, eps, leaf, kappa, n, form):
                 f"({ms[(op, nrhs)] / nrhs:.3f} ms per right-hand side, wall {wall:.3f} ms), "
                 f"representation {rep_bytes / 1e9:.2f} GB")
     ach = rep_bytes / (ms[("N", 1)] * 1e-3) / 1e9
+    # counter bytes of one pass from the committed profile of this workload
+    # (none when the kernel sources changed since the counters were taken)
+    fig = profile_figures(f"matvec_{args.workload}")
+    traffic = float(fig["matvec_hbm_bytes_per_pass_nrhs1"]) if fig else None
     out = {
         "metric": "matvec ms, y = G~x with the compressed representation, n=%d kappa=%g" % (n, kappa),
         "value": ms[("N", 1)], "unit": "ms", "n_gpus": 1, "steps": args.steps,
@@ -312,7 +316,8 @@ def run_matvec(args, dh2, torch, synth, blocks, w, eps, leaf, kappa, n, form):
                    "eps": eps, "form": form, "nrhs": 1},
         "roofline": {"bound": "hbm", "kernel": "matvec (representation read once per pass)",
                      "achieved": ach, "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
-                     "traffic": None},
+                     "traffic": traffic,
+                     **({"profile": f"profiles/matvec_{args.workload}.md"} if fig else {})},
         "adjoint_ms": ms[("C", 1)],
         "nrhs8_ms_per_rhs": {"N": ms[("N", 8)] / 8, "C": ms[("C", 8)] / 8},
         "representation_bytes": rep_bytes,
