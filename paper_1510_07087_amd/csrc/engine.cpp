@@ -1476,23 +1476,61 @@ static void project_all(MatrixData& M, hipStream_t st, DevMem& mem, SweepStats& 
   tr_.mark("proj upload", 0, -1, -1);
   PhaseTimer tp(st);
   tp.start();
+  // The launches (one per class) are independent: they are spread over
+  // kPrjStreams streams (the caller's and three more, default priority),
+  // each class to the stream with the least work so far, so that the tails
+  // of small launches overlap; the streams join the caller's at the end.
+  constexpr int kPrjStreams = 4;
+  struct Fork {
+    hipStream_t s[kPrjStreams] = {};
+    hipEvent_t e[kPrjStreams] = {};
+    ~Fork() {
+      for (int q = 1; q < kPrjStreams; ++q)
+        if (s[q]) (void)hipStreamDestroy(s[q]);
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } fk;
+  fk.s[0] = st;
+  for (int q = 0; q < kPrjStreams; ++q)
+    hip_check(hipEventCreateWithFlags(&fk.e[q], hipEventDisableTiming), "event");
+  hip_check(hipEventRecord(fk.e[0], st), "event record");
+  for (int q = 1; q < kPrjStreams; ++q) {
+    hip_check(hipStreamCreateWithFlags(&fk.s[q], hipStreamNonBlocking), "stream create");
+    hip_check(hipStreamWaitEvent(fk.s[q], fk.e[0], 0), "stream wait");
+  }
+  double load[kPrjStreams] = {0.0};
+  auto pick = [&](double work) {
+    int q = 0;
+    for (int x = 1; x < kPrjStreams; ++x)
+      if (load[x] < load[q]) q = x;
+    load[q] += work;
+    return fk.s[q];
+  };
   {
     int64_t toff = 0;
     for (int c = 1; c <= 16; ++c) {
-      launch_project_stacked(c, d_ptile + toff, ncount[c], d_pblk, M.d_omega, st);
+      if (ncount[c] > 0)
+        launch_project_stacked(c, d_ptile + toff, ncount[c], d_pblk, M.d_omega,
+                               pick((double)ncount[c] * c));
       toff += ncount[c];
     }
     launch_check("project (stacked)");
   }
   int64_t off = 0;
   for (const auto& L : launches) {
+    hipStream_t ls = pick((double)L[3] * std::max<int64_t>(1, L[0] * L[1]));
     if (L[0] > 0)
       launch_project_tiled(mixed, (int)L[0], (int)L[1], L[2] != 0, d_tasks + off, L[3], M.d_omega,
-                           st);
+                           ls);
     else
-      launch_project(mixed, d_tasks + off, L[3], M.d_omega, st);
+      launch_project(mixed, d_tasks + off, L[3], M.d_omega, ls);
     launch_check("project");
     off += L[3];
+  }
+  for (int q = 1; q < kPrjStreams; ++q) {
+    hip_check(hipEventRecord(fk.e[q], fk.s[q]), "event record");
+    hip_check(hipStreamWaitEvent(st, fk.e[q], 0), "stream wait");
   }
   tp.stop();
   tr_.mark("proj launch", 0, -1, -1);
@@ -1797,13 +1835,16 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     hip_check(hipEventRecord(r1, st), "event");
     hip_check(hipStreamWaitEvent(st, c1, 0), "stream wait");
     hip_check(hipEventRecord(e1, st), "event");
+    // the projection's task lists are built on the host while the device
+    // finishes the sweeps; its launches follow the sweeps on st
+    project_all(M, st, mem, ss_row);
     hip_check(hipEventSynchronize(e1), "event");
     hip_check(hipEventElapsedTime(&ms_sweeps, e0, e1), "event");
     hip_check(hipEventElapsedTime(&ms_col, c0, c1), "event");
     hip_check(hipEventElapsedTime(&ms_row, e0, r1), "event");
   }
   // projection of every admissible block (needs both bases)
-  project_all(M, st, mem, ss_row);
+  if (!M.concurrent) project_all(M, st, mem, ss_row);
   ms_sweeps += (float)(ss_row.t_prj * 1e3);
 
   // near field
