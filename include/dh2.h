@@ -311,7 +311,9 @@ typedef struct {
   int32_t items[2];
   double mem_bytes;        /* bases + transfer + coupling + near field      */
   double mem_per_n_kib;    /* KiB per degree of freedom (complex128 words)  */
-  double t_row, t_col, t_prj, t_near, t_total; /* device seconds per phase   */
+  /* device seconds per phase; the near field (t_near) is generated beside
+   * the sweeps, and t_total is the device span of the whole compression    */
+  double t_row, t_col, t_prj, t_near, t_total;
   /* algorithmic real flops (a complex multiply-add counts 8): per (t,c) with
    * r factor rows, N columns and rank k, 8 r^2 N for the reduction of the
    * block row and 8 k r N for R = Q^* A (columns actually formed); per
