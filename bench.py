@@ -75,9 +75,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(dh2, torch, blocks, w, eps, leaf, form, steps, warmup, groups, normals=None):
+def run_form(dh2, torch, blocks, w, eps, leaf, form, steps, warmup, groups, normals=None,
+             cap=0):
     prec = dh2.FP64 if form == "fp64" else dh2.MIXED
-    o = dh2.opts(leaf_size=leaf, precision=prec, groups=groups)
+    o = dh2.opts(leaf_size=leaf, precision=prec, groups=groups, max_device_bytes=cap)
     times, st, m = [], None, None
     for it in range(warmup + steps):
         m = None
@@ -346,6 +347,10 @@ def main():
                     help="slp (default): the single-layer matrix of the workload; dlp: the "
                          "double-layer matrix on the same points (sphere and ellipsoid "
                          "workloads), timed as a separate line")
+    ap.add_argument("--sequential", action="store_true",
+                    help="profiling aid: a device-memory cap equal to the device's memory, "
+                         "which makes the row and column sweeps run one after the other, so "
+                         "that each kernel's duration is its own (not a bench line)")
     ap.add_argument("--mode", choices=("compress", "matvec"), default="compress",
                     help="compress (default): the compression step; matvec: y = G~x and "
                          "y = G~^*x with the compressed representation of the first form")
@@ -396,9 +401,10 @@ def main():
         else:
             raise SystemExit("--source dlp needs a sphere or ellipsoid workload")
     res = {}
+    cap = torch.cuda.get_device_properties(0).total_memory if args.sequential else 0
     for form in forms:
         m, st, times = run_form(dh2, torch, blocks, w, eps, leaf, form, args.steps, args.warmup,
-                                args.groups, normals)
+                                args.groups, normals, cap)
         rows = np.random.default_rng(5).choice(n, 16, replace=False)
         x = torch.from_numpy(synth.complex_gaussian(n, 6)).to("cuda")
         _, _, rows_rel = dh2.rows_check(m, rows, x)
@@ -474,7 +480,8 @@ def main():
         "config": {"workload": args.workload, "n": n, "kappa": kappa, "leaf_size": leaf,
                    "eps": eps, "eta1": 20.0, "eta2": 5.0, "zeta": 2.0 / 3.0, "form": head,
                    "matrix": "double layer" if dlp else "single layer",
-                   "entries": "generated on the fly"},
+                   "entries": "generated on the fly",
+                   "sweeps": "sequential (profiling aid)" if args.sequential else "concurrent"},
         "roofline": {"bound": "mfma", "kernel": kern,
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
                      "frac": achieved / peak, "traffic": traffic,
