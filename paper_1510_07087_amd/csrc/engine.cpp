@@ -2310,7 +2310,7 @@ static void matvec_core(MatrixData& M, char op, int nr, const double2* x, double
   hip_check(hipEventRecord(P.ev_x, st), "event record");
   hip_check(hipStreamWaitEvent(P.side, P.ev_x, 0), "stream wait");
   launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near,
-                  P.d_nearT, VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 0, P.side);
+                  P.d_nearT, VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 1, 0, P.side);
   launch_leaf_sum(VB.d_split, VB.nsplit, w.part, w.yp, nr, P.side);
   hip_check(hipEventRecord(P.ev_near, P.side), "event record");
   launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, w.xp, w.xh, nr, st);
@@ -2327,7 +2327,7 @@ static void matvec_core(MatrixData& M, char op, int nr, const double2* x, double
   // basis terms added to the near-field rows
   hip_check(hipStreamWaitEvent(st, P.ev_near, 0), "stream wait");
   launch_bwd_leaf(Bs.d_items, VB.d_basis, VB.nbasis, VB.d_nref, P.d_nears, M.d_near, P.d_nearT,
-                  VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 1, st);
+                  VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 0, 1, st);
   launch_scatter_perm(w.yp, M.d_perm, n, y, st, nr);
   launch_check("matvec");
 }

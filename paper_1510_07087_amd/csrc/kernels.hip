@@ -1387,8 +1387,11 @@ __global__ __launch_bounds__(128) void k_bwd_inner(const ItemDev* items, const i
 // the task's basis terms and near-field blocks in turn, and the partial sums
 // are added through LDS in wave order.  The adjoint reads the transposed
 // copy of every near-field block (nearT, #s x #t column-major), so that both
-// products read consecutive rows across the lanes.
-template <int NR>
+// products read consecutive rows across the lanes.  The two kinds of task
+// are separate instantiations (NEAR), so that each keeps only the registers
+// of its own loop (with eight right-hand sides the basis tasks run at five
+// waves per SIMD instead of two).
+template <int NR, bool NEAR>
 __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const LeafDev* leaves,
                                                   const NearRefDev* nref, const NearDev* nears,
                                                   const double2* nearv, const double2* nearT,
@@ -1403,11 +1406,13 @@ __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const Le
   double2 s[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
-  for (int q = L.item_first + w; q < L.item_first + L.item_count; q += 4) {
-    const ItemDev& it = items[q];
-    dot_rhs<NR>(s, it.Q + (int64_t)j * it.k, 1, yh + yh_off[q] * nr, it.k, nr, false);
+  if constexpr (!NEAR) {
+    for (int q = L.item_first + w; q < L.item_first + L.item_count; q += 4) {
+      const ItemDev& it = items[q];
+      dot_rhs<NR>(s, it.Q + (int64_t)j * it.k, 1, yh + yh_off[q] * nr, it.k, nr, false);
+    }
   }
-  for (int64_t q = L.near_begin + w; q < L.near_end; q += 4) {
+  if constexpr (NEAR) for (int64_t q = L.near_begin + w; q < L.near_end; q += 4) {
     const NearRefDev ref = nref[q];
     const NearDev nb = nears[ref.b];
     // op N: sum_c B[row, c] x[s_off + c]; adjoint: sum_c conj(B[c, row])
@@ -3149,11 +3154,16 @@ void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleave
                      const NearRefDev* nref, const NearDev* nears, const double2* nearv,
                      const double2* nearT, const int64_t* yh_off, const double2* yh,
                      const double2* xp, double2* yp, double2* partial, int adjoint, int nr,
-                     int accumulate, hipStream_t st) {
+                     int near, int accumulate, hipStream_t st) {
   if (nleaves == 0) return;
-  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_bwd_leaf<NR>, dim3(nleaves), dim3(256), 0, st, items,
-                                         leaves, nref, nears, nearv, nearT, yh_off, yh, xp, yp,
-                                         partial, adjoint, nr, accumulate));
+  if (near)
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_bwd_leaf<NR, true>), dim3(nleaves), dim3(256), 0,
+                                           st, items, leaves, nref, nears, nearv, nearT, yh_off,
+                                           yh, xp, yp, partial, adjoint, nr, accumulate));
+  else
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_bwd_leaf<NR, false>), dim3(nleaves), dim3(256), 0,
+                                           st, items, leaves, nref, nears, nearv, nearT, yh_off,
+                                           yh, xp, yp, partial, adjoint, nr, accumulate));
 }
 
 void launch_leaf_sum(const LeafDev* leaves, int32_t nleaves, const double2* partial, double2* yp,

@@ -110,7 +110,7 @@ void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleave
                      const NearRefDev* nref, const NearDev* nears, const double2* nearv,
                      const double2* nearT, const int64_t* yh_off, const double2* yh,
                      const double2* xp, double2* yp, double2* partial, int adjoint, int nr,
-                     int accumulate, hipStream_t st);
+                     int near, int accumulate, hipStream_t st);
 void launch_leaf_sum(const LeafDev* leaves, int32_t nleaves, const double2* partial, double2* yp,
                      int nr, hipStream_t st);
 void launch_near_transpose(const NearDev* nears, int64_t nblocks, const double2* B, double2* BT,
