@@ -1201,10 +1201,14 @@ __device__ __forceinline__ void stg(float2* p, int64_t i, float2 v) {
   ((__attribute__((address_space(1))) gfv2*)p)[i] = gfv2{v.x, v.y};
 }
 
+// s[q] += sum_{c < n} op(a[c as]) v[c vs + q] (q < nr; vs = nr unless given),
+// op the conjugate when conj_a; U terms loaded ahead of their products
 template <int NR>
 __device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int64_t as,
-                                        const double2* v, int64_t n, int nr, bool conj_a) {
+                                        const double2* v, int64_t n, int nr, bool conj_a,
+                                        int64_t vs = 0) {
   constexpr int U = NR == 1 ? 8 : (NR == 2 ? 4 : (NR <= 4 ? 2 : 1));
+  const int64_t vst = vs ? vs : nr;
   int64_t c = 0;
   for (; c + U <= n; c += U) {
     double2 av[U], xv[U][NR];
@@ -1213,7 +1217,7 @@ __device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int6
       av[u] = ldg(a, (c + u) * as);
 #pragma unroll
       for (int q = 0; q < NR; ++q)
-        if (q < nr) xv[u][q] = ldg(v, (c + u) * nr + q);
+        if (q < nr) xv[u][q] = ldg(v, (c + u) * vst + q);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -1230,7 +1234,7 @@ __device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int6
 #pragma unroll
     for (int q = 0; q < NR; ++q)
       if (q < nr) {
-        const double2 xq = ldg(v, c * nr + q);
+        const double2 xq = ldg(v, c * vst + q);
         double2 t = conj_a ? cmulc(ac, xq) : cmul(ac, xq);
         s[q].x += t.x;
         s[q].y += t.y;
@@ -1384,13 +1388,14 @@ __global__ __launch_bounds__(128) void k_bwd_inner(const ItemDev* items, const i
 // of four waves per task (the basis terms of a leaf, added to the rows
 // already written (accumulate), or a leaf's near-field blocks, or a part of them),
 // lane j one row of the leaf (leaves have at most 64 rows): the waves take
-// the task's basis terms and near-field blocks in turn, and the partial sums
+// the task's basis terms in turn, or the columns of each near-field block in
+// turn (the workgroup streams one block at a time), and the partial sums
 // are added through LDS in wave order.  The adjoint reads the transposed
 // copy of every near-field block (nearT, #s x #t column-major), so that both
 // products read consecutive rows across the lanes.  The two kinds of task
 // are separate instantiations (NEAR), so that each keeps only the registers
-// of its own loop (with eight right-hand sides the basis tasks run at five
-// waves per SIMD instead of two).
+// of its own loop (with eight right-hand sides both run at five waves per
+// SIMD, against two for one kernel holding both loops).
 template <int NR, bool NEAR>
 __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const LeafDev* leaves,
                                                   const NearRefDev* nref, const NearDev* nears,
@@ -1412,16 +1417,21 @@ __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const Le
       dot_rhs<NR>(s, it.Q + (int64_t)j * it.k, 1, yh + yh_off[q] * nr, it.k, nr, false);
     }
   }
-  if constexpr (NEAR) for (int64_t q = L.near_begin + w; q < L.near_end; q += 4) {
+  if constexpr (NEAR) for (int64_t q = L.near_begin; q < L.near_end; ++q) {
     const NearRefDev ref = nref[q];
     const NearDev nb = nears[ref.b];
-    // op N: sum_c B[row, c] x[s_off + c]; adjoint: sum_c conj(B[c, row])
-    // x[t_off + c] = sum_c conj(B^T[row, c]) x[t_off + c], with row = ref.row0 + j
     const int64_t row = ref.row0 + j;
-    if (!adjoint)
-      dot_rhs<NR>(s, nearv + nb.off + row, nb.t_len, xp + nb.s_off * nr, nb.s_len, nr, false);
-    else
-      dot_rhs<NR>(s, nearT + nb.off + row, nb.s_len, xp + nb.t_off * nr, nb.t_len, nr, true);
+    // op N: sum_c B[row, c] x[s_off + c]; adjoint: sum_c conj(B^T[row, c])
+    // x[t_off + c] with B^T the transposed copy (#s x #t); row = ref.row0 + j.
+    // The four waves take the block's columns in turn (one stream per
+    // workgroup).
+    const int64_t ld = adjoint ? nb.s_len : nb.t_len;
+    const int64_t ncol = adjoint ? nb.t_len : nb.s_len;
+    const int64_t xo = adjoint ? nb.t_off : nb.s_off;
+    const double2* B = (adjoint ? nearT : nearv) + nb.off + row;
+    if (w < ncol)
+      dot_rhs<NR>(s, B + w * ld, 4 * ld, xp + (xo + w) * nr, (ncol - w + 3) / 4, nr, adjoint != 0,
+                  4 * (int64_t)nr);
   }
 #pragma unroll
   for (int q = 0; q < NR; ++q) part[w][q][lane] = s[q];
