@@ -1995,6 +1995,13 @@ std::vector<std::unique_ptr<MatrixData>> compress_batch(
   hipEvent_t ready;
   hip_check(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "event");
   hip_check(hipEventRecord(ready, st), "event record");
+  // the largest instances first (their work grows with n^2), so that the
+  // last instances to start are small and the streams finish together
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return blks[a]->tree->tr.n > blks[b]->tree->tr.n;
+  });
   std::atomic<int> next{0};
   std::atomic<bool> failed{false};
   std::mutex emu;
@@ -2010,8 +2017,9 @@ std::vector<std::unique_ptr<MatrixData>> compress_batch(
       hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream create");
       hip_check(hipStreamWaitEvent(s, ready, 0), "stream wait");
       for (;;) {
-        int i = next.fetch_add(1);
-        if (i >= n || failed.load()) break;
+        const int q = next.fetch_add(1);
+        if (q >= n || failed.load()) break;
+        const int i = order[q];
         out[i] = compress(blks[i], SRC_HELMHOLTZ, nullptr, 0, w[i], eps, o, s, nullptr,
                           kBatchConcurrent);
       }
