@@ -280,7 +280,7 @@ def run_matvec(args, dh2, torch, synth, blocks, w, eps, leaf, kappa, n, form):
     m = dh2.compress_helmholtz(blocks, w, eps, o)
     torch.cuda.synchronize()
     st = dh2.stats(m)
-    rep_bytes = st["mem_bytes"]
+    rep_bytes = st["repr_bytes"]   # as stored: S_b and near field in FP32 in the mixed form
     ms = {}
     for nrhs in (1, 8):
         xn = synth.complex_gaussian(n, 6, nrhs if nrhs > 1 else None)

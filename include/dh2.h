@@ -195,8 +195,9 @@ dh2_status dh2_blocks_colsets(dh2_blocks blocks, int32_t side, int32_t* item_t,
  * entries with an FP64 phase reduction and FP32 polynomials, Gram matrices
  * of the weighted block rows from exact int8 slices of their rows (int32
  * accumulation on int8 MFMA, converted to FP64), R^T stored in complex FP32
- * with FP32 MFMA R-products and projection; factorisation, truncation and
- * transfer matrices stay FP64.  The slicing keeps about 2^-42 of the squared
+ * with FP32 MFMA R-products and projection, coupling matrices and near
+ * field stored as complex FP32; factorisation, truncation and transfer
+ * matrices stay FP64.  The slicing keeps about 2^-42 of the squared
  * row maxima in the Gram matrices, which places the mixed form at eps >=
  * 1e-5; smaller eps takes DH2_FP64.
  * EINVAL: eps <= 0 or non-finite, zeta <= 0 or 2 zeta^2 >= 1, ld < n,
@@ -332,6 +333,11 @@ typedef struct {
   double flops_rprod_leaf;   /* R-product flops of leaf block rows */
   double ops_gram_leaf_i8;   /* mixed form: int8 MFMA operations of the leaf Gram
                                 matrices, 60 r (r + 1) N per leaf block row      */
+  double repr_bytes;         /* device bytes of the stored representation: bases
+                                and transfer matrices complex FP64, coupling
+                                matrices and near field complex FP64 (FP64 form)
+                                or complex FP32 (mixed form); one matrix-vector
+                                product reads them once                          */
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_matrix m, dh2_stats* out);
@@ -351,7 +357,9 @@ dh2_status dh2_basis_export(dh2_matrix m, int32_t side, int32_t* nitems,
                             double* mat);
 
 /* Coupling matrices: S_b (k_t x k_s column-major complex128) at
- * 2*off[b] of `S`, off has nadm+1 entries.  Sizes first with S == NULL.     */
+ * 2*off[b] of `S`, off has nadm+1 entries.  Sizes first with S == NULL.
+ * The mixed form stores S_b and the near field as complex FP32; both exports
+ * widen the stored values exactly.                                          */
 dh2_status dh2_coupling_export(dh2_matrix m, int64_t* off, double* S);
 
 /* Near-field blocks G|_b (|t| x |s| column-major complex128, permuted order

@@ -408,6 +408,18 @@ dh2_status dh2_basis_export(dh2_matrix m, int32_t side, int32_t* nitems, int64_t
   })
 }
 
+// cnt complex values from the device to interleaved host doubles; f32: the
+// device holds them as complex FP32 (widened exactly)
+static void copy_widen(double* dst, const void* src, int64_t cnt, bool f32, const char* what) {
+  if (!f32) {
+    hip_check(hipMemcpy(dst, src, cnt * sizeof(double2), hipMemcpyDeviceToHost), what);
+    return;
+  }
+  std::vector<float> tmp(2 * (size_t)cnt);
+  hip_check(hipMemcpy(tmp.data(), src, cnt * sizeof(float2), hipMemcpyDeviceToHost), what);
+  for (size_t i = 0; i < tmp.size(); ++i) dst[i] = (double)tmp[i];
+}
+
 dh2_status dh2_coupling_export(dh2_matrix m, int64_t* off, double* S) {
   DH2_TRY({
     if (!m || !off) fail(DH2_EINVAL, "NULL argument");
@@ -416,9 +428,7 @@ dh2_status dh2_coupling_export(dh2_matrix m, int64_t* off, double* S) {
     for (int64_t b = 0; b < nadm; ++b) {
       off[b] = o;
       int64_t cnt = (int64_t)M.S_rows[b] * M.S_cols[b];
-      if (S && cnt)
-        hip_check(hipMemcpy(S + 2 * o, M.S_ptr[b], cnt * sizeof(double2), hipMemcpyDeviceToHost),
-                  "export coupling");
+      if (S && cnt) copy_widen(S + 2 * o, M.S_ptr[b], cnt, M.s32, "export coupling");
       o += cnt;
     }
     off[nadm] = o;
@@ -435,8 +445,7 @@ dh2_status dh2_near_export(dh2_matrix m, int64_t* off, double* N) {
       tot += M.nears[b].t_len * M.nears[b].s_len;
     }
     off[nn] = tot;
-    if (N && tot)
-      hip_check(hipMemcpy(N, M.d_near, tot * sizeof(double2), hipMemcpyDeviceToHost), "export near");
+    if (N && tot) copy_widen(N, M.d_near, tot, M.s32, "export near");
   })
 }
 

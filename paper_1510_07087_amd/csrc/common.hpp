@@ -79,7 +79,7 @@ struct UnitDev {
 struct ProjDev {
   const void* R;      // R^T rows of the block (|s| x kt), complex FP64 or FP32
   const void* W;      // expanded column basis (|s| x ks row-major), complex FP64 or FP32
-  double2* S;         // output (kt x ks column-major)
+  void* S;            // output (kt x ks column-major), complex FP64 (FP64 form) or FP32 (mixed)
   int32_t kt, ks;
   int32_t ns;         // |s|
   int32_t b;
@@ -90,7 +90,7 @@ struct ProjDev {
 // the other); a tile is up to 64 consecutive stacked rows.
 struct PBlkDev {
   const float2* R;  // R^T rows of the block: column j of s at R[j * kt + i]
-  double2* S;       // output (kt x ks column-major)
+  float2* S;        // output (kt x ks column-major)
   int32_t kt, b;
 };
 struct PTileDev {

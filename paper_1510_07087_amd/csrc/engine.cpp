@@ -415,10 +415,10 @@ struct SideMV {
 struct MatvecPlan {
   SideMV s[2];
   NearDev* d_nears = nullptr;
-  double2* const* d_Sptr = nullptr;
+  void* const* d_Sptr = nullptr;
   int32_t* d_Srows = nullptr;
   int32_t* d_Scols = nullptr;
-  double2* const* d_STptr = nullptr;  // transposed copies S_b^T for the adjoint
+  void* const* d_STptr = nullptr;  // transposed copies S_b^T for the adjoint
   double2* xp = nullptr;
   double2* yp = nullptr;
   double2* xh = nullptr;  // sized for the larger side
@@ -426,7 +426,7 @@ struct MatvecPlan {
   double2* part = nullptr;  // partial sums of split leaves (64 rows x kMvRhs per slot)
   int64_t maxh = 0;       // coefficients of the larger side
   int32_t maxslots = 0;   // partial slots of the larger side
-  double2* d_nearT = nullptr;  // near-field blocks transposed (#s x #t column-major)
+  void* d_nearT = nullptr;  // near-field blocks transposed (#s x #t column-major)
   // the near-field rows run on a second stream beside the basis chain
   hipStream_t side = nullptr;
   hipEvent_t ev_x = nullptr, ev_near = nullptr;
@@ -1310,7 +1310,9 @@ static void project_all(MatrixData& M, hipStream_t st, DevMem& mem, SweepStats& 
       chunks.back().s_off = s0;
     }
   }
-  double2* Sarena = (double2*)mem.alloc(std::max<int64_t>(1, sumS) * sizeof(double2));
+  // S_b in the form's storage precision (complex FP32 in the mixed form)
+  const size_t sesz = M.s32 ? sizeof(float2) : sizeof(double2);
+  char* Sarena = (char*)mem.alloc(std::max<int64_t>(1, sumS) * sesz);
   S.keep.push_back(Sarena);
   auto build = [&](PChunk& ch) {
     const auto& pl = plans[ch.plan];
@@ -1324,12 +1326,12 @@ static void project_all(MatrixData& M, hipStream_t st, DevMem& mem, SweepStats& 
       ProjDev pd{};
       pd.R = (const char*)S.own[q.item] + (q.col - S.P->ninh[q.item]) * it.k * esz;
       pd.W = mixed ? (const void*)C.wexp32[q.witem] : (const void*)C.wexp[q.witem];
-      pd.S = Sarena + o;
+      pd.S = Sarena + o * sesz;
       pd.kt = it.k;
       pd.ks = ks;
       pd.ns = q.ns;
       pd.b = q.b;
-      M.S_ptr[q.b] = Sarena + o;
+      M.S_ptr[q.b] = Sarena + o * sesz;
       M.S_rows[q.b] = it.k;
       M.S_cols[q.b] = ks;
       o += (int64_t)it.k * ks;
@@ -1362,7 +1364,8 @@ static void project_all(MatrixData& M, hipStream_t st, DevMem& mem, SweepStats& 
       const int32_t b0 = (int32_t)ch.pblk.size();
       for (size_t x = g0; x < g1; ++x) {
         const ProjDev& pd = ch.tasks[x - ch.q0];
-        if (pd.kt > 0) ch.pblk.push_back(PBlkDev{(const float2*)pd.R, pd.S, pd.kt, pd.b});
+        if (pd.kt > 0)
+          ch.pblk.push_back(PBlkDev{(const float2*)pd.R, (float2*)pd.S, pd.kt, pd.b});
       }
       const int32_t b1 = (int32_t)ch.pblk.size();
       int32_t bi = b0, i0 = 0;
@@ -1579,6 +1582,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
   M.eps = eps;
   M.zeta = o.zeta;
   M.precision = o.precision;
+  M.s32 = o.precision == DH2_MIXED;
   M.max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 60;
   M.mem = std::make_unique<DevMem>(o.max_device_bytes);
   const ClusterTree& tr = blk->tree->tr;
@@ -1676,7 +1680,8 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     // the near field is generated beside the sweeps and held through them
     double near_bytes = 0;
     for (size_t b = 0; b < bt.near_t.size(); ++b)
-      near_bytes += 16.0 * (double)tr.size[bt.near_t[b]] * (double)tr.size[bt.near_s[b]];
+      near_bytes += (o.precision == DH2_MIXED ? 8.0 : 16.0) * (double)tr.size[bt.near_t[b]] *
+                    (double)tr.size[bt.near_s[b]];
     budget = std::max(0.25 * budget, budget - near_bytes);
   }
   // The row and column sweeps are independent (the projection follows both),
@@ -1799,7 +1804,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
       M.nears[b] = NearDev{tot, to[b], tl[b], so[b], sl[b]};
       tot += tl[b] * sl[b];
     }
-    M.d_near = (double2*)mem.alloc(std::max<int64_t>(1, tot) * sizeof(double2));
+    M.d_near = mem.alloc(std::max<int64_t>(1, tot) * (M.s32 ? sizeof(float2) : sizeof(double2)));
     nf.d[0] = upload(mem, to, st);
     nf.d[1] = upload(mem, tl, st);
     nf.d[2] = upload(mem, so, st);
@@ -1810,7 +1815,7 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
     hip_check(hipEventRecord(nf.e[2], st), "event");
     hip_check(hipStreamWaitEvent(nf.s, nf.e[2], 0), "stream wait");
     hip_check(hipEventRecord(nf.e[0], nf.s), "event");
-    launch_near(src, g, nf.d[0], nf.d[1], nf.d[2], nf.d[3], nf.d[4], nnear, M.d_near, nf.s);
+    launch_near(src, g, nf.d[0], nf.d[1], nf.d[2], nf.d[3], nf.d[4], nnear, M.d_near, M.s32, nf.s);
     launch_check("near field");
     hip_check(hipEventRecord(nf.e[1], nf.s), "event");
   }
@@ -1947,8 +1952,10 @@ std::unique_ptr<MatrixData> compress(std::shared_ptr<BlocksData> blk, int src, c
       kmax = std::max(kmax, it.k);
       words += (double)it.r * it.k;  // leaf Q or transfer [E1;E2]
     }
+  const double bwords = words;
   for (int64_t b = 0; b < nadm; ++b) words += (double)M.S_rows[b] * M.S_cols[b];
   for (const NearDev& nd : M.nears) words += (double)nd.t_len * nd.s_len;
+  S.repr_bytes = bwords * 16.0 + (words - bwords) * (M.s32 ? 8.0 : 16.0);
   S.k_max = kmax;
   S.mem_bytes = words * 16.0;
   S.mem_per_n_kib = S.mem_bytes / 1024.0 / (double)n;
@@ -2260,31 +2267,31 @@ static void build_mv(MatrixData& M, hipStream_t st) {
   {
     int64_t tot = 0;
     for (const NearDev& nb : M.nears) tot = std::max(tot, nb.off + nb.t_len * nb.s_len);
-    P->d_nearT = (double2*)mem.alloc(std::max<int64_t>(1, tot) * sizeof(double2));
+    P->d_nearT = mem.alloc(std::max<int64_t>(1, tot) * (M.s32 ? sizeof(float2) : sizeof(double2)));
   }
   P->d_nears = upload(mem, M.nears, st);
   hip_check(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "stream create");
   hip_check(hipEventCreateWithFlags(&P->ev_x, hipEventDisableTiming), "event");
   hip_check(hipEventCreateWithFlags(&P->ev_near, hipEventDisableTiming), "event");
-  launch_near_transpose(P->d_nears, (int64_t)M.nears.size(), M.d_near, P->d_nearT, st);
+  launch_near_transpose(P->d_nears, (int64_t)M.nears.size(), M.d_near, P->d_nearT, M.s32, st);
   launch_check("near-field transpose");
-  std::vector<double2*> sp(M.S_ptr.begin(), M.S_ptr.end());
-  P->d_Sptr = upload(mem, sp, st);
+  P->d_Sptr = upload(mem, M.S_ptr, st);
   P->d_Srows = upload(mem, M.S_rows, st);
   P->d_Scols = upload(mem, M.S_cols, st);
   {
     // the adjoint's coupling reads S_b^T (kc x kr), a copy made here
     int64_t tot = 0;
     for (int64_t b = 0; b < nadm; ++b) tot += (int64_t)M.S_rows[b] * M.S_cols[b];
-    double2* arena = (double2*)mem.alloc(std::max<int64_t>(1, tot) * sizeof(double2));
-    std::vector<double2*> tp(nadm);
+    const size_t sesz = M.s32 ? sizeof(float2) : sizeof(double2);
+    char* arena = (char*)mem.alloc(std::max<int64_t>(1, tot) * sesz);
+    std::vector<void*> tp(nadm);
     int64_t o = 0;
     for (int64_t b = 0; b < nadm; ++b) {
-      tp[b] = arena + o;
+      tp[b] = arena + o * sesz;
       o += (int64_t)M.S_rows[b] * M.S_cols[b];
     }
     P->d_STptr = upload(mem, tp, st);
-    launch_coupling_transpose(P->d_Sptr, P->d_STptr, P->d_Srows, P->d_Scols, nadm, st);
+    launch_coupling_transpose(P->d_Sptr, P->d_STptr, P->d_Srows, P->d_Scols, nadm, M.s32, st);
     launch_check("coupling transpose");
   }
   int64_t n = tr.n;
@@ -2318,7 +2325,7 @@ static void matvec_core(MatrixData& M, char op, int nr, const double2* x, double
   hip_check(hipEventRecord(P.ev_x, st), "event record");
   hip_check(hipStreamWaitEvent(P.side, P.ev_x, 0), "stream wait");
   launch_bwd_leaf(Bs.d_items, VB.d_leaves, VB.nleaves, VB.d_nref, P.d_nears, M.d_near,
-                  P.d_nearT, VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 1, 0, P.side);
+                  P.d_nearT, VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 1, 0, M.s32, P.side);
   launch_leaf_sum(VB.d_split, VB.nsplit, w.part, w.yp, nr, P.side);
   hip_check(hipEventRecord(P.ev_near, P.side), "event record");
   launch_fwd_leaf(A.d_items, VA.d_fwd_leaf, VA.n_fwd_leaf, VA.d_hoff, w.xp, w.xh, nr, st);
@@ -2328,14 +2335,15 @@ static void matvec_core(MatrixData& M, char op, int nr, const double2* x, double
   launch_coupling(Bs.d_items, Bs.nitems, VB.nheavy, VB.d_corder, VB.d_cbegin, VB.d_cblock,
                   VB.d_cpartner,
                   adj ? P.d_STptr : P.d_Sptr, adj ? P.d_Scols : P.d_Srows,
-                  adj ? P.d_Srows : P.d_Scols, VA.d_hoff, w.xh, VB.d_hoff, w.yh, adj, nr, st);
+                  adj ? P.d_Srows : P.d_Scols, VA.d_hoff, w.xh, VB.d_hoff, w.yh, adj, nr, M.s32,
+                  st);
   for (size_t l = 0; l < VB.d_bl_items.size(); ++l)
     launch_bwd_inner(Bs.d_items, VB.d_bl_items[l], VB.bl_count[l], VB.d_bl_fbegin[l],
                      VB.d_bl_fitem[l], VB.d_bl_fson[l], VB.d_hoff, w.yh, nr, st);
   // basis terms added to the near-field rows
   hip_check(hipStreamWaitEvent(st, P.ev_near, 0), "stream wait");
   launch_bwd_leaf(Bs.d_items, VB.d_basis, VB.nbasis, VB.d_nref, P.d_nears, M.d_near, P.d_nearT,
-                  VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 0, 1, st);
+                  VB.d_hoff, w.yh, w.xp, w.yp, w.part, adj, nr, 0, 1, M.s32, st);
   launch_scatter_perm(w.yp, M.d_perm, n, y, st, nr);
   launch_check("matvec");
 }

@@ -169,9 +169,12 @@ struct MatrixData {
   Side side[2];
   double* d_omega = nullptr;
   std::vector<double> omega;
-  std::vector<double2*> S_ptr; // per admissible block
+  // coupling matrices and near field: complex FP32 in the mixed form (s32),
+  // complex FP64 otherwise
+  bool s32 = false;
+  std::vector<void*> S_ptr;    // per admissible block
   std::vector<int32_t> S_rows, S_cols;
-  double2* d_near = nullptr;
+  void* d_near = nullptr;
   std::vector<NearDev> nears;
   dh2_stats stats{};
   std::unique_ptr<MatvecPlan> mv;

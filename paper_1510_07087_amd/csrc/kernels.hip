@@ -66,6 +66,15 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
+// Stored coupling matrices and near-field blocks: complex FP64 in the FP64
+// form, complex FP32 in the mixed form (SE); arithmetic on them is FP64.
+__device__ __forceinline__ double2 wide(double2 v) { return v; }
+__device__ __forceinline__ double2 wide(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ void put(double2* p, int64_t i, double2 v) { p[i] = v; }
+__device__ __forceinline__ void put(float2* p, int64_t i, double2 v) {
+  p[i] = make_float2((float)v.x, (float)v.y);
+}
+
 constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
 
 // ---------------------------------------------------------------------------
@@ -779,7 +788,8 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
   double om = omega[t.b];
   int nti = (kt + 15) / 16, ntj = (ks + 15) / 16;
   const void* Wb = t.W;
-  double2* Sb = t.S;
+  using SE = typename std::conditional<MX, float2, double2>::type;
+  SE* Sb = static_cast<SE*>(t.S);
   // column tiles of S in groups of eight (ranks beyond 128 take several)
   for (int tj0 = 0; tj0 < ntj; tj0 += 8)
   for (int ti16 = 0; ti16 < nti; ++ti16) {
@@ -804,7 +814,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjDev* tasks, int64_t n
         for (int v = 0; v < 4; ++v) {
           int i = ti16 * 16 + acc[q].row(lane, v);
           double2 z = acc[q].get(v);
-          if (i < kt && jj < ks) Sb[i + (int64_t)jj * kt] = make_double2(om * z.x, om * z.y);
+          if (i < kt && jj < ks) put(Sb, i + (int64_t)jj * kt, make_double2(om * z.x, om * z.y));
         }
       }
     }
@@ -1025,13 +1035,13 @@ __device__ __forceinline__ void pst_tile(const PTileDev& t, const PBlkDev* blks,
     if (st < ns % kRing) mac(st);
   if (lane < t.rows) {
     const double om = omega[B.b];
-    double2* Sr = B.S + i;
+    float2* Sr = B.S + i;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int col = 4 * c + v;
-        if (col < ks) Sr[(int64_t)col * kt] = make_double2(om * re[c][v], om * im[c][v]);
+        if (col < ks) put(Sr, (int64_t)col * kt, make_double2(om * re[c][v], om * im[c][v]));
       }
   }
 }
@@ -1055,7 +1065,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 template <bool MX, int NI, int NJ>
 __device__ void proj_store(const ProjDev& t, int ti0, double om, PAcc<MX> (&acc)[NI][NJ]) {
   int lane = threadIdx.x & 63, row = lane & 15;
-  double2* Sb = t.S;
+  using SE = typename std::conditional<MX, float2, double2>::type;
+  SE* Sb = static_cast<SE*>(t.S);
 #pragma unroll
   for (int I = 0; I < NI; ++I)
 #pragma unroll
@@ -1065,7 +1076,7 @@ __device__ void proj_store(const ProjDev& t, int ti0, double om, PAcc<MX> (&acc)
       for (int v = 0; v < 4; ++v) {
         int jj = 16 * J + acc[I][J].row(lane, v);
         double2 z = acc[I][J].get(v);
-        if (i < t.kt && jj < t.ks) Sb[i + (int64_t)jj * t.kt] = make_double2(om * z.x, om * z.y);
+        if (i < t.kt && jj < t.ks) put(Sb, i + (int64_t)jj * t.kt, make_double2(om * z.x, om * z.y));
       }
     }
 }
@@ -1126,7 +1137,8 @@ __global__ __launch_bounds__(256) void k_project_tiled(const ProjDev* tasks, int
         int i = 16 * (ti0 + I) + (l & 15);
         int jj = 16 * J + (MX ? f32_row(l, v) : f64_row(l, v));
         if (i < t.kt && jj < t.ks)
-          t.S[i + (int64_t)jj * t.kt] = make_double2(om * (double)re, om * (double)im);
+          put(static_cast<typename std::conditional<MX, float2, double2>::type*>(t.S),
+              i + (int64_t)jj * t.kt, make_double2(om * (double)re, om * (double)im));
       }
       __syncthreads();
     }
@@ -1136,16 +1148,16 @@ __global__ __launch_bounds__(256) void k_project_tiled(const ProjDev* tasks, int
 // ---------------------------------------------------------------------------
 // Near field: G|_b column-major per inadmissible block.
 // ---------------------------------------------------------------------------
-template <int SRC>
+template <int SRC, typename SE>
 __global__ __launch_bounds__(256) void k_near(GeomDev g, const int64_t* t_off, const int64_t* t_len,
                                               const int64_t* s_off, const int64_t* s_len,
-                                              const int64_t* out_off, double2* out) {
+                                              const int64_t* out_off, SE* out) {
   int64_t b = blockIdx.x;
   int64_t to = t_off[b], tl = t_len[b], so = s_off[b], sl = s_len[b];
-  double2* o = out + out_off[b];
+  SE* o = out + out_off[b];
   for (int64_t e = threadIdx.x; e < tl * sl; e += 256) {
     int64_t j = e / tl, i = e - j * tl;
-    o[e] = entry<SRC>(g, to + i, so + j, 0);
+    put(o, e, entry<SRC>(g, to + i, so + j, 0));
   }
 }
 
@@ -1203,8 +1215,8 @@ __device__ __forceinline__ void stg(float2* p, int64_t i, float2 v) {
 
 // s[q] += sum_{c < n} op(a[c as]) v[c vs + q] (q < nr; vs = nr unless given),
 // op the conjugate when conj_a; U terms loaded ahead of their products
-template <int NR>
-__device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int64_t as,
+template <int NR, typename AE = double2>
+__device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const AE* a, int64_t as,
                                         const double2* v, int64_t n, int nr, bool conj_a,
                                         int64_t vs = 0) {
   constexpr int U = NR == 1 ? 8 : (NR == 2 ? 4 : (NR <= 4 ? 2 : 1));
@@ -1214,7 +1226,7 @@ __device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int6
     double2 av[U], xv[U][NR];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      av[u] = ldg(a, (c + u) * as);
+      av[u] = wide(ldg(a, (c + u) * as));
 #pragma unroll
       for (int q = 0; q < NR; ++q)
         if (q < nr) xv[u][q] = ldg(v, (c + u) * vst + q);
@@ -1230,7 +1242,7 @@ __device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const double2* a, int6
         }
   }
   for (; c < n; ++c) {
-    const double2 ac = ldg(a, c * as);
+    const double2 ac = wide(ldg(a, c * as));
 #pragma unroll
     for (int q = 0; q < NR; ++q)
       if (q < nr) {
@@ -1295,12 +1307,12 @@ __global__ __launch_bounds__(128) void k_fwd_inner(const ItemDev* items, const i
 // take its blocks in turn, and their sums are added with shuffles, then
 // across the waves through LDS, in a fixed order.  The partner's
 // coefficients are the same for all lanes of a slot.
-template <int NR>
+template <int NR, typename SE>
 __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t nitems,
                                                   int32_t nheavy, const int32_t* order,
                                                   const int64_t* cbegin, const int32_t* cblock,
                                                   const int32_t* cpartner,
-                                                  const double2* const* S_ptr,
+                                                  const void* const* S_ptr,
                                                   const int32_t* S_rows, const int32_t* S_cols,
                                                   const int64_t* xh_off, const double2* xh,
                                                   const int64_t* yh_off, double2* yh,
@@ -1324,7 +1336,7 @@ __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t 
     for (int q = 0; q < NR; ++q) s[q] = make_double2(0.0, 0.0);
     for (int64_t c = cbegin[i] + first; c < cbegin[i + 1]; c += stride) {
       const int32_t b = cblock[c];
-      const double2* Sb = S_ptr[b];
+      const SE* Sb = static_cast<const SE*>(S_ptr[b]);
       const int kr = S_rows[b], kc = S_cols[b];  // of the oriented matrix
       const double2* x = xh + xh_off[cpartner[c]] * nr;
       // op N: sum_jj S[kk, jj] x[jj]; adjoint: sum_jj conj(S^T[kk, jj]) x[jj]
@@ -1396,10 +1408,10 @@ __global__ __launch_bounds__(128) void k_bwd_inner(const ItemDev* items, const i
 // are separate instantiations (NEAR), so that each keeps only the registers
 // of its own loop (with eight right-hand sides both run at five waves per
 // SIMD, against two for one kernel holding both loops).
-template <int NR, bool NEAR>
+template <int NR, bool NEAR, typename SE>
 __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const LeafDev* leaves,
                                                   const NearRefDev* nref, const NearDev* nears,
-                                                  const double2* nearv, const double2* nearT,
+                                                  const void* nearv, const void* nearT,
                                                   const int64_t* yh_off, const double2* yh,
                                                   const double2* xp, double2* yp,
                                                   double2* partial, int adjoint, int nr,
@@ -1428,7 +1440,7 @@ __global__ __launch_bounds__(256) void k_bwd_leaf(const ItemDev* items, const Le
     const int64_t ld = adjoint ? nb.s_len : nb.t_len;
     const int64_t ncol = adjoint ? nb.t_len : nb.s_len;
     const int64_t xo = adjoint ? nb.t_off : nb.s_off;
-    const double2* B = (adjoint ? nearT : nearv) + nb.off + row;
+    const SE* B = static_cast<const SE*>(adjoint ? nearT : nearv) + nb.off + row;
     if (w < ncol)
       dot_rhs<NR>(s, B + w * ld, 4 * ld, xp + (xo + w) * nr, (ncol - w + 3) / 4, nr, adjoint != 0,
                   4 * (int64_t)nr);
@@ -1483,9 +1495,10 @@ __global__ __launch_bounds__(64) void k_leaf_sum(const LeafDev* leaves, const do
 
 // transposed copy of the near-field blocks for the adjoint (one workgroup
 // per block, tiles of 64 rows x 32 columns through LDS)
-__global__ __launch_bounds__(256) void k_near_transpose(const NearDev* nears, const double2* B,
-                                                        double2* BT) {
-  __shared__ double2 tile[32][65];
+template <typename SE>
+__global__ __launch_bounds__(256) void k_near_transpose(const NearDev* nears, const SE* B,
+                                                        SE* BT) {
+  __shared__ SE tile[32][65];
   const NearDev nb = nears[blockIdx.x];
   const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;  // loads: 64 rows x 4
   const int sx = threadIdx.x & 31, sy = threadIdx.x >> 5;  // stores: 32 columns x 8
@@ -3035,17 +3048,25 @@ void launch_project_tiled(bool mixed, int ni, int nj, bool split, const ProjDev*
 
 void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
                  const int64_t* s_off, const int64_t* s_len, const int64_t* out_off,
-                 int64_t nblocks, double2* out, hipStream_t st) {
+                 int64_t nblocks, void* out, int f32, hipStream_t st) {
   if (nblocks == 0) return;
-  if (src == SRC_HELMHOLTZ)
-    hipLaunchKernelGGL(k_near<SRC_HELMHOLTZ>, dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
-                       t_len, s_off, s_len, out_off, out);
-  else if (src == SRC_DLP)
-    hipLaunchKernelGGL(k_near<SRC_DLP>, dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
-                       t_len, s_off, s_len, out_off, out);
+  auto go = [&](auto tag) {
+    using SE = decltype(tag);
+    SE* o = static_cast<SE*>(out);
+    if (src == SRC_HELMHOLTZ)
+      hipLaunchKernelGGL((k_near<SRC_HELMHOLTZ, SE>), dim3((unsigned)nblocks), dim3(256), 0, st, g,
+                         t_off, t_len, s_off, s_len, out_off, o);
+    else if (src == SRC_DLP)
+      hipLaunchKernelGGL((k_near<SRC_DLP, SE>), dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
+                         t_len, s_off, s_len, out_off, o);
+    else
+      hipLaunchKernelGGL((k_near<SRC_DENSE, SE>), dim3((unsigned)nblocks), dim3(256), 0, st, g,
+                         t_off, t_len, s_off, s_len, out_off, o);
+  };
+  if (f32)
+    go(float2{});
   else
-    hipLaunchKernelGGL(k_near<SRC_DENSE>, dim3((unsigned)nblocks), dim3(256), 0, st, g, t_off,
-                       t_len, s_off, s_len, out_off, out);
+    go(double2{});
 }
 
 // Scratch memory of the allocation-free matrix-vector product: one array per
@@ -3119,13 +3140,14 @@ void launch_fwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                                          litems, xh_off, xh, nr));
 }
 // S_b^T of every admissible block (one workgroup per block)
-__global__ __launch_bounds__(256) void k_coupling_transpose(const double2* const* S,
-                                                            double2* const* ST,
+template <typename SE>
+__global__ __launch_bounds__(256) void k_coupling_transpose(const void* const* S,
+                                                            void* const* ST,
                                                             const int32_t* rows,
                                                             const int32_t* cols) {
   const int b = blockIdx.x;
-  const double2* A = S[b];
-  double2* T = ST[b];
+  const SE* A = static_cast<const SE*>(S[b]);
+  SE* T = static_cast<SE*>(ST[b]);
   const int kr = rows[b], kc = cols[b];
   for (int e = threadIdx.x; e < kr * kc; e += 256) {
     const int i = e % kr, j = e / kr;
@@ -3133,25 +3155,36 @@ __global__ __launch_bounds__(256) void k_coupling_transpose(const double2* const
   }
 }
 
-void launch_coupling_transpose(const double2* const* S, double2* const* ST, const int32_t* rows,
-                               const int32_t* cols, int64_t nblocks, hipStream_t st) {
+void launch_coupling_transpose(const void* const* S, void* const* ST, const int32_t* rows,
+                               const int32_t* cols, int64_t nblocks, int f32, hipStream_t st) {
   if (nblocks == 0) return;
-  hipLaunchKernelGGL(k_coupling_transpose, dim3((unsigned)nblocks), dim3(256), 0, st, S, ST, rows,
-                     cols);
+  if (f32)
+    hipLaunchKernelGGL(k_coupling_transpose<float2>, dim3((unsigned)nblocks), dim3(256), 0, st, S,
+                       ST, rows, cols);
+  else
+    hipLaunchKernelGGL(k_coupling_transpose<double2>, dim3((unsigned)nblocks), dim3(256), 0, st, S,
+                       ST, rows, cols);
 }
 
 void launch_coupling(const ItemDev* items, int32_t nitems, int32_t nheavy,
                      const int32_t* order, const int64_t* cbegin, const int32_t* cblock,
-                     const int32_t* cpartner, const double2* const* S_ptr,
+                     const int32_t* cpartner, const void* const* S_ptr,
                      const int32_t* S_rows, const int32_t* S_cols, const int64_t* xh_off,
                      const double2* xh, const int64_t* yh_off, double2* yh, int adjoint, int nr,
-                     hipStream_t st) {
+                     int f32, hipStream_t st) {
   if (nitems == 0) return;
   // one launch: workgroups [0, nheavy) one item each, then four items each
   const int32_t nwg = nheavy + (nitems - nheavy + 3) / 4;
-  DH2_NR_DISPATCH(nr, hipLaunchKernelGGL(k_coupling<NR>, dim3(nwg), dim3(256), 0, st, items,
-                                         nitems, nheavy, order, cbegin, cblock, cpartner, S_ptr,
-                                         S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint, nr));
+  if (f32)
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_coupling<NR, float2>), dim3(nwg), dim3(256), 0, st,
+                                           items, nitems, nheavy, order, cbegin, cblock, cpartner,
+                                           S_ptr, S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint,
+                                           nr));
+  else
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_coupling<NR, double2>), dim3(nwg), dim3(256), 0, st,
+                                           items, nitems, nheavy, order, cbegin, cblock, cpartner,
+                                           S_ptr, S_rows, S_cols, xh_off, xh, yh_off, yh, adjoint,
+                                           nr));
 }
 void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* fbegin, const int32_t* fitem, const int32_t* fsonidx,
@@ -3161,19 +3194,26 @@ void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                                          litems, fbegin, fitem, fsonidx, yh_off, yh, nr));
 }
 void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleaves,
-                     const NearRefDev* nref, const NearDev* nears, const double2* nearv,
-                     const double2* nearT, const int64_t* yh_off, const double2* yh,
+                     const NearRefDev* nref, const NearDev* nears, const void* nearv,
+                     const void* nearT, const int64_t* yh_off, const double2* yh,
                      const double2* xp, double2* yp, double2* partial, int adjoint, int nr,
-                     int near, int accumulate, hipStream_t st) {
+                     int near, int accumulate, int f32, hipStream_t st) {
   if (nleaves == 0) return;
-  if (near)
-    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_bwd_leaf<NR, true>), dim3(nleaves), dim3(256), 0,
-                                           st, items, leaves, nref, nears, nearv, nearT, yh_off,
-                                           yh, xp, yp, partial, adjoint, nr, accumulate));
+  if (near && f32)
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_bwd_leaf<NR, true, float2>), dim3(nleaves),
+                                           dim3(256), 0, st, items, leaves, nref, nears, nearv,
+                                           nearT, yh_off, yh, xp, yp, partial, adjoint, nr,
+                                           accumulate));
+  else if (near)
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_bwd_leaf<NR, true, double2>), dim3(nleaves),
+                                           dim3(256), 0, st, items, leaves, nref, nears, nearv,
+                                           nearT, yh_off, yh, xp, yp, partial, adjoint, nr,
+                                           accumulate));
   else
-    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_bwd_leaf<NR, false>), dim3(nleaves), dim3(256), 0,
-                                           st, items, leaves, nref, nears, nearv, nearT, yh_off,
-                                           yh, xp, yp, partial, adjoint, nr, accumulate));
+    DH2_NR_DISPATCH(nr, hipLaunchKernelGGL((k_bwd_leaf<NR, false, double2>), dim3(nleaves),
+                                           dim3(256), 0, st, items, leaves, nref, nears, nearv,
+                                           nearT, yh_off, yh, xp, yp, partial, adjoint, nr,
+                                           accumulate));
 }
 
 void launch_leaf_sum(const LeafDev* leaves, int32_t nleaves, const double2* partial, double2* yp,
@@ -3183,10 +3223,15 @@ void launch_leaf_sum(const LeafDev* leaves, int32_t nleaves, const double2* part
                                          partial, yp, nr));
 }
 
-void launch_near_transpose(const NearDev* nears, int64_t nblocks, const double2* B, double2* BT,
-                           hipStream_t st) {
+void launch_near_transpose(const NearDev* nears, int64_t nblocks, const void* B, void* BT,
+                           int f32, hipStream_t st) {
   if (nblocks == 0) return;
-  hipLaunchKernelGGL(k_near_transpose, dim3((unsigned)nblocks), dim3(256), 0, st, nears, B, BT);
+  if (f32)
+    hipLaunchKernelGGL(k_near_transpose<float2>, dim3((unsigned)nblocks), dim3(256), 0, st, nears,
+                       static_cast<const float2*>(B), static_cast<float2*>(BT));
+  else
+    hipLaunchKernelGGL(k_near_transpose<double2>, dim3((unsigned)nblocks), dim3(256), 0, st, nears,
+                       static_cast<const double2*>(B), static_cast<double2*>(BT));
 }
 void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
                    const double2* xp, int adjoint, double2* out, hipStream_t st) {

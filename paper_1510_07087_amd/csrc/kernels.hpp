@@ -76,9 +76,11 @@ int project_rows_per_pass(bool mixed, int nj);
 // split: one workgroup per task with the columns of s divided among its waves
 void launch_project_tiled(bool mixed, int ni, int nj, bool split, const ProjDev* tasks,
                           int64_t ntasks, const double* omega, hipStream_t st);
+// f32 (below): the coupling matrices and near-field blocks are stored as
+// complex FP32 (mixed form), else as complex FP64; products with them are FP64.
 void launch_near(int src, const GeomDev& g, const int64_t* t_off, const int64_t* t_len,
                  const int64_t* s_off, const int64_t* s_len, const int64_t* out_off,
-                 int64_t nblocks, double2* out, hipStream_t st);
+                 int64_t nblocks, void* out, int f32, hipStream_t st);
 // Device address of this device's scratch array for the allocation-free
 // matrix-vector product (looked up once per device), and its size in bytes.
 hipError_t noalloc_scratch(void** out);
@@ -95,26 +97,26 @@ void launch_fwd_leaf(const ItemDev* items, const int32_t* litems, int32_t nl,
                      hipStream_t st);
 void launch_fwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* xh_off, double2* xh, int nr, hipStream_t st);
-void launch_coupling_transpose(const double2* const* S, double2* const* ST, const int32_t* rows,
-                               const int32_t* cols, int64_t nblocks, hipStream_t st);
+void launch_coupling_transpose(const void* const* S, void* const* ST, const int32_t* rows,
+                               const int32_t* cols, int64_t nblocks, int f32, hipStream_t st);
 void launch_coupling(const ItemDev* items, int32_t nitems, int32_t nheavy,
                      const int32_t* order, const int64_t* cbegin, const int32_t* cblock,
-                     const int32_t* cpartner, const double2* const* S_ptr,
+                     const int32_t* cpartner, const void* const* S_ptr,
                      const int32_t* S_rows, const int32_t* S_cols, const int64_t* xh_off,
                      const double2* xh, const int64_t* yh_off, double2* yh, int adjoint, int nr,
-                     hipStream_t st);
+                     int f32, hipStream_t st);
 void launch_bwd_inner(const ItemDev* items, const int32_t* litems, int32_t nl,
                       const int64_t* fbegin, const int32_t* fitem, const int32_t* fsonidx,
                       const int64_t* yh_off, double2* yh, int nr, hipStream_t st);
 void launch_bwd_leaf(const ItemDev* items, const LeafDev* leaves, int32_t nleaves,
-                     const NearRefDev* nref, const NearDev* nears, const double2* nearv,
-                     const double2* nearT, const int64_t* yh_off, const double2* yh,
+                     const NearRefDev* nref, const NearDev* nears, const void* nearv,
+                     const void* nearT, const int64_t* yh_off, const double2* yh,
                      const double2* xp, double2* yp, double2* partial, int adjoint, int nr,
-                     int near, int accumulate, hipStream_t st);
+                     int near, int accumulate, int f32, hipStream_t st);
 void launch_leaf_sum(const LeafDev* leaves, int32_t nleaves, const double2* partial, double2* yp,
                      int nr, hipStream_t st);
-void launch_near_transpose(const NearDev* nears, int64_t nblocks, const double2* B, double2* BT,
-                           hipStream_t st);
+void launch_near_transpose(const NearDev* nears, int64_t nblocks, const void* B, void* BT,
+                           int f32, hipStream_t st);
 void launch_direct(int src, const GeomDev& g, const int64_t* rows, int64_t nrows,
                    const double2* xp, int adjoint, double2* out, hipStream_t st);
 

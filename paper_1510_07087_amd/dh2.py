@@ -60,7 +60,8 @@ class Stats(C.Structure):
                 ("groups", C.c_int32), ("precision", C.c_int32),
                 ("flops_gram_leaf", C.c_double), ("t_gram_leaf", C.c_double),
                 ("n_gram_leaf", C.c_int32), ("pad", C.c_int32),
-                ("flops_rprod_leaf", C.c_double), ("ops_gram_leaf_i8", C.c_double)]
+                ("flops_rprod_leaf", C.c_double), ("ops_gram_leaf_i8", C.c_double),
+                ("repr_bytes", C.c_double)]
 
 
 EXPORTED = [

@@ -7,8 +7,10 @@
   (separated boxes only); the result matches the oracle's.
 
 The near field is generated in FP64 in both forms (about ten roundings per
-entry, so 4e-15 relative); the other tolerances are those of
-test_gpu_parity.
+entry, so 4e-15 relative) and stored as complex FP64 (FP64 form) or complex
+FP32 (mixed form: each component rounded to nearest, relative 2^-24, so the
+product is off by at most 2^-24 ||G||_F ||x|| more); the other tolerances
+are those of test_gpu_parity.
 """
 import numpy as np
 import pytest
@@ -58,10 +60,12 @@ def test_near_field_only(n, form):
     assert info["nadm"] == 0 and info["nnear"] == 1
     G = OM.helmholtz_dense_original(p, w, KAPPA)
     x = synth.complex_gaussian(n, 5)
+    store = 2.0 ** -24 * np.linalg.norm(G) * np.linalg.norm(x) if form == "mixed" else 0.0
     for op, A in (("N", G), ("C", G.conj().T)):
         y = _apply(m, x, op)
         ref = A @ x
-        assert np.linalg.norm(y - ref) <= 4e-15 * np.linalg.norm(ref) * max(1.0, np.sqrt(n)), op
+        bound = 4e-15 * np.linalg.norm(ref) * max(1.0, np.sqrt(n)) + store
+        assert np.linalg.norm(y - ref) <= bound, op
 
 
 @pytest.fixture(scope="module")

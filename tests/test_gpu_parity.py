@@ -174,8 +174,10 @@ def test_near_field(problem, gpu):
         rel = np.abs(blk - ref.near[q]) / np.abs(ref.near[q])
         worst = max(worst, float(rel.max()))
     print(f"[gpu parity] near field max relative entry error {worst:.2e}", flush=True)
-    # each entry takes about ten roundings in FP64 on either side
-    assert worst <= 4e-15
+    # each entry takes about ten roundings in FP64 on either side; the mixed
+    # form stores the near field as complex FP32, each component rounded to
+    # nearest (relative 2^-24)
+    assert worst <= (2.0 ** -24 + 4e-15 if gpu["mode"] == "mixed" else 4e-15)
 
 
 def test_global_error(problem, gpu):
