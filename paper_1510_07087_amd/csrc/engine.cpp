@@ -705,11 +705,6 @@ struct SweepStats {
   int64_t n_redo_mem = 0;              // factored a third time with X in memory
 };
 
-static int64_t npairs_of(int r) {
-  int nt = (r + 15) / 16;
-  return (int64_t)nt * (nt + 1) / 2;
-}
-
 static void expand_level(MatrixData& M, int s, int32_t lv, hipStream_t st, DevMem& mem);
 
 static void sweep(MatrixData& M, int s, const GeomDev& g, hipStream_t st, SweepStats& ss,
@@ -1258,7 +1253,6 @@ static void expand_side(MatrixData& M, int s, hipStream_t st, DevMem& mem) {
 // ks <= 64 that share W_sc are stacked (k_project_stacked).
 static void project_all(MatrixData& M, hipStream_t st, DevMem& mem, SweepStats& ss) {
   Trace tr_;
-  const ClusterTree& tr = M.blk->tree->tr;
   Side& S = M.side[0];
   const Side& C = M.side[1];
   const bool mixed = M.precision == DH2_MIXED;
@@ -2238,7 +2232,7 @@ static void build_mv(MatrixData& M, hipStream_t st) {
       R.item_first = slots;
       R.item_count = 0;
       int64_t q = r0;
-      for (int64_t part = 0; q < r1; ++part) {
+      while (q < r1) {
         LeafDev T = L;
         T.slot = slots++;
         T.near_begin = q;
