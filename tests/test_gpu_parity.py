@@ -249,9 +249,14 @@ def test_stats(problem, gpu):
             r = tr.size[t] if tr.son1[t] < 0 else mat.shape[0]
             assert mat.shape == (r, k)
             words += r * k
+    bwords = words
     words += sum(S.size for S in gpu["S"])
     words += sum(int(tr.size[t]) * int(tr.size[s]) for t, s in zip(bt.near_t, bt.near_s))
     assert st["mem_bytes"] == 16.0 * words
+    # device bytes as stored: bases FP64; couplings and near field complex
+    # FP32 in the mixed form, complex FP64 otherwise
+    esz = 8.0 if gpu["mode"] == "mixed" else 16.0
+    assert st["repr_bytes"] == 16.0 * bwords + esz * (words - bwords)
     assert st["k_max"] == max(k for data in (gpu["dv"], gpu["dw"]) for (k, _, _) in data.values())
     so = OD.storage_stats(ref)
     print(f"[gpu parity] {gpu['mode']}: Mem/n {st['mem_per_n_kib']:.4f} KiB, oracle "
