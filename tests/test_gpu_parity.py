@@ -206,6 +206,47 @@ def test_matvec(problem, gpu):
             assert np.linalg.norm(y - ref) <= 1e-10 * np.linalg.norm(ref), (op, nrhs)
 
 
+def test_matvec_rhs_blocks(problem, gpu):
+    """Blocks of right-hand sides: 2, 4 and 8 share one pass (the kernels'
+    two-, four- and eight-wide instantiations), 11 takes two passes (eight,
+    then three); every column equals the single product on that column
+    (each column's sums are formed in the same order) and the dense
+    reconstruction to 1e-10.  The allocation-free product on 11 columns
+    equals dh2_matvec; zero right-hand sides are accepted and write nothing."""
+    from paper_1510_07087_amd import dh2
+    Gt, m = gpu["Gt"], gpu["m"]
+    print(f"[gpu parity] {gpu['mode']}: matvec blocks of 2, 4, 8, 11 right-hand sides", flush=True)
+    for nrhs in (2, 4, 8, 11):
+        x = synth.complex_gaussian(2048, 40 + nrhs, nrhs)
+        xd = torch.from_numpy(np.ascontiguousarray(x.T)).to("cuda").T
+        for op, A in (("N", Gt), ("C", Gt.conj().T)):
+            yd = torch.empty_like(xd)
+            dh2.matvec(m, op, xd, yd)
+            y = yd.cpu().numpy()
+            ref = A @ x
+            assert np.linalg.norm(y - ref) <= 1e-10 * np.linalg.norm(ref), (op, nrhs)
+            for q in range(nrhs):
+                x1 = xd[:, q].contiguous()
+                y1 = torch.empty_like(x1)
+                dh2.matvec(m, op, x1, y1)
+                a, b = y[:, q], y1.cpu().numpy()
+                assert np.linalg.norm(a - b) <= 1e-14 * np.linalg.norm(b), (op, nrhs, q)
+            if nrhs == 11:
+                yn = torch.full_like(xd, complex(np.nan, np.nan))
+                dh2.matvec_noalloc(m, op, xd, yn)
+                torch.cuda.synchronize()
+                assert np.array_equal(yn.cpu().numpy(), y), op
+    # no right-hand side: accepted, nothing written
+    import ctypes as C
+    x0 = torch.zeros(4, dtype=torch.complex128, device="cuda")
+    y0 = torch.full_like(x0, complex(1.0, 2.0))
+    code = dh2.lib().dh2_matvec(m.h, b"N", 0, C.c_void_p(x0.data_ptr()),
+                                C.c_void_p(y0.data_ptr()),
+                                C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert code == 0 and bool(torch.all(y0 == complex(1.0, 2.0)))
+
+
 def test_error_estimate(problem, gpu):
     from paper_1510_07087_amd import dh2
     G = problem["G"]
