@@ -75,6 +75,14 @@ __device__ __forceinline__ void put(float2* p, int64_t i, double2 v) {
   p[i] = make_float2((float)v.x, (float)v.y);
 }
 
+// LDS written by some lanes of a wave and then read by others of the same
+// wave: the writes complete and become visible before the reads
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
 
 // ---------------------------------------------------------------------------
@@ -1254,6 +1262,35 @@ __device__ __forceinline__ void dot_rhs(double2 (&s)[NR], const AE* a, int64_t a
   }
 }
 
+// s += sum_{c < m} op(a[c as]) xs[c] for the lane's row, the vector entries
+// in LDS (the same entry for every lane of a slot: a broadcast read), U
+// terms of a loaded ahead of their products
+template <typename AE>
+__device__ __forceinline__ void dot_lds(double2& s, const AE* a, int64_t as, const double2* xs,
+                                        int m, bool conj_a) {
+  constexpr int U = 8;
+  int c = 0;
+  for (; c + U <= m; c += U) {
+    double2 av[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) av[u] = wide(ldg(a, (int64_t)(c + u) * as));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double2 xq = xs[c + u];
+      const double2 t = conj_a ? cmulc(av[u], xq) : cmul(av[u], xq);
+      s.x += t.x;
+      s.y += t.y;
+    }
+  }
+  for (; c < m; ++c) {
+    const double2 ac = wide(ldg(a, (int64_t)c * as));
+    const double2 xq = xs[c];
+    const double2 t = conj_a ? cmulc(ac, xq) : cmul(ac, xq);
+    s.x += t.x;
+    s.y += t.y;
+  }
+}
+
 // forward, leaf items: xh = Q^* x|t
 template <int NR>
 __global__ __launch_bounds__(128) void k_fwd_leaf(const ItemDev* items, const int32_t* litems,
@@ -1308,7 +1345,7 @@ __global__ __launch_bounds__(128) void k_fwd_inner(const ItemDev* items, const i
 // across the waves through LDS, in a fixed order.  The partner's
 // coefficients are the same for all lanes of a slot.
 template <int NR, typename SE>
-__global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t nitems,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 5 : 1))) void k_coupling(const ItemDev* items, int32_t nitems,
                                                   int32_t nheavy, const int32_t* order,
                                                   const int64_t* cbegin, const int32_t* cblock,
                                                   const int32_t* cpartner,
@@ -1318,6 +1355,9 @@ __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t 
                                                   const int64_t* yh_off, double2* yh,
                                                   int adjoint, int nr) {
   __shared__ double2 part[4][NR][64];
+  // one right-hand side: the partner's coefficients of the current block,
+  // kp per slot, staged in LDS instead of loaded by every lane per column
+  __shared__ double2 xsh[NR == 1 ? 4 * 64 : 1];
   const int w = wave_id();
   const bool heavy = (int32_t)blockIdx.x < nheavy;  // the same for the whole workgroup
   const int32_t wi = heavy ? (int32_t)blockIdx.x
@@ -1340,7 +1380,18 @@ __global__ __launch_bounds__(256) void k_coupling(const ItemDev* items, int32_t 
       const int kr = S_rows[b], kc = S_cols[b];  // of the oriented matrix
       const double2* x = xh + xh_off[cpartner[c]] * nr;
       // op N: sum_jj S[kk, jj] x[jj]; adjoint: sum_jj conj(S^T[kk, jj]) x[jj]
-      dot_rhs<NR>(s, Sb + kk, kr, x, kc, nr, adjoint != 0);
+      if constexpr (NR == 1) {
+        double2* xs = xsh + 64 * w + sl * kp;
+        for (int j0 = 0; j0 < kc; j0 += kp) {
+          const int m = min(kp, kc - j0);
+          wave_sync();  // the slot's reads of the previous entries are done
+          if (kl < m) xs[kl] = ldg(x, j0 + kl);
+          wave_sync();
+          dot_lds(s[0], Sb + kk + (int64_t)j0 * kr, kr, xs, m, adjoint != 0);
+        }
+      } else {
+        dot_rhs<NR>(s, Sb + kk, kr, x, kc, nr, adjoint != 0);
+      }
     }
     for (int o = kp; o < 64; o <<= 1)
 #pragma unroll
@@ -1553,11 +1604,6 @@ __global__ __launch_bounds__(256) void k_direct(GeomDev g, const int64_t* rows, 
 // entries with FP32 polynomials, R stored in complex FP32, R-products on
 // FP32 MFMA; Gram matrices are accumulated in FP64 in both forms.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Column data of the leaf block rows of one level, written once per level:
 // one workgroup per item walks its column-set entries.  Column j of the
